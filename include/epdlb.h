@@ -1,0 +1,173 @@
+/* epdlb -- hybrid Lattice Boltzmann / External Potential Dynamics step on MI355X (gfx950).
+ *
+ * C ABI of libepdlb.so.  The method is that of Heuser, Sevink and Schmid,
+ * "Self-assembly of polymeric particles in Poiseuille flow: a hybrid Lattice
+ * Boltzmann / External Potential Dynamics simulation study" (arXiv:1804.02883):
+ * one hybrid step advects the composition and potential fields with the flow,
+ * updates the EPD potentials with the chemical potential (Sec. II, Eq. diff_w),
+ * evaluates the chain propagators and densities (Sec. II, split step and
+ * Eq. phi_s), reconstructs the longitudinal force from the diffusive change in
+ * composition (Sec. II, k-space force), and advances a D2Q9 lattice Boltzmann
+ * fluid with that force plus the reverse-Poiseuille drive (Eq. LB_prop,
+ * Eq. force_col, Eq. force_field_2); the order follows the flow chart of App. C.
+ *
+ * Conventions for every function below:
+ *  - Return value 0 (EPDLB_OK) on success, a negative EPDLB_E* code otherwise;
+ *    epdlb_last_error() then returns a message (thread-local).  No function
+ *    aborts the process.
+ *  - Host arrays are caller-owned, FP64, planes of nx*ny values in row-major
+ *    [y][x] order (x contiguous); multi-plane arrays are plane after plane.
+ *  - Device memory is owned by the context (or by the caller when a workspace
+ *    is passed to epdlb_create).  Work is queued on the context's stream;
+ *    epdlb_step returns before the GPU finishes; reads synchronise the stream.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef EPDLB_H
+#define EPDLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EPDLB_ABI_VERSION 1
+
+/* Opaque simulation context; owns (or borrows) all device memory of one replica. */
+typedef struct epdlb_ctx epdlb_ctx;
+
+enum {
+  EPDLB_OK = 0,
+  EPDLB_EINVAL = -1,     /* bad argument, shape or parameter */
+  EPDLB_ENOMEM = -2,     /* device allocation failed or workspace too small */
+  EPDLB_EHIP = -3,       /* a HIP runtime call failed */
+  EPDLB_ENONFINITE = -4, /* a partition function or field became non-finite */
+  EPDLB_ESTATE = -6,     /* call out of order (e.g. step before seed) */
+  EPDLB_ENODEV = -7      /* no usable gfx950 device */
+};
+
+/* Model and run parameters.  Field names follow the paper's notation
+ * (Sec. II model, Sec. III units and parameter set, Sec. IV driving force).
+ * Fill with epdlb_params_default() and override. */
+typedef struct {
+  int32_t abi_version;   /* must be EPDLB_ABI_VERSION */
+  int32_t nx, ny;        /* grid; powers of two, 32 <= nx <= 1024, 16 <= ny <= 1024 */
+  int32_t n_contour;     /* N: segments per chain (ds = 1/N), 2 <= N <= 256 */
+  double f_A;            /* A fraction of the diblock, 0 < f_A < 1 */
+  double phi_P;          /* mean copolymer volume fraction, 0 < phi_P < 1 */
+  double chi_AB, chi_AS, chi_BS; /* Flory-Huggins parameters */
+  double kappa_H;        /* Helfand compressibility parameter */
+  double D_S, D_A, D_B;  /* diffusion constants */
+  double R_G;            /* radius of gyration (length unit) */
+  double dx, dt;         /* grid spacing and time step (shared by EPD and LB) */
+  double kT_over_v;      /* 1/(beta v): scales the reconstructed force */
+  double lb_tau;         /* LB relaxation time (BGK), > 1/2 */
+  double g;              /* reverse-Poiseuille force amplitude */
+  int32_t g_units;       /* 0: g in f* = rho R_G / tau^2; 1: g in lattice units */
+  int32_t precision;     /* 0: FP64 everywhere; 1: FP32 fields, FP64 reductions */
+  int32_t init_flow;     /* 1: start LB from the analytic profile (Eq. flow_field) */
+  int32_t couple_lb;     /* 1: flow advects the fields and the polymer force drives the flow */
+} epdlb_params;
+
+/* Scalars maintained on the device (FP64). */
+typedef struct {
+  int64_t step;          /* hybrid steps taken since seeding */
+  double Q_P;            /* single-chain partition function (forward chain) */
+  double Q_P_bwd;        /* same from the backward chain (equal up to rounding) */
+  double Q_S;            /* solvent partition function (with gauge_S below) */
+  double gauge_S;        /* constant subtracted from omega_S for Q_S */
+  double mean_omega[3];  /* site means of omega_A, omega_B, omega_S */
+} epdlb_diag;
+
+/* Stage identifiers for epdlb_run_stage (one hybrid step = 1, 2, 3, 4). */
+enum {
+  EPDLB_STAGE_ADVECT_UPDATE = 1, /* Phi, omega, u -> omega', S~ = sum Phi~_I / D_I */
+  EPDLB_STAGE_DENSITIES = 2,     /* omega -> propagators -> Phi, Q_P, and S = sum Phi_I/D_I - S~ */
+  EPDLB_STAGE_FORCE = 3,         /* S -> lattice force F (polymer + external) */
+  EPDLB_STAGE_LB = 4             /* f*, F -> stream/collide -> f*', rho, u */
+};
+
+/* Auxiliary planes for epdlb_read_aux / epdlb_write_aux. */
+enum {
+  EPDLB_AUX_STILDE = 1, /* 1 plane */
+  EPDLB_AUX_S = 2,      /* 1 plane */
+  EPDLB_AUX_FORCE = 3   /* 2 planes: F_x, F_y in lattice units */
+};
+
+/* Fill *p with the paper's defaults (Sec. III: R_G = D_S = 1, D_A = D_B = D_S/N,
+ * dx = R_G/3, dt = 0.002 tau; 32x32 grid, N = 16).  Host only. */
+int epdlb_params_default(epdlb_params* p);
+
+/* Check *p without touching a GPU.  Host only. */
+int epdlb_validate(const epdlb_params* p);
+
+/* Device bytes a context for *p needs when the caller supplies the workspace.  Host only. */
+int epdlb_workspace_bytes(const epdlb_params* p, size_t* bytes);
+
+/* Initial noise: out[3*nx*ny] = sigma * xi, xi standard normal from SplitMix64
+ * in counter mode with Box-Muller pairs (species A, B, S; then y; then x).
+ * The paper starts from a homogeneous mixture plus tiny noise (Sec. III).  Host only. */
+int epdlb_noise_fill(uint64_t seed, double sigma, int32_t nx, int32_t ny, double* out);
+
+/* Create a context on HIP device `device`.  `stream` is a hipStream_t (NULL:
+ * the context creates its own).  `workspace` is device memory of at least
+ * epdlb_workspace_bytes() bytes that stays owned by the caller (NULL: the
+ * context allocates).  On success *out is the new context. */
+int epdlb_create(const epdlb_params* p, int device, void* stream, void* workspace,
+                 size_t workspace_bytes, epdlb_ctx** out);
+
+/* omega_I = sigma * noise(seed), Phi = Phi[omega], LB at f^eq(rho = 1, u_init). */
+int epdlb_seed(epdlb_ctx* ctx, uint64_t seed, double sigma);
+
+/* Same with caller-given potentials omega[3*nx*ny]. */
+int epdlb_set_fields(epdlb_ctx* ctx, const double* omega);
+
+/* Upload a full state: omega[3], phi[3], post-collision populations fstar[9]
+ * (D2Q9 order c = (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1))
+ * and velocity u[2] (lattice units).  Phi is taken as given. */
+int epdlb_set_state(epdlb_ctx* ctx, const double* omega, const double* phi,
+                    const double* fstar, const double* u);
+
+/* Queue n hybrid steps on the context stream. */
+int epdlb_step(epdlb_ctx* ctx, int64_t n);
+
+/* Queue one stage of a step (EPDLB_STAGE_*), for per-stage checks. */
+int epdlb_run_stage(epdlb_ctx* ctx, int32_t stage);
+
+/* Wait for queued work; reports non-finite partition functions. */
+int epdlb_sync(epdlb_ctx* ctx);
+
+/* Copy current fields to host (FP64, nx*ny each). */
+int epdlb_read_densities(epdlb_ctx* ctx, double* phiA, double* phiB, double* phiS);
+int epdlb_read_fields(epdlb_ctx* ctx, double* wA, double* wB, double* wS);
+int epdlb_read_velocity(epdlb_ctx* ctx, double* rho, double* ux, double* uy);
+int epdlb_read_populations(epdlb_ctx* ctx, double* fstar /* 9*nx*ny */);
+int epdlb_read_aux(epdlb_ctx* ctx, int32_t which, double* out);
+int epdlb_write_aux(epdlb_ctx* ctx, int32_t which, const double* in);
+int epdlb_read_diag(epdlb_ctx* ctx, epdlb_diag* d);
+
+/* Per-kernel timing with HIP events recorded on the context stream around
+ * each launch, for the next `max_launches` launches (later launches are not
+ * recorded; recording never blocks). */
+typedef struct {
+  char name[32];         /* kernel family, e.g. "prop_row" */
+  int64_t launches;      /* launches recorded */
+  double total_ms, min_ms, max_ms;
+} epdlb_kernel_stat;
+int epdlb_profile_start(epdlb_ctx* ctx, int32_t max_launches);
+
+/* Synchronise, resolve the recorded events into at most `cap` per-family
+ * entries (*n_out of them), and stop recording. */
+int epdlb_profile_read(epdlb_ctx* ctx, epdlb_kernel_stat* out, int32_t cap, int32_t* n_out);
+
+/* Release the context (device memory it allocated, its own stream). */
+void epdlb_destroy(epdlb_ctx* ctx);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* epdlb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EPDLB_H */

@@ -1,0 +1,370 @@
+"""ctypes binding of libepdlb.so: the C ABI's functions under the same names,
+plus a small `Simulation` convenience wrapper.
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels of the library.  PyTorch supplies device memory (the context's
+workspace is a torch uint8 tensor) and the stream (torch's current stream), so
+torch's allocator and events see the library's work.  Without a GPU the host
+entry points (params, validation, workspace size, noise) still work.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libepdlb.so")
+
+EPDLB_ABI_VERSION = 1
+EPDLB_OK = 0
+EPDLB_EINVAL = -1
+EPDLB_ENOMEM = -2
+EPDLB_EHIP = -3
+EPDLB_ENONFINITE = -4
+EPDLB_ESTATE = -6
+EPDLB_ENODEV = -7
+
+EPDLB_STAGE_ADVECT_UPDATE = 1
+EPDLB_STAGE_DENSITIES = 2
+EPDLB_STAGE_FORCE = 3
+EPDLB_STAGE_LB = 4
+
+EPDLB_AUX_STILDE = 1
+EPDLB_AUX_S = 2
+EPDLB_AUX_FORCE = 3
+
+
+class epdlb_params(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("n_contour", ctypes.c_int32),
+        ("f_A", ctypes.c_double), ("phi_P", ctypes.c_double),
+        ("chi_AB", ctypes.c_double), ("chi_AS", ctypes.c_double), ("chi_BS", ctypes.c_double),
+        ("kappa_H", ctypes.c_double),
+        ("D_S", ctypes.c_double), ("D_A", ctypes.c_double), ("D_B", ctypes.c_double),
+        ("R_G", ctypes.c_double), ("dx", ctypes.c_double), ("dt", ctypes.c_double),
+        ("kT_over_v", ctypes.c_double),
+        ("lb_tau", ctypes.c_double), ("g", ctypes.c_double),
+        ("g_units", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("init_flow", ctypes.c_int32), ("couple_lb", ctypes.c_int32),
+    ]
+
+
+class epdlb_diag(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_int64),
+        ("Q_P", ctypes.c_double), ("Q_P_bwd", ctypes.c_double),
+        ("Q_S", ctypes.c_double), ("gauge_S", ctypes.c_double),
+        ("mean_omega", ctypes.c_double * 3),
+    ]
+
+
+class epdlb_kernel_stat(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char * 32),
+        ("launches", ctypes.c_int64),
+        ("total_ms", ctypes.c_double), ("min_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+    ]
+
+
+class EpdlbError(RuntimeError):
+    def __init__(self, code, fn, msg):
+        super().__init__(f"{fn} failed ({code}): {msg}")
+        self.code = code
+
+
+_lib = None
+
+_P = ctypes.POINTER
+_dp = _P(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+SIGNATURES = {
+    "epdlb_params_default": (ctypes.c_int, [_P(epdlb_params)]),
+    "epdlb_validate": (ctypes.c_int, [_P(epdlb_params)]),
+    "epdlb_workspace_bytes": (ctypes.c_int, [_P(epdlb_params), _P(ctypes.c_size_t)]),
+    "epdlb_noise_fill": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_double, ctypes.c_int32,
+                                        ctypes.c_int32, _dp]),
+    "epdlb_create": (ctypes.c_int, [_P(epdlb_params), ctypes.c_int, _vp, _vp, ctypes.c_size_t,
+                                    _P(_vp)]),
+    "epdlb_seed": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_double]),
+    "epdlb_set_fields": (ctypes.c_int, [_vp, _dp]),
+    "epdlb_set_state": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp]),
+    "epdlb_step": (ctypes.c_int, [_vp, ctypes.c_int64]),
+    "epdlb_run_stage": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "epdlb_sync": (ctypes.c_int, [_vp]),
+    "epdlb_read_densities": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
+    "epdlb_read_fields": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
+    "epdlb_read_velocity": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
+    "epdlb_read_populations": (ctypes.c_int, [_vp, _dp]),
+    "epdlb_read_aux": (ctypes.c_int, [_vp, ctypes.c_int32, _dp]),
+    "epdlb_write_aux": (ctypes.c_int, [_vp, ctypes.c_int32, _dp]),
+    "epdlb_read_diag": (ctypes.c_int, [_vp, _P(epdlb_diag)]),
+    "epdlb_profile_start": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "epdlb_profile_read": (ctypes.c_int, [_vp, _P(epdlb_kernel_stat), ctypes.c_int32,
+                                          _P(ctypes.c_int32)]),
+    "epdlb_destroy": (None, [_vp]),
+    "epdlb_last_error": (ctypes.c_char_p, []),
+}
+
+
+def load_library(path=LIB_PATH):
+    """Load libepdlb.so (built in-tree by paper_1804_02883_amd.build); raise if missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: run `python -m paper_1804_02883_amd.build` first")
+    try:  # bind to the HIP runtime torch already loaded, if any
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code, fn):
+    if code != EPDLB_OK:
+        msg = load_library().epdlb_last_error().decode()
+        raise EpdlbError(code, fn, msg)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a, count):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.size != count:
+        raise ValueError(f"expected {count} values, got {a.size}")
+    return a
+
+
+def make_params(d=None, **kw):
+    """epdlb_params from the library defaults, updated by a dict and keywords."""
+    p = epdlb_params()
+    _check(load_library().epdlb_params_default(ctypes.byref(p)), "epdlb_params_default")
+    for k, v in dict(d or {}, **kw).items():
+        if not hasattr(p, k):
+            raise KeyError(f"unknown parameter {k}")
+        setattr(p, k, v)
+    return p
+
+
+# ---- functions with the C ABI's names --------------------------------------------------
+
+def epdlb_params_default():
+    return make_params()
+
+
+def epdlb_validate(p):
+    return load_library().epdlb_validate(ctypes.byref(p))
+
+
+def epdlb_workspace_bytes(p):
+    n = ctypes.c_size_t(0)
+    _check(load_library().epdlb_workspace_bytes(ctypes.byref(p), ctypes.byref(n)), "epdlb_workspace_bytes")
+    return n.value
+
+
+def epdlb_noise_fill(seed, sigma, nx, ny):
+    out = np.empty(3 * nx * ny, dtype=np.float64)
+    _check(load_library().epdlb_noise_fill(seed, sigma, nx, ny, _ptr(out)), "epdlb_noise_fill")
+    return out.reshape(3, ny, nx)
+
+
+def epdlb_create(p, device=0, stream=None, workspace=None, workspace_bytes=0):
+    h = _vp()
+    _check(load_library().epdlb_create(ctypes.byref(p), device, stream, workspace, workspace_bytes,
+                                       ctypes.byref(h)), "epdlb_create")
+    return h
+
+
+def epdlb_seed(ctx, seed, sigma):
+    _check(load_library().epdlb_seed(ctx, seed, sigma), "epdlb_seed")
+
+
+def epdlb_set_fields(ctx, omega, n):
+    w = _f64(omega, 3 * n)
+    _check(load_library().epdlb_set_fields(ctx, _ptr(w)), "epdlb_set_fields")
+
+
+def epdlb_set_state(ctx, omega, phi, fstar, u, n):
+    a, b, c, d = _f64(omega, 3 * n), _f64(phi, 3 * n), _f64(fstar, 9 * n), _f64(u, 2 * n)
+    _check(load_library().epdlb_set_state(ctx, _ptr(a), _ptr(b), _ptr(c), _ptr(d)), "epdlb_set_state")
+
+
+def epdlb_step(ctx, n):
+    _check(load_library().epdlb_step(ctx, n), "epdlb_step")
+
+
+def epdlb_run_stage(ctx, stage):
+    _check(load_library().epdlb_run_stage(ctx, stage), "epdlb_run_stage")
+
+
+def epdlb_sync(ctx):
+    _check(load_library().epdlb_sync(ctx), "epdlb_sync")
+
+
+def _read3(fn, ctx, shape):
+    out = np.empty((3,) + shape, dtype=np.float64)
+    _check(getattr(load_library(), fn)(ctx, _ptr(out[0]), _ptr(out[1]), _ptr(out[2])), fn)
+    return out
+
+
+def epdlb_read_densities(ctx, shape):
+    return _read3("epdlb_read_densities", ctx, shape)
+
+
+def epdlb_read_fields(ctx, shape):
+    return _read3("epdlb_read_fields", ctx, shape)
+
+
+def epdlb_read_velocity(ctx, shape):
+    """Returns (rho, u) with u of shape (2, ny, nx)."""
+    out = _read3("epdlb_read_velocity", ctx, shape)
+    return out[0], out[1:]
+
+
+def epdlb_read_populations(ctx, shape):
+    out = np.empty((9,) + shape, dtype=np.float64)
+    _check(load_library().epdlb_read_populations(ctx, _ptr(out)), "epdlb_read_populations")
+    return out
+
+
+_AUX_PLANES = {EPDLB_AUX_STILDE: 1, EPDLB_AUX_S: 1, EPDLB_AUX_FORCE: 2}
+
+
+def epdlb_read_aux(ctx, which, shape):
+    out = np.empty((_AUX_PLANES[which],) + shape, dtype=np.float64)
+    _check(load_library().epdlb_read_aux(ctx, which, _ptr(out)), "epdlb_read_aux")
+    return out
+
+
+def epdlb_write_aux(ctx, which, data, shape):
+    a = _f64(data, _AUX_PLANES[which] * shape[0] * shape[1])
+    _check(load_library().epdlb_write_aux(ctx, which, _ptr(a)), "epdlb_write_aux")
+
+
+def epdlb_read_diag(ctx):
+    d = epdlb_diag()
+    _check(load_library().epdlb_read_diag(ctx, ctypes.byref(d)), "epdlb_read_diag")
+    return dict(step=d.step, Q_P=d.Q_P, Q_P_bwd=d.Q_P_bwd, Q_S=d.Q_S, gauge_S=d.gauge_S,
+                mean_omega=tuple(d.mean_omega))
+
+
+def epdlb_profile_start(ctx, max_launches):
+    _check(load_library().epdlb_profile_start(ctx, max_launches), "epdlb_profile_start")
+
+
+def epdlb_profile_read(ctx):
+    """{kernel family: dict(launches, total_ms, min_ms, max_ms, avg_ms)}"""
+    cap = 32
+    arr = (epdlb_kernel_stat * cap)()
+    n = ctypes.c_int32(0)
+    _check(load_library().epdlb_profile_read(ctx, arr, cap, ctypes.byref(n)), "epdlb_profile_read")
+    out = {}
+    for i in range(n.value):
+        s = arr[i]
+        out[s.name.decode()] = dict(launches=s.launches, total_ms=s.total_ms, min_ms=s.min_ms,
+                                    max_ms=s.max_ms, avg_ms=s.total_ms / max(s.launches, 1))
+    return out
+
+
+def epdlb_destroy(ctx):
+    load_library().epdlb_destroy(ctx)
+
+
+def epdlb_last_error():
+    return load_library().epdlb_last_error().decode()
+
+
+# ---- convenience wrapper -----------------------------------------------------------------
+
+class Simulation:
+    """One replica on one GPU.  Device memory comes from torch's caching
+    allocator and work is queued on torch's current stream of `device`."""
+
+    def __init__(self, params, device=0, use_torch=True):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("epdlb needs a ROCm GPU (gfx950); none is visible")
+        self.p = params if isinstance(params, epdlb_params) else make_params(params)
+        self.shape = (self.p.ny, self.p.nx)
+        self.n = self.p.nx * self.p.ny
+        self.device = device
+        self._ws = None
+        stream = None
+        ws_ptr, ws_bytes = None, 0
+        if use_torch:
+            dev = torch.device("cuda", device)
+            self.stream = torch.cuda.current_stream(dev)
+            stream = _vp(self.stream.cuda_stream)
+            ws_bytes = epdlb_workspace_bytes(self.p)
+            self._ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
+            base = self._ws.data_ptr()
+            ws_ptr = _vp((base + 255) & ~255)
+        self.ctx = epdlb_create(self.p, device, stream, ws_ptr, ws_bytes)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            epdlb_destroy(self.ctx)
+            self.ctx = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def seed(self, seed, sigma):
+        epdlb_seed(self.ctx, seed, sigma)
+
+    def set_fields(self, omega):
+        epdlb_set_fields(self.ctx, omega, self.n)
+
+    def set_state(self, omega, phi, fstar, u):
+        epdlb_set_state(self.ctx, omega, phi, fstar, u, self.n)
+
+    def step(self, n=1):
+        epdlb_step(self.ctx, n)
+
+    def run_stage(self, stage):
+        epdlb_run_stage(self.ctx, stage)
+
+    def sync(self):
+        epdlb_sync(self.ctx)
+
+    def densities(self):
+        return epdlb_read_densities(self.ctx, self.shape)
+
+    def fields(self):
+        return epdlb_read_fields(self.ctx, self.shape)
+
+    def velocity(self):
+        return epdlb_read_velocity(self.ctx, self.shape)
+
+    def populations(self):
+        return epdlb_read_populations(self.ctx, self.shape)
+
+    def aux(self, which):
+        return epdlb_read_aux(self.ctx, which, self.shape)
+
+    def write_aux(self, which, data):
+        epdlb_write_aux(self.ctx, which, data, self.shape)
+
+    def diag(self):
+        return epdlb_read_diag(self.ctx)
+
+    def profile_start(self, max_launches):
+        epdlb_profile_start(self.ctx, max_launches)
+
+    def profile_read(self):
+        return epdlb_profile_read(self.ctx)

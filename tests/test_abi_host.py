@@ -1,0 +1,86 @@
+"""Host-side checks of the C-ABI library (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1804_02883_amd import binding as B
+from seeded_inputs import initial_omega, preset
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "epdlb.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(epdlb_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.load_library()
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(B.SIGNATURES), set(names) ^ set(B.SIGNATURES)
+
+
+def test_params_struct_matches_header_order():
+    text = open(HEADER).read()
+    body = text[text.index("typedef struct {\n  int32_t abi_version"):]
+    body = body[:body.index("} epdlb_params;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl or decl.startswith("typedef"):
+            decl = decl.split("{")[-1].strip()
+        if not decl:
+            continue
+        names = decl.split(None, 1)[1]
+        fields += [x.strip() for x in names.split(",")]
+    assert fields == [f[0] for f in B.epdlb_params._fields_]
+
+
+def test_defaults_and_validation():
+    p = B.make_params()
+    assert p.abi_version == 1 and p.nx == 32 and p.n_contour == 16
+    assert abs(p.dx - 1 / 3) < 1e-16 and p.dt == 0.002 and p.D_A == 1 / 16
+    assert B.epdlb_validate(p) == 0
+    for bad in [dict(nx=48), dict(nx=16), dict(ny=8), dict(n_contour=1), dict(f_A=1.0),
+                dict(phi_P=0.0), dict(lb_tau=0.5), dict(precision=2), dict(abi_version=7),
+                dict(g=float("nan"))]:
+        q = B.make_params(**bad)
+        assert B.epdlb_validate(q) == B.EPDLB_EINVAL, bad
+        assert B.epdlb_last_error() != ""
+
+
+def test_workspace_bytes_scale():
+    p32 = B.make_params(preset("cfg3"))
+    p64 = B.make_params(preset("cfg3"), precision=0)
+    b32, b64 = B.epdlb_workspace_bytes(p32), B.epdlb_workspace_bytes(p64)
+    n = 1024 * 512
+    N = 64
+    planes = 2 * N + 38  # omega 6, phi 3, S~ 1, S 1, q 2N, tmp 2, spec 2, F 2, f* 18, rho 1, u 2
+    assert planes * n * 4 <= b32 < planes * n * 4 + (1 << 22)
+    assert abs(b64 - 2 * b32) < (1 << 22)
+
+
+def test_noise_matches_seeded_inputs():
+    out = B.epdlb_noise_fill(1001, 1e-3, 32, 16)
+    ref = initial_omega(32, 16, 1001, 1e-3)
+    assert np.max(np.abs(out - ref)) <= 1e-18
+    assert out.shape == (3, 16, 32)
+
+
+def test_create_without_gpu_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    p = B.make_params()
+    with pytest.raises(B.EpdlbError) as e:
+        B.epdlb_create(p)
+    assert e.value.code in (B.EPDLB_ENODEV, B.EPDLB_EHIP)

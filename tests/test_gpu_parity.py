@@ -1,0 +1,265 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Tolerances (relative to the largest oracle magnitude of the compared field):
+FP64 <= 1e-10, FP32 <= 1e-4 on densities (FP32 per-stage checks use the
+bounds stated next to each test, derived from FP32 rounding of the inputs).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import epdlb_oracle as O
+from seeded_inputs import initial_omega, preset
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(p):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1804_02883_amd import Simulation
+    return Simulation(p)
+
+
+def rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def tol(p, fp64=1e-10, fp32=1e-4):
+    return fp64 if p["precision"] == 0 else fp32
+
+
+SHAPES = [
+    # (nx, ny, N, f_A, precision): several tiles, inactive transform groups,
+    # junction segments, both precisions
+    (32, 32, 16, 0.5, 0),
+    (64, 16, 7, 0.37, 0),
+    (128, 64, 12, 0.3, 0),
+    (32, 128, 9, 0.55, 1),
+    (256, 256, 32, 0.5, 1),
+    (1024, 32, 10, 0.3, 1),
+    (64, 1024, 6, 0.45, 1),
+]
+
+
+@pytest.mark.parametrize("nx,ny,N,fA,prec", SHAPES)
+def test_densities_vs_oracle(nx, ny, N, fA, prec):
+    say(f"[densities] nx={nx} ny={ny} N={N} f_A={fA} prec={prec}")
+    p = preset("cfg1", nx=nx, ny=ny, n_contour=N, f_A=fA, precision=prec)
+    rng = np.random.default_rng(nx * 7 + ny + N)
+    w = 0.3 * rng.standard_normal((3, ny, nx)) + np.array([0.2, -0.4, 0.1])[:, None, None]
+    sim = _sim(p)
+    sim.set_fields(w)
+    phi = sim.densities()
+    d = sim.diag()
+    ref = O.densities(w, p)
+    for I in range(3):
+        assert rel(phi[I], ref["phi"][I]) < tol(p, 1e-12, 2e-5), I
+    assert abs(d["Q_P"] / ref["Q_P"] - 1) < tol(p, 1e-12, 1e-5)
+    assert abs(d["Q_P_bwd"] / ref["Q_P"] - 1) < tol(p, 1e-12, 1e-5)
+    # Q_S is evaluated with the library's gauge constant
+    assert abs(d["Q_S"] * np.exp(-d["gauge_S"]) / (ref["Q_S"] * np.exp(-ref["gauge"][2])) - 1) < tol(p, 1e-12, 1e-5)
+    # compressibility means
+    assert abs(phi[0].mean() - fA * p["phi_P"]) < tol(p, 1e-14, 1e-6)
+    assert abs(phi.sum(axis=0).mean() - 1) < tol(p, 1e-14, 1e-6)
+    sim.close()
+
+
+def test_homogeneous_closed_form_gpu():
+    say("[homogeneous] 64x32 FP64")
+    p = preset("cfg1", nx=64, ny=32, n_contour=20, f_A=0.33)
+    w = np.stack([np.full((32, 64), v) for v in (0.7, -0.2, 0.4)])
+    sim = _sim(p)
+    sim.set_fields(w)
+    phi = sim.densities()
+    assert np.max(np.abs(phi[0] - 0.33 * 0.1)) < 1e-15
+    assert np.max(np.abs(phi[1] - 0.67 * 0.1)) < 1e-15
+    assert np.max(np.abs(phi[2] - 0.9)) < 1e-15
+    sim.close()
+
+
+def _random_state(p, seed, amp_u=0.05):
+    rng = np.random.default_rng(seed)
+    ny, nx = p["ny"], p["nx"]
+    phi = np.stack([np.full((ny, nx), v) for v in (0.05, 0.05, 0.9)]) + 0.01 * rng.standard_normal((3, ny, nx))
+    w = 0.2 * rng.standard_normal((3, ny, nx))
+    u = amp_u * rng.standard_normal((2, ny, nx))
+    rho = 1 + 0.01 * rng.standard_normal((ny, nx))
+    f = O.lb_equilibrium(rho, u) * (1 + 0.01 * rng.standard_normal((9, ny, nx)))
+    return phi, w, u, f
+
+
+@pytest.mark.parametrize("nx,ny,prec", [(32, 16, 0), (64, 32, 0), (256, 64, 1), (512, 256, 1)])
+def test_stage_advect_update(nx, ny, prec):
+    say(f"[advect_update] {nx}x{ny} prec={prec}")
+    from paper_1804_02883_amd import EPDLB_STAGE_ADVECT_UPDATE, EPDLB_AUX_STILDE
+    p = preset("cfg1", nx=nx, ny=ny, precision=prec)
+    phi, w, u, f = _random_state(p, nx + ny)
+    sim = _sim(p)
+    sim.set_state(w, phi, f, u)
+    sim.run_stage(EPDLB_STAGE_ADVECT_UPDATE)
+    wn = sim.fields()
+    st = sim.aux(EPDLB_AUX_STILDE)[0]
+    pt, wt = O.advect(phi, w, u)
+    ref = O.field_update(pt, wt, p)
+    D = O.diffusivities(p)
+    st_ref = sum(pt[I] / D[I] for I in range(3))
+    for I in range(3):
+        assert rel(wn[I], ref[I]) < tol(p, 1e-13, 2e-6), I
+    assert rel(st, st_ref) < tol(p, 1e-13, 2e-6)
+    d = sim.diag()
+    assert abs(d["mean_omega"][0] - wn[0].mean()) < tol(p, 1e-15, 1e-7)
+    sim.close()
+
+
+@pytest.mark.parametrize("nx,ny,prec", [(32, 32, 0), (128, 16, 0), (64, 256, 1), (1024, 512, 1)])
+def test_stage_force(nx, ny, prec):
+    say(f"[force] {nx}x{ny} prec={prec}")
+    from paper_1804_02883_amd import EPDLB_STAGE_FORCE, EPDLB_AUX_S, EPDLB_AUX_FORCE
+    p = preset("cfg1", nx=nx, ny=ny, precision=prec, g=3e-4)
+    phi, w, u, f = _random_state(p, 3)
+    rng = np.random.default_rng(nx * ny)
+    S = 1e-3 * rng.standard_normal((ny, nx))
+    S -= S.mean()
+    sim = _sim(p)
+    sim.set_state(w, phi, f, u)
+    sim.write_aux(EPDLB_AUX_S, S)
+    sim.run_stage(EPDLB_STAGE_FORCE)
+    F = sim.aux(EPDLB_AUX_FORCE)
+    ref = O.lattice_force(S, p)
+    fp = O.polymer_force(S, p) * p["dt"] ** 2 / p["dx"]
+    scale = np.max(np.abs(fp))
+    assert np.max(np.abs(F[0] - ref[0])) / scale < tol(p, 1e-12, 5e-6)
+    assert np.max(np.abs(F[1] - ref[1])) / scale < tol(p, 1e-12, 5e-6)
+    sim.close()
+
+
+@pytest.mark.parametrize("nx,ny,prec,tau", [(32, 16, 0, 1.0), (64, 64, 0, 0.8), (256, 128, 1, 1.0)])
+def test_stage_lb(nx, ny, prec, tau):
+    say(f"[lb] {nx}x{ny} prec={prec} tau={tau}")
+    from paper_1804_02883_amd import EPDLB_STAGE_LB, EPDLB_AUX_FORCE
+    p = preset("cfg1", nx=nx, ny=ny, precision=prec, lb_tau=tau)
+    phi, w, u, f = _random_state(p, 5)
+    rng = np.random.default_rng(11)
+    F = 1e-4 * rng.standard_normal((2, ny, nx))
+    sim = _sim(p)
+    sim.set_state(w, phi, f, u)
+    sim.write_aux(EPDLB_AUX_FORCE, F)
+    sim.run_stage(EPDLB_STAGE_LB)
+    fo = sim.populations()
+    rho, ug = sim.velocity()
+    ref, rho_r, u_r = O.lb_step(f, F, tau)
+    assert rel(fo, ref) < tol(p, 1e-14, 1e-6)
+    assert rel(rho, rho_r) < tol(p, 1e-14, 1e-6)
+    assert np.max(np.abs(ug - u_r)) < tol(p, 1e-15, 1e-7)
+    sim.close()
+
+
+def test_cfg1_full_run_fp64():
+    """32x32, FP64, N = 16: 200 hybrid steps from the seeded noise, all fields <= 1e-10."""
+    say("[cfg1] 200 steps FP64")
+    p = preset("cfg1")
+    w0 = initial_omega(32, 32, 1001, 1e-3)
+    sim = _sim(p)
+    sim.set_fields(w0)
+    s = O.init_state(p, w0)
+    for chunk in (1, 9, 90, 100):
+        sim.step(chunk)
+        for _ in range(chunk):
+            s = O.step(s, p)
+        sim.sync()
+        phi = sim.densities()
+        w = sim.fields()
+        rho, u = sim.velocity()
+        for I in range(3):
+            assert rel(phi[I], s["phi"][I]) < 1e-10, (chunk, I)
+        assert np.max(np.abs(w - s["omega"])) < 1e-10 * max(np.max(np.abs(s["omega"])), 1e-3)
+        # u is a difference of O(1) populations: FP64 round-off floor ~1e-15 absolute
+        for k in range(2):
+            assert np.max(np.abs(u[k] - s["u"][k])) < 1e-10 * np.max(np.abs(s["u"][0])) + 1e-14, (chunk, k)
+        assert rel(sim.populations(), s["fstar"]) < 1e-12
+    sim.close()
+
+
+def test_cfg1_seed_matches_generator():
+    say("[cfg1] seed")
+    p = preset("cfg1")
+    sim = _sim(p)
+    sim.seed(1001, 1e-3)
+    w = sim.fields()
+    assert np.max(np.abs(w - initial_omega(32, 32, 1001, 1e-3))) == 0.0
+    sim.close()
+
+
+@pytest.mark.parametrize("chi", ["L", "Q"])
+def test_fp32_256_steps_vs_oracle(chi):
+    """256x256, FP32 with FP64 reductions, N = 32: densities after 1, 10, 100 steps <= 1e-4."""
+    say(f"[cfg2-shape] FP32 chi={chi}")
+    from seeded_inputs.presets import base_params
+    p = base_params(256, 256, 32, 0.5, 0.1, chi, 1e-5, precision=1)
+    w0 = initial_omega(256, 256, 1002, 1e-3)
+    sim = _sim(p)
+    sim.set_fields(w0)
+    s = O.init_state(p, w0)
+    done = 0
+    for target in (1, 10, 100):
+        sim.step(target - done)
+        for _ in range(target - done):
+            s = O.step(s, p)
+        done = target
+        sim.sync()
+        phi = sim.densities()
+        for I in range(3):
+            assert rel(phi[I], s["phi"][I]) < 1e-4, (target, I)
+        # deviation from homogeneity is what evolves; check it to 1e-2 relative
+        dev = phi[0] - phi[0].mean()
+        dev_r = s["phi"][0] - s["phi"][0].mean()
+        assert rel(dev, dev_r) < 2e-2, target
+    sim.close()
+
+
+def test_cfg3_full_size_step():
+    """1024x512, FP32, N = 64, f_A = 0.3 (junction segment): densities and
+    velocity after 2 steps against the oracle on the whole grid."""
+    say("[cfg3] 1024x512 N=64 FP32, 2 steps")
+    p = preset("cfg3")
+    w0 = initial_omega(1024, 512, 1003, 1e-3)
+    sim = _sim(p)
+    sim.set_fields(w0)
+    s = O.init_state(p, w0)
+    phi0 = sim.densities()
+    for I in range(3):
+        assert rel(phi0[I], s["phi"][I]) < 1e-4
+    sim.step(2)
+    for _ in range(2):
+        s = O.step(s, p)
+    sim.sync()
+    phi = sim.densities()
+    for I in range(3):
+        assert rel(phi[I], s["phi"][I]) < 1e-4
+    rho, u = sim.velocity()
+    assert rel(u[0], s["u"][0]) < 1e-4
+    d = sim.diag()
+    assert abs(d["Q_P"] / s["Q_P"] - 1) < 1e-5
+    sim.close()
+
+
+def test_determinism_bitwise():
+    say("[determinism] 128x64 FP32 x2")
+    p = preset("cfg2", nx=128, ny=64)
+    outs = []
+    for _ in range(2):
+        sim = _sim(p)
+        sim.seed(77, 1e-3)
+        sim.step(20)
+        sim.sync()
+        outs.append((sim.densities(), sim.populations()))
+        sim.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
