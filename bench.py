@@ -67,6 +67,8 @@ def main():
     ap.add_argument("--profile-launches", type=int, default=8192)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tune-cache", default=None)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -85,21 +87,24 @@ def main():
     torch.cuda.set_device(0)
     sim = Simulation(p)
     sim.seed(cfg["seed"], cfg["sigma"])
+    shapes = sim.shapes() if args.no_tune else sim.autotune(20, args.tune_cache)
     sim.step(args.warmup)
     sim.sync()
 
     stream = torch.cuda.current_stream()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    sim.profile_start(args.profile_launches)
     torch.cuda.synchronize()
     ev0.record(stream)
     sim.step(args.steps)
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
-    prof = sim.profile_read()
     sim.sync()
+    # per-kernel event timing (stream launches, after the timed region)
+    sim.profile_start(args.profile_launches)
+    sim.step(max(1, args.profile_launches // (2 * N + 8)))
+    prof = sim.profile_read()
     ms_per_step = ms / args.steps
     value = n * args.steps / (ms / 1e3)
 
@@ -124,7 +129,7 @@ def main():
                config=dict(workload=f"{args.workload}: {cfg['name']}, chi reading L, g={p['g']}, "
                                     f"seed {cfg['seed']} noise sigma {cfg['sigma']}, plain (exact propagator)",
                            nx=p["nx"], ny=p["ny"], n_contour=N, path="plain"),
-               roofline=roofline, breakdown=breakdown, Q_P=d["Q_P"])
+               roofline=roofline, breakdown=breakdown, shapes=shapes, Q_P=d["Q_P"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -147,6 +147,24 @@ int epdlb_read_aux(epdlb_ctx* ctx, int32_t which, double* out);
 int epdlb_write_aux(epdlb_ctx* ctx, int32_t which, const double* in);
 int epdlb_read_diag(epdlb_ctx* ctx, epdlb_diag* d);
 
+/* Launch shape of one FFT pass family: R values per lane, nf transforms per
+ * block, and the time per launch the autotuner measured (0 if not tuned). */
+typedef struct {
+  char family[16];       /* "prop_row", "prop_col", "force_row" or "force_col" */
+  int32_t R, nf;
+  double us;
+} epdlb_shape;
+
+/* Time the candidate launch shapes of every FFT pass family on this grid
+ * (each candidate as a captured graph of `reps` launches) and keep the
+ * fastest.  Only scratch planes are written; the simulation state is kept.
+ * `cache_path` (nullable) is a text file of earlier results that is read
+ * first and appended to.  Host-synchronous. */
+int epdlb_autotune(epdlb_ctx* ctx, int32_t reps, const char* cache_path);
+int epdlb_get_shapes(epdlb_ctx* ctx, epdlb_shape* out, int32_t cap, int32_t* n_out);
+/* Force one family's shape; EPDLB_EINVAL if it cannot be launched. */
+int epdlb_set_shape(epdlb_ctx* ctx, const char* family, int32_t R, int32_t nf);
+
 /* Per-kernel timing with HIP events recorded on the context stream around
  * each launch, for the next `max_launches` launches (later launches are not
  * recorded; recording never blocks). */

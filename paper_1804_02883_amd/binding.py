@@ -68,6 +68,11 @@ class epdlb_kernel_stat(ctypes.Structure):
     ]
 
 
+class epdlb_shape(ctypes.Structure):
+    _fields_ = [("family", ctypes.c_char * 16), ("R", ctypes.c_int32), ("nf", ctypes.c_int32),
+                ("us", ctypes.c_double)]
+
+
 class EpdlbError(RuntimeError):
     def __init__(self, code, fn, msg):
         super().__init__(f"{fn} failed ({code}): {msg}")
@@ -101,6 +106,9 @@ SIGNATURES = {
     "epdlb_read_aux": (ctypes.c_int, [_vp, ctypes.c_int32, _dp]),
     "epdlb_write_aux": (ctypes.c_int, [_vp, ctypes.c_int32, _dp]),
     "epdlb_read_diag": (ctypes.c_int, [_vp, _P(epdlb_diag)]),
+    "epdlb_autotune": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_char_p]),
+    "epdlb_get_shapes": (ctypes.c_int, [_vp, _P(epdlb_shape), ctypes.c_int32, _P(ctypes.c_int32)]),
+    "epdlb_set_shape": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_int32, ctypes.c_int32]),
     "epdlb_profile_start": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "epdlb_profile_read": (ctypes.c_int, [_vp, _P(epdlb_kernel_stat), ctypes.c_int32,
                                           _P(ctypes.c_int32)]),
@@ -259,6 +267,22 @@ def epdlb_read_diag(ctx):
                 mean_omega=tuple(d.mean_omega))
 
 
+def epdlb_autotune(ctx, reps=20, cache_path=None):
+    cp = cache_path.encode() if cache_path else None
+    _check(load_library().epdlb_autotune(ctx, reps, cp), "epdlb_autotune")
+
+
+def epdlb_get_shapes(ctx):
+    arr = (epdlb_shape * 8)()
+    n = ctypes.c_int32(0)
+    _check(load_library().epdlb_get_shapes(ctx, arr, 8, ctypes.byref(n)), "epdlb_get_shapes")
+    return {arr[i].family.decode(): (arr[i].R, arr[i].nf) for i in range(n.value)}
+
+
+def epdlb_set_shape(ctx, family, R, nf):
+    _check(load_library().epdlb_set_shape(ctx, family.encode(), R, nf), "epdlb_set_shape")
+
+
 def epdlb_profile_start(ctx, max_launches):
     _check(load_library().epdlb_profile_start(ctx, max_launches), "epdlb_profile_start")
 
@@ -362,6 +386,16 @@ class Simulation:
 
     def diag(self):
         return epdlb_read_diag(self.ctx)
+
+    def autotune(self, reps=20, cache_path=None):
+        epdlb_autotune(self.ctx, reps, cache_path)
+        return epdlb_get_shapes(self.ctx)
+
+    def shapes(self):
+        return epdlb_get_shapes(self.ctx)
+
+    def set_shape(self, family, R, nf):
+        epdlb_set_shape(self.ctx, family, R, nf)
 
     def profile_start(self, max_launches):
         epdlb_profile_start(self.ctx, max_launches)

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -119,21 +120,34 @@ struct epdlb_ctx {
   bool seeded = false;
   int64_t nstep = 0;
   std::vector<double> seg_a;   // A fraction per segment
-  int nf_row = 1, nf_col = 1, nf_frow = 1, nf_fcol = 1;
+  // FFT launch shapes: R values per lane, nf transforms per block
+  struct Shape {
+    int R, nf;
+  };
+  Shape sh_row{8, 1}, sh_col{8, 4}, sh_frow{8, 1}, sh_fcol{8, 4};
   // per-launch event profiler (epdlb_profile_start / epdlb_profile_read)
   bool prof_on = false;
   int prof_used = 0;
   std::vector<hipEvent_t> prof_ev;  // 2 per launch
   std::vector<int> prof_kind;
+  // captured multi-kernel steps, keyed by (steps, omega parity, f* parity)
+  struct GraphEntry {
+    int steps, cur, fcur;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  hipStream_t cap_stream = nullptr;
+  bool use_graph = true;
   template <typename T> T* ptr(size_t off) const { return reinterpret_cast<T*>(base + off); }
 };
 
 namespace {
 
-enum Kind { K_STATS, K_ADVECT, K_PROP_ROW, K_PROP_COL, K_DENSITY, K_FROW_FWD, K_FCOL, K_FROW_INV, K_LB,
-            K_NUM };
-const char* const kKindName[K_NUM] = {"field_stats", "advect_update", "prop_row", "prop_col", "density",
-                                      "force_row_fwd", "force_col", "force_row_inv", "lb"};
+enum Kind { K_STATS, K_ADVECT, K_FINISH, K_PROP_ROW, K_PROP_COL, K_DENSITY, K_FROW_FWD, K_FCOL, K_FROW_INV,
+            K_LB, K_NUM };
+const char* const kKindName[K_NUM] = {"field_stats",   "advect_update", "finish_stats", "prop_row",
+                                      "prop_col",      "density",       "force_row_fwd", "force_col",
+                                      "force_row_inv", "lb"};
 
 // Event pair around one launch while the profiler has room; never blocks.
 struct ProfScope {
@@ -175,20 +189,6 @@ int validate(const epdlb_params* p) {
 
 double g_lattice(const epdlb_params& p) { return p.g_units ? p.g : p.g * p.dt * p.dt / p.dx; }
 
-template <int L> int split_n1() { return Split<L>::N1; }
-int n1_of(int L) {
-  switch (L) {
-    case 16: return split_n1<16>();
-    case 32: return split_n1<32>();
-    case 64: return split_n1<64>();
-    case 128: return split_n1<128>();
-    case 256: return split_n1<256>();
-    case 512: return split_n1<512>();
-    case 1024: return split_n1<1024>();
-  }
-  return 0;
-}
-
 int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // ---------------------------------------------------------------------------
@@ -201,70 +201,115 @@ hipError_t prep_lds(K kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
 }
 
-template <typename T, int L>
-hipError_t launch_prop_row(const PropArgs<T>& a, hipStream_t s) {
-  const size_t lds = 2 * size_t(RowMap<L>::size(a.nf)) * sizeof(T);
-  hipError_t e = prep_lds(k_prop_row<T, L>, lds);
-  if (e != hipSuccess) return e;
-  const int tiles = (a.ny / 2 + a.nf - 1) / a.nf;
-  hipLaunchKernelGGL((k_prop_row<T, L>), dim3(tiles, 2), dim3(a.nf * Split<L>::N1), lds, s, a);
-  return hipGetLastError();
+template <typename T, int L, int R>
+constexpr bool fft_ok() {
+  return (R == 8 || (R == 16 && sizeof(T) == 4)) && L >= R;
 }
-template <typename T, int L, int W>
-hipError_t launch_prop_col_w(const PropArgs<T>& a, hipStream_t s) {
-  constexpr int NF = W * 64 / Split<L>::N1;
-  const size_t lds = 2 * size_t(ColMap<L, NF>::size()) * sizeof(T);
-  hipError_t e = prep_lds(k_prop_col<T, L, NF>, lds);
-  if (e != hipSuccess) return e;
-  const int tiles = (a.nx / 2 + NF - 1) / NF;
-  hipLaunchKernelGGL((k_prop_col<T, L, NF>), dim3(tiles, 2), dim3(NF * Split<L>::N1), lds, s, a);
-  return hipGetLastError();
-}
-template <typename T, int L>
-hipError_t launch_prop_col(const PropArgs<T>& a, hipStream_t s) {
-  switch (a.nf) {
-    case 1: return launch_prop_col_w<T, L, 1>(a, s);
-    case 2: return launch_prop_col_w<T, L, 2>(a, s);
-    case 4: return launch_prop_col_w<T, L, 4>(a, s);
+
+template <typename T, int L, int R>
+hipError_t launch_prop_row_r(const PropArgs<T>& a, hipStream_t s) {
+  if constexpr (fft_ok<T, L, R>()) {
+    using V = LdsView<T, L, R, true, 1>;
+    const size_t lds = 2 * size_t(V::size_per_component(a.nf)) * sizeof(T);
+    hipError_t e = prep_lds(k_prop_row<T, L, R>, lds);
+    if (e != hipSuccess) return e;
+    const int tiles = (a.ny / 2 + a.nf - 1) / a.nf;
+    hipLaunchKernelGGL((k_prop_row<T, L, R>), dim3(tiles, 2), dim3(a.nf * (L / R)), lds, s, a);
+    return hipGetLastError();
   }
   return hipErrorInvalidValue;
 }
 template <typename T, int L>
-hipError_t launch_force_row_fwd(const ForceArgs<T>& a, hipStream_t s) {
-  const size_t lds = 2 * size_t(RowMap<L>::size(a.nf)) * sizeof(T);
-  hipError_t e = prep_lds(k_force_row_fwd<T, L>, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_force_row_fwd<T, L>), dim3((a.ny + a.nf - 1) / a.nf),
-                     dim3(a.nf * Split<L>::N1), lds, s, a);
-  return hipGetLastError();
+hipError_t launch_prop_row(const PropArgs<T>& a, int R, hipStream_t s) {
+  return R == 16 ? launch_prop_row_r<T, L, 16>(a, s) : launch_prop_row_r<T, L, 8>(a, s);
 }
-template <typename T, int L, int W>
-hipError_t launch_force_col_w(const ForceArgs<T>& a, hipStream_t s) {
-  constexpr int NF = W * 64 / Split<L>::N1;
-  const size_t lds = 2 * size_t(ColMap<L, NF>::size()) * sizeof(T);
-  hipError_t e = prep_lds(k_force_col<T, L, NF>, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_force_col<T, L, NF>), dim3((a.nx + NF - 1) / NF), dim3(NF * Split<L>::N1), lds,
-                     s, a);
-  return hipGetLastError();
+
+template <typename T, int L, int R, int NF>
+hipError_t launch_prop_col_rn(const PropArgs<T>& a, hipStream_t s) {
+  if constexpr (fft_ok<T, L, R>() && NF * (L / R) <= 512 && (sizeof(T) == 4 || NF == 4)) {
+    using V = LdsView<T, L, R, false, NF>;
+    const size_t lds = 2 * size_t(V::size_per_component(NF)) * sizeof(T);
+    hipError_t e = prep_lds(k_prop_col<T, L, R, NF>, lds);
+    if (e != hipSuccess) return e;
+    const int tiles = (a.nx / 2 + NF - 1) / NF;
+    hipLaunchKernelGGL((k_prop_col<T, L, R, NF>), dim3(tiles, 2), dim3(NF * (L / R)), lds, s, a);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
 }
-template <typename T, int L>
-hipError_t launch_force_col(const ForceArgs<T>& a, hipStream_t s) {
+template <typename T, int L, int R>
+hipError_t launch_prop_col_r(const PropArgs<T>& a, hipStream_t s) {
   switch (a.nf) {
-    case 1: return launch_force_col_w<T, L, 1>(a, s);
-    case 2: return launch_force_col_w<T, L, 2>(a, s);
-    case 4: return launch_force_col_w<T, L, 4>(a, s);
+    case 4: return launch_prop_col_rn<T, L, R, 4>(a, s);
+    case 8: return launch_prop_col_rn<T, L, R, 8>(a, s);
+    case 16: return launch_prop_col_rn<T, L, R, 16>(a, s);
   }
   return hipErrorInvalidValue;
 }
 template <typename T, int L>
-hipError_t launch_force_row_inv(const ForceArgs<T>& a, hipStream_t s) {
-  const size_t lds = 2 * size_t(RowMap<L>::size(a.nf)) * sizeof(T);
-  hipError_t e = prep_lds(k_force_row_inv<T, L>, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_force_row_inv<T, L>), dim3((a.ny + a.nf - 1) / a.nf),
-                     dim3(a.nf * Split<L>::N1), lds, s, a);
-  return hipGetLastError();
+hipError_t launch_prop_col(const PropArgs<T>& a, int R, hipStream_t s) {
+  return R == 16 ? launch_prop_col_r<T, L, 16>(a, s) : launch_prop_col_r<T, L, 8>(a, s);
+}
+
+template <typename T, int L, int R>
+hipError_t launch_force_row_fwd_r(const ForceArgs<T>& a, hipStream_t s) {
+  if constexpr (fft_ok<T, L, R>()) {
+    using V = LdsView<T, L, R, true, 1>;
+    const size_t lds = 2 * size_t(V::size_per_component(a.nf)) * sizeof(T);
+    hipError_t e = prep_lds(k_force_row_fwd<T, L, R>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_force_row_fwd<T, L, R>), dim3((a.ny + a.nf - 1) / a.nf), dim3(a.nf * (L / R)),
+                       lds, s, a);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+template <typename T, int L>
+hipError_t launch_force_row_fwd(const ForceArgs<T>& a, int R, hipStream_t s) {
+  return R == 16 ? launch_force_row_fwd_r<T, L, 16>(a, s) : launch_force_row_fwd_r<T, L, 8>(a, s);
+}
+template <typename T, int L, int R>
+hipError_t launch_force_row_inv_r(const ForceArgs<T>& a, hipStream_t s) {
+  if constexpr (fft_ok<T, L, R>()) {
+    using V = LdsView<T, L, R, true, 1>;
+    const size_t lds = 2 * size_t(V::size_per_component(a.nf)) * sizeof(T);
+    hipError_t e = prep_lds(k_force_row_inv<T, L, R>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_force_row_inv<T, L, R>), dim3((a.ny + a.nf - 1) / a.nf), dim3(a.nf * (L / R)),
+                       lds, s, a);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+template <typename T, int L>
+hipError_t launch_force_row_inv(const ForceArgs<T>& a, int R, hipStream_t s) {
+  return R == 16 ? launch_force_row_inv_r<T, L, 16>(a, s) : launch_force_row_inv_r<T, L, 8>(a, s);
+}
+template <typename T, int L, int R, int NF>
+hipError_t launch_force_col_rn(const ForceArgs<T>& a, hipStream_t s) {
+  if constexpr (fft_ok<T, L, R>() && NF * (L / R) <= 512 && (sizeof(T) == 4 || NF == 4)) {
+    using V = LdsView<T, L, R, false, NF>;
+    const size_t lds = 2 * size_t(V::size_per_component(NF)) * sizeof(T);
+    hipError_t e = prep_lds(k_force_col<T, L, R, NF>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_force_col<T, L, R, NF>), dim3((a.nx + NF - 1) / NF), dim3(NF * (L / R)), lds, s,
+                       a);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+template <typename T, int L, int R>
+hipError_t launch_force_col_r(const ForceArgs<T>& a, hipStream_t s) {
+  switch (a.nf) {
+    case 4: return launch_force_col_rn<T, L, R, 4>(a, s);
+    case 8: return launch_force_col_rn<T, L, R, 8>(a, s);
+    case 16: return launch_force_col_rn<T, L, R, 16>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+template <typename T, int L>
+hipError_t launch_force_col(const ForceArgs<T>& a, int R, hipStream_t s) {
+  return R == 16 ? launch_force_col_r<T, L, 16>(a, s) : launch_force_col_r<T, L, 8>(a, s);
 }
 
 #define EPDLB_SWITCH_L(L, FN, T, ...)                 \
@@ -279,20 +324,20 @@ hipError_t launch_force_row_inv(const ForceArgs<T>& a, hipStream_t s) {
   }                                                   \
   return hipErrorInvalidValue;
 
-template <typename T> hipError_t prop_row(int L, const PropArgs<T>& a, hipStream_t s) {
-  EPDLB_SWITCH_L(L, launch_prop_row, T, a, s)
+template <typename T> hipError_t prop_row(int L, int R, const PropArgs<T>& a, hipStream_t s) {
+  EPDLB_SWITCH_L(L, launch_prop_row, T, a, R, s)
 }
-template <typename T> hipError_t prop_col(int L, const PropArgs<T>& a, hipStream_t s) {
-  EPDLB_SWITCH_L(L, launch_prop_col, T, a, s)
+template <typename T> hipError_t prop_col(int L, int R, const PropArgs<T>& a, hipStream_t s) {
+  EPDLB_SWITCH_L(L, launch_prop_col, T, a, R, s)
 }
-template <typename T> hipError_t force_row_fwd(int L, const ForceArgs<T>& a, hipStream_t s) {
-  EPDLB_SWITCH_L(L, launch_force_row_fwd, T, a, s)
+template <typename T> hipError_t force_row_fwd(int L, int R, const ForceArgs<T>& a, hipStream_t s) {
+  EPDLB_SWITCH_L(L, launch_force_row_fwd, T, a, R, s)
 }
-template <typename T> hipError_t force_col(int L, const ForceArgs<T>& a, hipStream_t s) {
-  EPDLB_SWITCH_L(L, launch_force_col, T, a, s)
+template <typename T> hipError_t force_col(int L, int R, const ForceArgs<T>& a, hipStream_t s) {
+  EPDLB_SWITCH_L(L, launch_force_col, T, a, R, s)
 }
-template <typename T> hipError_t force_row_inv(int L, const ForceArgs<T>& a, hipStream_t s) {
-  EPDLB_SWITCH_L(L, launch_force_row_inv, T, a, s)
+template <typename T> hipError_t force_row_inv(int L, int R, const ForceArgs<T>& a, hipStream_t s) {
+  EPDLB_SWITCH_L(L, launch_force_row_inv, T, a, R, s)
 }
 
 // ---------------------------------------------------------------------------
@@ -306,11 +351,12 @@ int stage_stats(epdlb_ctx* c) {
   a.n = n;
   a.scal = c->ptr<double>(c->L.scal);
   a.partials = c->ptr<double>(c->L.partials);
-  a.counter = c->ptr<unsigned>(c->L.counters) + 0;
-  a.dA = c->p.dx * c->p.dx;
   const int blocks = int(std::min<long>(1024, (n + 255) / 256));
   ProfScope ps(c, K_STATS);
   hipLaunchKernelGGL((k_field_stats<T>), dim3(blocks), dim3(256), 0, c->stream, a);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(k_finish_stats, dim3(1), dim3(256), 0, c->stream, a.partials, blocks, a.scal, n,
+                     c->p.dx * c->p.dx);
   HIPCHK(hipGetLastError());
   return EPDLB_OK;
 }
@@ -327,7 +373,6 @@ int stage_advect_update(epdlb_ctx* c) {
   a.stilde = c->ptr<T>(c->L.stilde);
   a.scal = c->ptr<double>(c->L.scal);
   a.partials = c->ptr<double>(c->L.partials);
-  a.counter = c->ptr<unsigned>(c->L.counters) + 0;
   a.nx = p.nx;
   a.ny = p.ny;
   a.n = n;
@@ -341,10 +386,15 @@ int stage_advect_update(epdlb_ctx* c) {
     a.invD[i] = T(1.0 / D[i]);
   }
   a.advect = p.couple_lb ? 1 : 0;
-  a.dA = p.dx * p.dx;
   {
     ProfScope ps(c, K_ADVECT);
     hipLaunchKernelGGL((k_advect_update<T>), dim3(p.nx / kTX, p.ny / kTY), dim3(kTX * kTY), 0, c->stream, a);
+  }
+  HIPCHK(hipGetLastError());
+  {
+    ProfScope ps(c, K_FINISH);
+    hipLaunchKernelGGL(k_finish_stats, dim3(1), dim3(256), 0, c->stream, a.partials,
+                       (p.nx / kTX) * (p.ny / kTY), c->ptr<double>(c->L.scal), n, p.dx * p.dx);
   }
   HIPCHK(hipGetLastError());
   c->cur = 1 - c->cur;
@@ -352,9 +402,8 @@ int stage_advect_update(epdlb_ctx* c) {
 }
 
 template <typename T>
-int stage_densities(epdlb_ctx* c, bool with_S) {
+PropArgs<T> make_prop_args(epdlb_ctx* c) {
   const epdlb_params& p = c->p;
-  const int N = p.n_contour;
   const long n = long(p.nx) * p.ny;
   PropArgs<T> a;
   a.wA = c->ptr<T>(c->L.omega[c->cur]);
@@ -370,27 +419,60 @@ int stage_densities(epdlb_ctx* c, bool with_S) {
   a.nx = p.nx;
   a.ny = p.ny;
   a.plane = n;
-  a.nsteps = N;
   a.partials = c->ptr<double>(c->L.partials);
-  a.counter = c->ptr<unsigned>(c->L.counters) + 1;
-  a.qout = c->ptr<double>(c->L.scal) + kQPf;
-  a.dA = p.dx * p.dx;
-  for (int j = 0; j < N; ++j) {
-    a.j = j;
-    a.a[0] = T(c->seg_a[j]);
-    a.a[1] = T(c->seg_a[N - 1 - j]);
-    a.nf = c->nf_row;
-    {
+  a.a = 0;
+  a.first = a.mid = a.second = a.last = 0;
+  a.frac[0][0] = a.frac[0][1] = a.frac[1][0] = a.frac[1][1] = T(1);
+  a.nf = 1;
+  return a;
+}
+
+template <typename T>
+int stage_densities(epdlb_ctx* c, bool with_S) {
+  const epdlb_params& p = c->p;
+  const int N = p.n_contour;
+  const long n = long(p.nx) * p.ny;
+  PropArgs<T> a = make_prop_args<T>(c);
+  auto seg = [&](int chain, int step) { return T(c->seg_a[chain == 0 ? step : N - 1 - step]); };
+  auto launch = [&](bool row) -> int {
+    if (row) {
+      a.nf = c->sh_row.nf;
       ProfScope ps(c, K_PROP_ROW);
-      HIPCHK(prop_row<T>(p.nx, a, c->stream));
-    }
-    a.nf = c->nf_col;
-    {
+      HIPCHK(prop_row<T>(p.nx, c->sh_row.R, a, c->stream));
+    } else {
+      a.nf = c->sh_col.nf;
       ProfScope ps(c, K_PROP_COL);
-      HIPCHK(prop_col<T>(p.ny, a, c->stream));
+      HIPCHK(prop_col<T>(p.ny, c->sh_col.R, a, c->stream));
     }
+    return EPDLB_OK;
+  };
+  // step 0 starts with its x convolution of E(step 0)
+  a.a = 0;
+  a.first = 1;
+  a.mid = a.second = a.last = 0;
+  for (int ch = 0; ch < 2; ++ch) a.frac[ch][0] = a.frac[ch][1] = seg(ch, 0);
+  CHK(launch(true));
+  // boundary a -> a+1: last convolution of step a and first of step a+1
+  // (y-oriented after an even step, x-oriented after an odd one)
+  a.first = 0;
+  a.mid = 1;
+  for (int s = 0; s < N; ++s) {
+    a.a = s;
+    a.second = s + 1 < N;
+    a.last = s + 1 == N;
+    for (int ch = 0; ch < 2; ++ch) {
+      a.frac[ch][0] = seg(ch, s);
+      a.frac[ch][1] = s + 1 < N ? seg(ch, s + 1) : seg(ch, s);
+    }
+    CHK(launch(s % 2 == 1));
   }
   DensArgs<T> d;
+  d.qpart = a.partials;
+  // partial slots of the final propagator launch (x-oriented if N-1 is odd)
+  d.nqpart = ((N - 1) % 2 == 1) ? (p.ny / 2 + c->sh_row.nf - 1) / c->sh_row.nf
+                                : (p.nx / 2 + c->sh_col.nf - 1) / c->sh_col.nf;
+  d.dA = p.dx * p.dx;
+  d.scal_out = c->ptr<double>(c->L.scal);
   d.q[0] = a.q[0];
   d.q[1] = a.q[1];
   d.wS = a.wA + 2 * n;
@@ -417,7 +499,7 @@ int stage_densities(epdlb_ctx* c, bool with_S) {
 }
 
 template <typename T>
-int stage_force(epdlb_ctx* c) {
+ForceArgs<T> make_force_args(epdlb_ctx* c) {
   const epdlb_params& p = c->p;
   ForceArgs<T> a;
   a.S = c->ptr<T>(c->L.S);
@@ -433,20 +515,28 @@ int stage_force(epdlb_ctx* c) {
   a.pref = p.kT_over_v / p.dt / (double(p.nx) * p.ny);
   a.conv = p.couple_lb ? p.dt * p.dt / p.dx : 0.0;
   a.gext = g_lattice(p);
-  a.nf = c->nf_frow;
+  a.nf = 1;
+  return a;
+}
+
+template <typename T>
+int stage_force(epdlb_ctx* c) {
+  const epdlb_params& p = c->p;
+  ForceArgs<T> a = make_force_args<T>(c);
+  a.nf = c->sh_frow.nf;
   {
     ProfScope ps(c, K_FROW_FWD);
-    HIPCHK(force_row_fwd<T>(p.nx, a, c->stream));
+    HIPCHK(force_row_fwd<T>(p.nx, c->sh_frow.R, a, c->stream));
   }
-  a.nf = c->nf_fcol;
+  a.nf = c->sh_fcol.nf;
   {
     ProfScope ps(c, K_FCOL);
-    HIPCHK(force_col<T>(p.ny, a, c->stream));
+    HIPCHK(force_col<T>(p.ny, c->sh_fcol.R, a, c->stream));
   }
-  a.nf = c->nf_frow;
+  a.nf = c->sh_frow.nf;
   {
     ProfScope ps(c, K_FROW_INV);
-    HIPCHK(force_row_inv<T>(p.nx, a, c->stream));
+    HIPCHK(force_row_inv<T>(p.nx, c->sh_frow.R, a, c->stream));
   }
   return EPDLB_OK;
 }
@@ -488,6 +578,102 @@ int run_stage_t(epdlb_ctx* c, int stage) {
 
 int run_stage(epdlb_ctx* c, int stage) {
   return c->p.precision == 0 ? run_stage_t<double>(c, stage) : run_stage_t<float>(c, stage);
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner for the FFT pass launch shapes (values per lane R, transforms per
+// block nf).  A candidate is timed as a captured graph of `reps` back-to-back
+// launches; the passes write scratch planes only (row output, chain plane 2,
+// Q partials, force spectrum and force planes), so the state is unchanged.
+// ---------------------------------------------------------------------------
+enum Family { F_PROP_ROW, F_PROP_COL, F_FORCE_ROW, F_FORCE_COL, F_NUM };
+const char* const kFamilyName[F_NUM] = {"prop_row", "prop_col", "force_row", "force_col"};
+
+epdlb_ctx::Shape& family_shape(epdlb_ctx* c, int f) {
+  switch (f) {
+    case F_PROP_ROW: return c->sh_row;
+    case F_PROP_COL: return c->sh_col;
+    case F_FORCE_ROW: return c->sh_frow;
+    default: return c->sh_fcol;
+  }
+}
+
+template <typename T>
+hipError_t launch_family(epdlb_ctx* c, int fam, int R, int nf, hipStream_t s) {
+  const epdlb_params& p = c->p;
+  if (fam == F_PROP_ROW || fam == F_PROP_COL) {
+    PropArgs<T> a = make_prop_args<T>(c);
+    a.a = 0;  // fused boundary kernel: writes q_1 and the scratch plane
+    a.mid = a.second = 1;
+    a.nf = nf;
+    return fam == F_PROP_ROW ? prop_row<T>(p.nx, R, a, s) : prop_col<T>(p.ny, R, a, s);
+  }
+  ForceArgs<T> a = make_force_args<T>(c);
+  a.nf = nf;
+  if (fam == F_FORCE_ROW) {
+    hipError_t e = force_row_fwd<T>(p.nx, R, a, s);
+    if (e != hipSuccess) return e;
+    return force_row_inv<T>(p.nx, R, a, s);
+  }
+  return force_col<T>(p.ny, R, a, s);
+}
+
+// Average microseconds per launch of one candidate, or a negative value if the
+// candidate cannot be launched.
+double time_candidate(epdlb_ctx* c, int fam, int R, int nf, int reps) {
+  auto launch = [&](hipStream_t s) {
+    return c->p.precision == 0 ? launch_family<double>(c, fam, R, nf, s)
+                               : launch_family<float>(c, fam, R, nf, s);
+  };
+  if (launch(c->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return -1.0;
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return -1.0;
+  if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return -1.0;
+  if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess) return -1.0;
+  bool ok = true;
+  for (int i = 0; i < reps && ok; ++i) ok = launch(c->cap_stream) == hipSuccess;
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture(c->cap_stream, &g) != hipSuccess || !ok || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return -1.0;
+  }
+  hipGraphExec_t ge = nullptr;
+  hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return -1.0;
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  double best = 1e30;
+  (void)hipGraphLaunch(ge, c->stream);  // warm
+  for (int t = 0; t < 3; ++t) {
+    (void)hipEventRecord(e0, c->stream);
+    (void)hipGraphLaunch(ge, c->stream);
+    (void)hipEventRecord(e1, c->stream);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    best = std::min(best, 1e3 * double(ms) / reps);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipGraphExecDestroy(ge);
+  return best;
+}
+
+void drop_graphs(epdlb_ctx* c) {
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+  c->graphs.clear();
+}
+
+std::string tune_key(const epdlb_ctx* c, int fam) {
+  char buf[128];
+  std::snprintf(buf, sizeof(buf), "gfx950 %d %d %d %d %s", c->p.nx, c->p.ny, c->p.n_contour, c->p.precision,
+                kFamilyName[fam]);
+  return buf;
 }
 
 // ---------------------------------------------------------------------------
@@ -574,6 +760,17 @@ int compute_stats(epdlb_ctx* c) {
   return EPDLB_OK;
 }
 
+// Populations live on the device as deviations from the rest weights w_i.
+const double kW9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+int upload_populations(epdlb_ctx* c, size_t off, const double* f) {
+  const size_t n = size_t(c->p.nx) * c->p.ny;
+  std::vector<double> g(9 * n);
+  for (int k = 0; k < 9; ++k)
+    for (size_t i = 0; i < n; ++i) g[k * n + i] = f[k * n + i] - kW9[k];
+  return upload(c, off, g.data(), g.size());
+}
+
 // LB at f^eq(rho = 1, u_init); u_init the analytic reverse-Poiseuille profile.
 int init_lb(epdlb_ctx* c) {
   const epdlb_params& p = c->p;
@@ -603,9 +800,46 @@ int init_lb(epdlb_ctx* c) {
       }
     }
   c->fcur = 0;
-  CHK(upload(c, c->L.fstar[0], f.data(), f.size()));
+  CHK(upload_populations(c, c->L.fstar[0], f.data()));
   CHK(upload(c, c->L.u, u.data(), u.size()));
   CHK(upload(c, c->L.rho, rho.data(), rho.size()));
+  return EPDLB_OK;
+}
+
+// Capture `steps` hybrid steps from the current buffer parity into a graph.
+int get_graph(epdlb_ctx* c, int steps, hipGraphExec_t* out) {
+  for (auto& g : c->graphs)
+    if (g.steps == steps && g.cur == c->cur && g.fcur == c->fcur) {
+      *out = g.exec;
+      return EPDLB_OK;
+    }
+  if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  const int cur0 = c->cur, fcur0 = c->fcur;
+  const bool prof0 = c->prof_on;
+  hipStream_t user = c->stream;
+  c->stream = c->cap_stream;
+  c->prof_on = false;
+  HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+  int r = EPDLB_OK;
+  for (int s = 0; s < steps && r == EPDLB_OK; ++s)
+    for (int st = EPDLB_STAGE_ADVECT_UPDATE; st <= EPDLB_STAGE_LB && r == EPDLB_OK; ++st) r = run_stage(c, st);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+  c->stream = user;
+  c->prof_on = prof0;
+  c->cur = cur0;
+  c->fcur = fcur0;
+  if (r != EPDLB_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return r;
+  }
+  HIPCHK(e);
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  HIPCHK(e);
+  c->graphs.push_back({steps, cur0, fcur0, exec});
+  *out = exec;
   return EPDLB_OK;
 }
 
@@ -694,6 +928,7 @@ int epdlb_create(const epdlb_params* p, int device, void* stream, void* workspac
   if (!c) return fail(EPDLB_ENOMEM, "host allocation failed");
   c->p = *p;
   c->device = device;
+  if (const char* env = std::getenv("EPDLB_GRAPH")) c->use_graph = std::atoi(env) != 0;
   c->L = make_layout(*p);
   if (stream) {
     c->stream = reinterpret_cast<hipStream_t>(stream);
@@ -719,23 +954,18 @@ int epdlb_create(const epdlb_params* p, int device, void* stream, void* workspac
     c->base = static_cast<unsigned char*>(m);
     c->own_mem = true;
   }
-  // launch shapes.  Row passes: nf transforms of n1x lanes per block; column
-  // passes: nf = wavefronts per block.  Prefer enough blocks to cover the CUs.
-  const int n1x = n1_of(p->nx), n1y = n1_of(p->ny);
-  auto pick_row = [&](int transforms, int chains) {
-    int nf = 256 / n1x;
-    while (nf * n1x > 64 && chains * ((transforms + nf - 1) / nf) < 512) nf /= 2;
-    return clampi(nf, 1, transforms);
+  // launch shapes (defaults; R = 8 values per lane).  Row passes: nf
+  // transforms of L/R lanes per block (<= 256 lanes); column passes: NF
+  // transforms interleaved, NF*L/R <= 512 lanes, NF = 8 where it fits.
+  auto row_nf = [&](int L, int transforms) {
+    const int tl = L / 8;
+    return clampi(256 / tl, 1, transforms);
   };
-  auto pick_col = [&](int transforms, int chains) {
-    int w = 4;
-    while (w > 1 && chains * ((transforms + w * 64 / n1y - 1) / (w * 64 / n1y)) < 512) w /= 2;
-    return w;
-  };
-  c->nf_row = pick_row(p->ny / 2, 2);
-  c->nf_col = pick_col(p->nx / 2, 2);
-  c->nf_frow = pick_row(p->ny, 1);
-  c->nf_fcol = pick_col(p->nx, 1);
+  auto col_nf = [&](int L) { return (L / 8) * 8 <= 512 ? 8 : 4; };
+  c->sh_row = {8, row_nf(p->nx, p->ny / 2)};
+  c->sh_col = {8, p->precision == 0 ? 4 : col_nf(p->ny)};
+  c->sh_frow = {8, row_nf(p->nx, p->ny)};
+  c->sh_fcol = {8, p->precision == 0 ? 4 : col_nf(p->ny)};
   int r = upload_tables(c);
   if (r != EPDLB_OK) {
     epdlb_destroy(c);
@@ -777,7 +1007,7 @@ int epdlb_set_state(epdlb_ctx* c, const double* omega, const double* phi, const 
   c->fcur = 0;
   CHK(upload(c, c->L.omega[0], omega, 3 * n));
   CHK(upload(c, c->L.phi, phi, 3 * n));
-  CHK(upload(c, c->L.fstar[0], fstar, 9 * n));
+  CHK(upload_populations(c, c->L.fstar[0], fstar));
   CHK(upload(c, c->L.u, u, 2 * n));
   HIPCHK(hipMemsetAsync(c->base + c->L.scal, 0, kNumScal * sizeof(double), c->stream));
   CHK(compute_stats(c));
@@ -792,6 +1022,23 @@ int epdlb_step(epdlb_ctx* c, int64_t n) {
   if (!c->seeded) return fail(EPDLB_ESTATE, "step before seed/set_fields/set_state");
   if (n < 0) return fail(EPDLB_EINVAL, "negative step count");
   HIPCHK(hipSetDevice(c->device));
+  if (c->use_graph && !c->prof_on) {
+    // replay captured two-step graphs (buffer parity returns to its start),
+    // then a one-step graph for an odd remainder
+    while (n > 0) {
+      const int k = n >= 2 ? 2 : 1;
+      hipGraphExec_t g;
+      CHK(get_graph(c, k, &g));
+      HIPCHK(hipGraphLaunch(g, c->stream));
+      if (k == 1) {
+        c->cur = 1 - c->cur;
+        c->fcur = 1 - c->fcur;
+      }
+      c->nstep += k;
+      n -= k;
+    }
+    return EPDLB_OK;
+  }
   for (int64_t s = 0; s < n; ++s) {
     for (int st = EPDLB_STAGE_ADVECT_UPDATE; st <= EPDLB_STAGE_LB; ++st) CHK(run_stage(c, st));
     ++c->nstep;
@@ -839,7 +1086,11 @@ int epdlb_read_velocity(epdlb_ctx* c, double* rho, double* ux, double* uy) {
 
 int epdlb_read_populations(epdlb_ctx* c, double* f) {
   if (!c || !f) return fail(EPDLB_EINVAL, "NULL argument");
-  return download(c, c->L.fstar[c->fcur], f, 9 * size_t(c->p.nx) * c->p.ny);
+  const size_t n = size_t(c->p.nx) * c->p.ny;
+  CHK(download(c, c->L.fstar[c->fcur], f, 9 * n));
+  for (int k = 0; k < 9; ++k)
+    for (size_t i = 0; i < n; ++i) f[k * n + i] += kW9[k];
+  return EPDLB_OK;
 }
 
 static int aux_loc(epdlb_ctx* c, int which, size_t* off, size_t* planes) {
@@ -879,6 +1130,98 @@ int epdlb_read_diag(epdlb_ctx* c, epdlb_diag* d) {
   d->mean_omega[1] = s[kMeanB];
   d->mean_omega[2] = s[kMeanS];
   return EPDLB_OK;
+}
+
+int epdlb_autotune(epdlb_ctx* c, int32_t reps, const char* cache_path) {
+  if (!c || reps < 1) return fail(EPDLB_EINVAL, "bad autotune arguments");
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  // cached results
+  std::vector<std::string> cache_lines;
+  if (cache_path) {
+    if (FILE* fp = std::fopen(cache_path, "r")) {
+      char line[256];
+      while (std::fgets(line, sizeof(line), fp)) cache_lines.emplace_back(line);
+      std::fclose(fp);
+    }
+  }
+  const bool fp32 = c->p.precision == 1;
+  const char* verbose_env = std::getenv("EPDLB_TUNE_VERBOSE");
+  const bool verbose = verbose_env && std::atoi(verbose_env) != 0;
+  for (int fam = 0; fam < F_NUM; ++fam) {
+    const std::string key = tune_key(c, fam);
+    bool found = false;
+    for (auto& l : cache_lines) {
+      if (l.compare(0, key.size(), key) == 0 && l.size() > key.size() && l[key.size()] == ' ') {
+        int R = 0, nf = 0;
+        double us = 0;
+        if (std::sscanf(l.c_str() + key.size(), "%d %d %lf", &R, &nf, &us) == 3 &&
+            time_candidate(c, fam, R, nf, 1) >= 0.0) {
+          family_shape(c, fam) = {R, nf};
+          found = true;
+        }
+      }
+    }
+    if (found) continue;
+    const bool row = (fam == F_PROP_ROW || fam == F_FORCE_ROW);
+    const int L = row ? c->p.nx : c->p.ny;
+    const int transforms = fam == F_PROP_ROW ? c->p.ny / 2 : c->p.ny;
+    double best = 1e30;
+    epdlb_ctx::Shape best_sh = family_shape(c, fam);
+    const int Rs[2] = {8, 16};
+    for (int R : Rs) {
+      if (R == 16 && !fp32) continue;
+      if (row) {
+        for (int nf = 1; nf * (L / R) <= 256 && nf <= transforms; nf *= 2) {
+          const double us = time_candidate(c, fam, R, nf, reps);
+          if (verbose) std::fprintf(stderr, "[tune] %s R=%d nf=%d: %.3f us\n", kFamilyName[fam], R, nf, us);
+          if (us > 0 && us < best) best = us, best_sh = {R, nf};
+        }
+      } else {
+        const int nfs[3] = {4, 8, 16};
+        for (int nf : nfs) {
+          const double us = time_candidate(c, fam, R, nf, reps);
+          if (verbose) std::fprintf(stderr, "[tune] %s R=%d nf=%d: %.3f us\n", kFamilyName[fam], R, nf, us);
+          if (us > 0 && us < best) best = us, best_sh = {R, nf};
+        }
+      }
+    }
+    family_shape(c, fam) = best_sh;
+    if (cache_path && best < 1e29) {
+      if (FILE* fp = std::fopen(cache_path, "a")) {
+        std::fprintf(fp, "%s %d %d %.3f\n", key.c_str(), best_sh.R, best_sh.nf, best);
+        std::fclose(fp);
+      }
+    }
+  }
+  drop_graphs(c);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return EPDLB_OK;
+}
+
+int epdlb_get_shapes(epdlb_ctx* c, epdlb_shape* out, int32_t cap, int32_t* n_out) {
+  if (!c || !out || !n_out || cap < F_NUM) return fail(EPDLB_EINVAL, "bad shape arguments");
+  for (int f = 0; f < F_NUM; ++f) {
+    std::memset(&out[f], 0, sizeof(out[f]));
+    std::snprintf(out[f].family, sizeof(out[f].family), "%s", kFamilyName[f]);
+    out[f].R = family_shape(c, f).R;
+    out[f].nf = family_shape(c, f).nf;
+  }
+  *n_out = F_NUM;
+  return EPDLB_OK;
+}
+
+int epdlb_set_shape(epdlb_ctx* c, const char* family, int32_t R, int32_t nf) {
+  if (!c || !family) return fail(EPDLB_EINVAL, "NULL argument");
+  for (int f = 0; f < F_NUM; ++f)
+    if (std::strcmp(family, kFamilyName[f]) == 0) {
+      HIPCHK(hipSetDevice(c->device));
+      if (time_candidate(c, f, R, nf, 1) < 0.0) return fail(EPDLB_EINVAL, "shape cannot be launched");
+      family_shape(c, f) = {R, nf};
+      drop_graphs(c);
+      return EPDLB_OK;
+    }
+  return fail(EPDLB_EINVAL, "unknown pass family");
 }
 
 int epdlb_profile_start(epdlb_ctx* c, int32_t max_launches) {
@@ -930,6 +1273,8 @@ int epdlb_profile_read(epdlb_ctx* c, epdlb_kernel_stat* out, int32_t cap, int32_
 
 void epdlb_destroy(epdlb_ctx* c) {
   if (!c) return;
+  drop_graphs(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->own_mem && c->base) (void)hipFree(c->base);

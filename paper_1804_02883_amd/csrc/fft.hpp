@@ -1,15 +1,16 @@
-// Register + LDS FFT building blocks for gfx950 (64-wide wavefronts).
+// Register + LDS Stockham FFT for gfx950 (64-wide wavefronts).
 //
-// A length-L transform is split L = N1 x N2 (N1 <= N2, powers of two).  A
-// group of N1 lanes owns one transform:
-//   time layout  lane n1 holds v[n2] = x[n1 + N1*n2],            n2 = 0..N2-1
-//   freq layout  lane t  holds r[m*N1 + k1] = X[(t + N1*m) + N2*k1],
-//                m = 0..N2/N1-1, k1 = 0..N1-1
-// The forward transform is an N2-point DFT in registers, a twiddle by
-// W_L^{n1*k2}, one LDS exchange, and N1-point DFTs in registers.  The inverse
-// runs the same steps backwards, so a pointwise multiplier can be applied in
-// the (permuted) frequency layout with no reordering.  Global loads in the
-// time layout are contiguous across the N1 lanes of a group.
+// One length-L transform is owned by T = L/R lanes; lane j holds the R
+// elements j + T*m (m = 0..R-1) in registers, in BOTH the time and the
+// frequency domain, so global loads and stores are contiguous across lanes
+// and a pointwise multiplier is applied without any reordering.
+//
+// The forward transform is a Stockham auto-sort FFT (decimation in time) with
+// radices [R0, R, ..., R] (R0 = L / R^(S-1)); the inverse runs radices
+// [R, ..., R, R0] with conjugate twiddles.  Each pass is a radix-r DFT in
+// registers; consecutive passes exchange data through LDS.  The first pass of
+// each direction reads registers and the last one leaves its outputs in
+// registers, so a forward+inverse pair costs 2(S-1) LDS round trips.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -71,6 +72,7 @@ constexpr int brev(int k, int bits) {
   return r;
 }
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
 // In-register DFT of size R (power of two, R <= 64), natural order in and out.
 // SIGN = -1: X[k] = sum x[n] e^{-2 pi i nk/R};  SIGN = +1: conjugate kernel.
@@ -120,114 +122,180 @@ __device__ __forceinline__ void dft(T* re, T* im) {
   }
 }
 
-// Split of a transform length into N1 lanes x N2 registers.
-template <int L> struct Split {
-  static constexpr int N1 = L <= 32 ? 4 : L <= 128 ? 8 : L <= 512 ? 16 : 32;
-  static constexpr int N2 = L / N1;
-  static constexpr int M = N2 / N1;
-  static_assert(N1 * N2 == L && N2 % N1 == 0, "split");
-};
-
-// LDS addressing for one exchange buffer: element (transform f, k2, n1) of
-// the real or imaginary component.
-//  * RowMap (lanes of one transform contiguous; nf transforms per block, only
-//    the per-transform base depends on nf): f*FS + k2*(N1+1) + n1;
-//  * ColMap (NF transforms interleaved, NF a compile-time constant so every
-//    LDS access is a base register plus an immediate offset):
-//    f + NF*n1 + (NF*N1 + 16)*k2, which puts lanes with different n1 inside
-//    one wavefront into different bank groups.
-template <int L> struct RowMap {
-  using S = Split<L>;
-  static constexpr int N1 = S::N1, N2 = S::N2;
-  static constexpr int FS = N2 * (N1 + 1) + 1;
-  __host__ __device__ static constexpr int size(int nf) { return FS * nf; }
-  __device__ __forceinline__ int idx(int f, int k2, int n1) const {
-    return f * FS + k2 * (N1 + 1) + n1;
-  }
-};
-template <int L, int NF> struct ColMap {
-  using S = Split<L>;
-  static constexpr int N1 = S::N1, N2 = S::N2;
-  static constexpr int K2S = NF * N1 + 16;
-  __host__ __device__ static constexpr int size() { return K2S * N2; }
-  __device__ __forceinline__ int idx(int f, int k2, int n1) const {
-    return f + NF * n1 + K2S * k2;
-  }
-};
-
-// Forward transform: time layout in (re/im[N2]) -> freq layout out.
-// `tw` holds W_L^e = exp(-2 pi i e/L), e = 0..L-1.  All lanes of the block
-// must call this (it contains block barriers).
-template <typename T, int L, class Map>
-__device__ __forceinline__ void fft_forward(T* re, T* im, int f, int lane, const Map& map,
-                                            const T2<T>* __restrict__ tw, T* lre, T* lim) {
-  using S = Split<L>;
-  constexpr int N1 = S::N1, N2 = S::N2, M = S::M;
-  dft<T, N2, -1>(re, im);
-#pragma unroll
-  for (int k2 = 1; k2 < N2; ++k2) {
-    const T2<T> w = tw[lane * k2];
-    const T r = re[k2] * w.x - im[k2] * w.y;
-    im[k2] = re[k2] * w.y + im[k2] * w.x;
-    re[k2] = r;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k2 = 0; k2 < N2; ++k2) {
-    lre[map.idx(f, k2, lane)] = re[k2];
-    lim[map.idx(f, k2, lane)] = im[k2];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < M; ++m) {
-#pragma unroll
-    for (int n1 = 0; n1 < N1; ++n1) {
-      re[m * N1 + n1] = lre[map.idx(f, lane + N1 * m, n1)];
-      im[m * N1 + n1] = lim[map.idx(f, lane + N1 * m, n1)];
+// Pass structure of a length-L transform with R values per lane.
+template <int L, int R> struct Plan {
+  static constexpr int passes() {
+    int s = 1, p = R;
+    while (p < L) {
+      p *= R;
+      ++s;
     }
+    return s;
   }
+  static constexpr int S = passes();              // number of radix passes
+  static constexpr int R0 = L / ipow(R, S - 1);   // the one small radix
+  static constexpr int T = L / R;                 // lanes per transform
+  static constexpr int LP = L + L / 64;           // padded LDS length per component
+  static_assert(R0 >= 2 && R0 <= R && R0 * ipow(R, S - 1) == L, "plan");
+  __device__ static __forceinline__ int skew(int i) { return i + (i >> 6); }
+};
+
+// LDS view of one transform: element i of the real / imaginary component.
+//  * CONTIG:      transform f occupies [f*LP, (f+1)*LP) of each component
+//  * interleaved: transforms are the fastest index (f + NF*skew(i)), so that
+//                 lanes of one wavefront holding different transforms hit
+//                 consecutive banks
+template <typename T, int L, int R, bool CONTIG, int NF>
+struct LdsView {
+  T* re;
+  T* im;
+  int f;
+  __device__ __forceinline__ int at(int i) const {
+    if constexpr (CONTIG) return f * Plan<L, R>::LP + Plan<L, R>::skew(i);
+    else return f + NF * Plan<L, R>::skew(i);
+  }
+  __host__ __device__ static constexpr int size_per_component(int nf) {
+    return CONTIG ? Plan<L, R>::LP * nf : NF * Plan<L, R>::LP;
+  }
+};
+
+// One Stockham pass of radix r over sub-transforms of length Ns.
+// Input element of butterfly jj, leg q: in[jj + q*L/r].  Output element:
+// out[(jj/Ns)*Ns*r + jj%Ns + q*Ns].  FROM_REG / TO_REG: the pass reads /
+// leaves its data in the lane's registers (natural layout j + T*m).
+template <typename T, int L, int R, int r, int Ns, int SIGN, bool FROM_REG, bool TO_REG, class V>
+__device__ __forceinline__ void stockham_pass(T* re, T* im, int j, const V& lds, const T2<T>* w1s,
+                                              const T2<T>* whs) {
+  constexpr int TL = L / R;
+  constexpr int SUB = R / r;
+  T vr[R], vi[R];
 #pragma unroll
-  for (int m = 0; m < M; ++m) dft<T, N1, -1>(re + m * N1, im + m * N1);
+  for (int s = 0; s < SUB; ++s) {
+    const int jj = j + TL * s;
+#pragma unroll
+    for (int q = 0; q < r; ++q) {
+      if constexpr (FROM_REG) {
+        vr[s * r + q] = re[s + q * SUB];
+        vi[s * r + q] = im[s + q * SUB];
+      } else {
+        const int a = lds.at(jj + q * (L / r));
+        vr[s * r + q] = lds.re[a];
+        vi[s * r + q] = lds.im[a];
+      }
+    }
+    if constexpr (Ns > 1) {
+      // twiddles W^(k q), k = jj mod Ns, for q = 1..r-1: W^k and W^(k r/2)
+      // come preloaded (q >= r/2 restarts from the latter to bound the
+      // recurrence); complex products in between
+      const T2<T> w1 = w1s[s];
+      const T2<T> wh = whs[s];
+      const T w1y = SIGN > 0 ? -w1.y : w1.y;
+      const T why = SIGN > 0 ? -wh.y : wh.y;
+      T cr = T(1), ci = T(0);
+#pragma unroll
+      for (int q = 1; q < r; ++q) {
+        if (q == r / 2) {
+          cr = wh.x;
+          ci = why;
+        } else {
+          const T t = cr * w1.x - ci * w1y;
+          ci = cr * w1y + ci * w1.x;
+          cr = t;
+        }
+        const T x = vr[s * r + q] * cr - vi[s * r + q] * ci;
+        vi[s * r + q] = vr[s * r + q] * ci + vi[s * r + q] * cr;
+        vr[s * r + q] = x;
+      }
+    }
+    dft<T, r, SIGN>(vr + s * r, vi + s * r);
+  }
+  if constexpr (TO_REG) {
+    // last pass: Ns = L/r, so jj < Ns and the outputs are jj + q*Ns = j + T*(s + q*SUB)
+#pragma unroll
+    for (int s = 0; s < SUB; ++s)
+#pragma unroll
+      for (int q = 0; q < r; ++q) {
+        re[s + q * SUB] = vr[s * r + q];
+        im[s + q * SUB] = vi[s * r + q];
+      }
+  } else {
+    __syncthreads();  // previous readers of the buffer are done
+#pragma unroll
+    for (int s = 0; s < SUB; ++s) {
+      const int jj = j + TL * s;
+      const int base = (jj / Ns) * Ns * r + (jj & (Ns - 1));
+#pragma unroll
+      for (int q = 0; q < r; ++q) {
+        const int a = lds.at(base + q * Ns);
+        lds.re[a] = vr[s * r + q];
+        lds.im[a] = vi[s * r + q];
+      }
+    }
+    __syncthreads();
+  }
 }
 
-// Inverse transform (unnormalised): freq layout in -> time layout out.
-template <typename T, int L, class Map>
-__device__ __forceinline__ void fft_inverse(T* re, T* im, int f, int lane, const Map& map,
-                                            const T2<T>* __restrict__ tw, T* lre, T* lim) {
-  using S = Split<L>;
-  constexpr int N1 = S::N1, N2 = S::N2, M = S::M;
+// Radix and sub-transform length of pass P in each direction.
+template <int L, int R, int P, bool FWD> struct PassInfo {
+  using PL = Plan<L, R>;
+  static constexpr int r = FWD ? (P == 0 ? PL::R0 : R) : (P == PL::S - 1 ? PL::R0 : R);
+  static constexpr int Ns = P == 0 ? 1 : PassInfo<L, R, P - 1, FWD>::Ns * PassInfo<L, R, P - 1, FWD>::r;
+};
+template <int L, int R, bool FWD> struct PassInfo<L, R, -1, FWD> {
+  static constexpr int r = 1, Ns = 1;
+};
+
+// Twiddles of every pass, loaded once per kernel so that no pass waits on a
+// table load: w1[P][s] = W_L^(k e), wh[P][s] = W_L^(k (r/2) e), with
+// k = (j + T s) mod Ns and e = L/(Ns r).
+template <typename T, int L, int R> struct Twiddles {
+  static constexpr int S = Plan<L, R>::S;
+  T2<T> w1[S][R], wh[S][R];
+};
+template <typename T, int L, int R, int P, bool FWD>
+__device__ __forceinline__ void load_twiddles(Twiddles<T, L, R>& t, int j, const T2<T>* __restrict__ tw) {
+  using PI = PassInfo<L, R, P, FWD>;
+  constexpr int r = PI::r, Ns = PI::Ns, TL = L / R;
+  if constexpr (Ns > 1) {
 #pragma unroll
-  for (int m = 0; m < M; ++m) dft<T, N1, +1>(re + m * N1, im + m * N1);
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < M; ++m) {
-#pragma unroll
-    for (int n1 = 0; n1 < N1; ++n1) {
-      lre[map.idx(f, lane + N1 * m, n1)] = re[m * N1 + n1];
-      lim[map.idx(f, lane + N1 * m, n1)] = im[m * N1 + n1];
+    for (int s = 0; s < R / r; ++s) {
+      const int k = (j + TL * s) & (Ns - 1);
+      t.w1[P][s] = tw[k * (L / (Ns * r))];
+      t.wh[P][s] = tw[k * (r / 2) * (L / (Ns * r))];
     }
   }
-  __syncthreads();
-#pragma unroll
-  for (int k2 = 0; k2 < N2; ++k2) {
-    re[k2] = lre[map.idx(f, k2, lane)];
-    im[k2] = lim[map.idx(f, k2, lane)];
-  }
-#pragma unroll
-  for (int k2 = 1; k2 < N2; ++k2) {
-    const T2<T> w = tw[lane * k2];  // multiply by the conjugate twiddle
-    const T r = re[k2] * w.x + im[k2] * w.y;
-    im[k2] = im[k2] * w.x - re[k2] * w.y;
-    re[k2] = r;
-  }
-  dft<T, N2, +1>(re, im);
+  if constexpr (P + 1 < Plan<L, R>::S) load_twiddles<T, L, R, P + 1, FWD>(t, j, tw);
 }
 
-// Frequency index held in register slot (m, k1) by lane t.
-template <int L>
-__device__ __forceinline__ int freq_index(int t, int m, int k1) {
-  using S = Split<L>;
-  return (t + S::N1 * m) + S::N2 * k1;
+template <typename T, int L, int R, int P, bool FWD, class V>
+__device__ __forceinline__ void run_passes(T* re, T* im, int j, const V& lds, const Twiddles<T, L, R>& t) {
+  using PI = PassInfo<L, R, P, FWD>;
+  constexpr int S = Plan<L, R>::S;
+  stockham_pass<T, L, R, PI::r, PI::Ns, FWD ? -1 : +1, P == 0, P == S - 1>(re, im, j, lds, t.w1[P], t.wh[P]);
+  if constexpr (P + 1 < S) run_passes<T, L, R, P + 1, FWD>(re, im, j, lds, t);
+}
+
+// Twiddle sets for a forward and an inverse transform (load both before the
+// data arrives; `tw` holds W_L^e = exp(-2 pi i e/L)).
+template <typename T, int L, int R>
+__device__ __forceinline__ void load_fwd_twiddles(Twiddles<T, L, R>& t, int j, const T2<T>* tw) {
+  load_twiddles<T, L, R, 0, true>(t, j, tw);
+}
+template <typename T, int L, int R>
+__device__ __forceinline__ void load_inv_twiddles(Twiddles<T, L, R>& t, int j, const T2<T>* tw) {
+  load_twiddles<T, L, R, 0, false>(t, j, tw);
+}
+
+// x (time, lane layout j + T*m) -> X (frequency, same layout), radices
+// [R0, R, ..., R].  Every lane of the block must call it.
+template <typename T, int L, int R, class V>
+__device__ __forceinline__ void fft_forward(T* re, T* im, int j, const V& lds, const Twiddles<T, L, R>& t) {
+  run_passes<T, L, R, 0, true>(re, im, j, lds, t);
+}
+// Inverse (unnormalised), radices [R, ..., R, R0].
+template <typename T, int L, int R, class V>
+__device__ __forceinline__ void fft_inverse(T* re, T* im, int j, const V& lds, const Twiddles<T, L, R>& t) {
+  run_passes<T, L, R, 0, false>(re, im, j, lds, t);
 }
 
 }  // namespace epdlb

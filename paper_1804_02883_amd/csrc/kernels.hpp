@@ -49,64 +49,73 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red /*[16*NV]
   }
 }
 
-// Writes this block's NV sums to partials[slot*NV..], then, in the last block
-// to finish, sums all nslots partials in slot order into out[0..NV-1] and
-// resets the counter.  Returns true in the last block (all threads).
+// Writes this block's NV sums to partials[slot*NV + i].  A later kernel
+// (or a later stage of the consumer) adds the partials in slot order, so the
+// grid-wide sums are deterministic and need no device-scope fences here.
 template <int NV>
-__device__ bool grid_sum(double (&v)[NV], double* red, double* partials, int slot, int nslots,
-                         unsigned* counter, double* out) {
+__device__ __forceinline__ void block_partial(double (&v)[NV], double* red, double* partials, int slot) {
   block_sum<NV>(v, red);
-  __shared__ int is_last;
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0)
 #pragma unroll
     for (int i = 0; i < NV; ++i) partials[slot * NV + i] = v[i];
-    __threadfence();
-    const unsigned prev = atomicAdd(counter, 1u);
-    is_last = (prev == unsigned(nslots - 1));
-  }
-  __syncthreads();
-  if (!is_last) return false;
-  __threadfence();
-  double acc[NV];
+}
+
+// Sums nslots partials of NV values each, in slot order, over one block.
+template <int NV>
+__device__ __forceinline__ void sum_partials(const double* partials, int nslots, double (&acc)[NV],
+                                             double* red) {
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0.0;
   for (int s = threadIdx.x; s < nslots; s += blockDim.x)
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] += __hip_atomic_load(&partials[s * NV + i], __ATOMIC_RELAXED,
-                                                             __HIP_MEMORY_SCOPE_AGENT);
+    for (int i = 0; i < NV; ++i) acc[i] += partials[s * NV + i];
   block_sum<NV>(acc, red);
+}
+
+// Finishes the field statistics: partials of (sum w_A, sum w_B, sum w_S,
+// sum exp(-(w_S - gauge))) -> means, Q_S and the gauge it used.  One block.
+__global__ void __launch_bounds__(256) k_finish_stats(const double* partials, int nslots, double* scal,
+                                                      long n, double dA) {
+  __shared__ double red[16 * 4];
+  double acc[4];
+  sum_partials<4>(partials, nslots, acc, red);
   if (threadIdx.x == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) out[i] = acc[i];
-    *counter = 0u;
+    scal[kGaugeS] = scal[kMeanS];  // the constant the exponentials were taken with
+    scal[kMeanA] = acc[0] / double(n);
+    scal[kMeanB] = acc[1] / double(n);
+    scal[kMeanS] = acc[2] / double(n);
+    scal[kQS] = acc[3] * dA;
   }
-  return true;
 }
 
 // ---------------------------------------------------------------------------
-// Chain propagators: one contour step = row pass (K_x) + column pass (K_y).
-// Both chains (forward = 0, backward = 1) run in the same launch.
+// Chain propagators.  K = K_x K_y = K_y K_x, so each contour step applies its
+// two one-dimensional convolutions in alternating order: even steps x then y,
+// odd steps y then x.  The last convolution of step a and the first one of
+// step a+1 then share an orientation and run in ONE kernel with q_{a+1}
+// stored in between: N + 1 launches for N contour steps, both chains per
+// launch (blockIdx.y = chain; 0 forward, 1 backward).
 // ---------------------------------------------------------------------------
 template <typename T> struct PropArgs {
   const T* wA;
   const T* wB;
   const double* scal;     // kMeanA, kMeanB: gauge constants
-  T* q[2];                // chain planes q_1..q_N at q[c] + (j-1)*plane
-  T* tmp;                 // 2 planes: row-pass output per chain
+  T* q[2];                // q_1..q_N of chain c at q[c] + (j-1)*plane
+  T* tmp;                 // 2 planes (per chain): data between the two convolutions of a step
   const T* mult_x;        // exp(-R_G^2 kx^2 ds)/nx in FFT order
   const T* mult_y;        // exp(-R_G^2 ky^2 ds)/ny
   const T2<T>* tw_x;      // exp(-2 pi i e/nx)
   const T2<T>* tw_y;
   int nx, ny;
   long plane;
-  int j;                  // contour step: computes q_{j+1} from q_j
-  int nsteps;             // N
-  T a[2];                 // A-fraction of the segment each chain uses this step
-  double* partials;       // last step: Q partial sums
-  unsigned* counter;
-  double* qout;           // last step: scal + kQPf (2 values)
-  double dA;
-  int nf;                 // transforms per block
+  int a;                  // contour step finished by the first convolution
+  int first;              // input is E(step 0) (q_0 = 1) instead of tmp
+  int mid;                // after convolution 1: x E(step a), store q_{a+1}
+  int second;             // then x E(step a+1), convolution 2, store tmp
+  int last;               // with mid: partial sums of q_N for Q_P
+  T frac[2][2];           // A fraction of the segment used by chain c at step a (+0/+1)
+  double* partials;       // last: per-block sums of q_N, chain c at [c*gridDim.x]
+  int nf;                 // transforms per block (row kernels)
 };
 
 template <typename T>
@@ -115,148 +124,209 @@ __device__ __forceinline__ T boltz(T wa, T wb, T a, T ca, T cb) {
   return exp(T(-0.5) * x);
 }
 
-template <typename T, int L>
-__global__ void __launch_bounds__(256) k_prop_row(PropArgs<T> P) {
-  using S = Split<L>;
-  constexpr int N1 = S::N1, N2 = S::N2;
+// Half-step Boltzmann factor exp(-(w_seg - c_seg)/2) of a segment with A
+// fraction `fr` at flat index i.
+template <typename T>
+__device__ __forceinline__ T efactor(const PropArgs<T>& P, T fr, T ca, T cb, long i) {
+  if (fr == T(1)) return exp(T(-0.5) * (P.wA[i] - ca));
+  if (fr == T(0)) return exp(T(-0.5) * (P.wB[i] - cb));
+  return boltz(P.wA[i], P.wB[i], fr, ca, cb);
+}
+template <typename T>
+__device__ __forceinline__ T2<T> efactor2(const PropArgs<T>& P, T fr, T ca, T cb, long i2) {
+  T2<T> e;
+  if (fr == T(1)) {
+    const T2<T> w = reinterpret_cast<const T2<T>*>(P.wA)[i2];
+    e.x = exp(T(-0.5) * (w.x - ca));
+    e.y = exp(T(-0.5) * (w.y - ca));
+  } else if (fr == T(0)) {
+    const T2<T> w = reinterpret_cast<const T2<T>*>(P.wB)[i2];
+    e.x = exp(T(-0.5) * (w.x - cb));
+    e.y = exp(T(-0.5) * (w.y - cb));
+  } else {
+    const T2<T> u = reinterpret_cast<const T2<T>*>(P.wA)[i2];
+    const T2<T> w = reinterpret_cast<const T2<T>*>(P.wB)[i2];
+    e.x = boltz(u.x, w.x, fr, ca, cb);
+    e.y = boltz(u.y, w.y, fr, ca, cb);
+  }
+  return e;
+}
+
+// Convolution with the real, even multiplier g in the lane layout.
+template <typename T, int L, int R, class V>
+__device__ __forceinline__ void convolve(T* re, T* im, int j, const V& lds, const Twiddles<T, L, R>& twf,
+                                         const Twiddles<T, L, R>& twi, const T* g) {
+  fft_forward(re, im, j, lds, twf);
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    re[m] *= g[m];
+    im[m] *= g[m];
+  }
+  fft_inverse(re, im, j, lds, twi);
+}
+
+// x-oriented kernel: rows 2rp and 2rp+1 of one chain packed as one complex
+// row (the multiplier is real and even, so the two real rows stay apart).
+template <typename T, int L, int R>
+__global__ void __launch_bounds__(512) k_prop_row(PropArgs<T> P) {
+  constexpr int TL = L / R;
+  using V = LdsView<T, L, R, true, 1>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[16 * 1];
   T* lre = reinterpret_cast<T*>(smem_raw);
-  RowMap<L> map;
-  T* lim = lre + RowMap<L>::size(P.nf);
-  const int f = threadIdx.x / N1, lane = threadIdx.x % N1;
+  const int f = threadIdx.x / TL, j = threadIdx.x % TL;
+  V lds{lre, lre + V::size_per_component(P.nf), f};
   const int c = blockIdx.y;
   const int rp = blockIdx.x * P.nf + f;
   const bool active = rp < P.ny / 2;
   const long r0 = long(2 * rp) * P.nx, r1 = r0 + P.nx;
-  const T a = P.a[c];
   const T ca = T(P.scal[kMeanA]), cb = T(P.scal[kMeanB]);
-  const bool pureA = (a == T(1)), pureB = (a == T(0));
-  const T* qin = P.q[c] + long(P.j - 1) * P.plane;
-  T re[N2], im[N2];
+  Twiddles<T, L, R> twf, twi;
+  load_fwd_twiddles(twf, j, P.tw_x);
+  load_inv_twiddles(twi, j, P.tw_x);
+  T g[R];
 #pragma unroll
-  for (int n2 = 0; n2 < N2; ++n2) {
-    T va = T(0), vb = T(0);
+  for (int m = 0; m < R; ++m) g[m] = P.mult_x[j + TL * m];
+  T* tmp = P.tmp + c * P.plane;
+  T re[R], im[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const int x = j + TL * m;
+    re[m] = T(0);
+    im[m] = T(0);
     if (active) {
-      const int x = lane + N1 * n2;
-      T ea, eb;
-      if (pureA) {
-        ea = exp(T(-0.5) * (P.wA[r0 + x] - ca));
-        eb = exp(T(-0.5) * (P.wA[r1 + x] - ca));
-      } else if (pureB) {
-        ea = exp(T(-0.5) * (P.wB[r0 + x] - cb));
-        eb = exp(T(-0.5) * (P.wB[r1 + x] - cb));
+      if (P.first) {
+        re[m] = efactor(P, P.frac[c][0], ca, cb, r0 + x);
+        im[m] = efactor(P, P.frac[c][0], ca, cb, r1 + x);
       } else {
-        ea = boltz(P.wA[r0 + x], P.wB[r0 + x], a, ca, cb);
-        eb = boltz(P.wA[r1 + x], P.wB[r1 + x], a, ca, cb);
-      }
-      if (P.j == 0) {
-        va = ea;
-        vb = eb;
-      } else {
-        va = ea * qin[r0 + x];
-        vb = eb * qin[r1 + x];
+        re[m] = tmp[r0 + x];
+        im[m] = tmp[r1 + x];
       }
     }
-    re[n2] = va;
-    im[n2] = vb;
   }
-  fft_forward<T, L>(re, im, f, lane, map, P.tw_x, lre, lim);
+  convolve(re, im, j, lds, twf, twi, g);
+  double qsum = 0.0;
+  if (P.mid) {
+    T* qo = P.q[c] + long(P.a) * P.plane;
 #pragma unroll
-  for (int m = 0; m < S::M; ++m)
-#pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) {
-      const T g = P.mult_x[freq_index<L>(lane, m, k1)];
-      re[m * N1 + k1] *= g;
-      im[m * N1 + k1] *= g;
+    for (int m = 0; m < R; ++m) {
+      const int x = j + TL * m;
+      if (active) {
+        re[m] *= efactor(P, P.frac[c][0], ca, cb, r0 + x);
+        im[m] *= efactor(P, P.frac[c][0], ca, cb, r1 + x);
+        qo[r0 + x] = re[m];
+        qo[r1 + x] = im[m];
+        qsum += double(re[m]) + double(im[m]);
+      }
     }
-  fft_inverse<T, L>(re, im, f, lane, map, P.tw_x, lre, lim);
-  if (active) {
-    T* out = P.tmp + c * P.plane;
+    if (P.second) {
 #pragma unroll
-    for (int n2 = 0; n2 < N2; ++n2) {
-      const int x = lane + N1 * n2;
-      out[r0 + x] = re[n2];
-      out[r1 + x] = im[n2];
+      for (int m = 0; m < R; ++m) {
+        const int x = j + TL * m;
+        if (active) {
+          re[m] *= efactor(P, P.frac[c][1], ca, cb, r0 + x);
+          im[m] *= efactor(P, P.frac[c][1], ca, cb, r1 + x);
+        }
+      }
+      convolve(re, im, j, lds, twf, twi, g);
     }
+  }
+  if ((!P.mid || P.second) && active) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int x = j + TL * m;
+      tmp[r0 + x] = re[m];
+      tmp[r1 + x] = im[m];
+    }
+  }
+  if (P.last) {
+    double v[1] = {qsum};
+    block_partial<1>(v, red, P.partials + c * gridDim.x, blockIdx.x);
   }
 }
 
-template <typename T, int L, int NF>
-__global__ void __launch_bounds__(256) k_prop_col(PropArgs<T> P) {
-  using S = Split<L>;
-  constexpr int N1 = S::N1, N2 = S::N2;
+// y-oriented kernel: columns 2cp and 2cp+1 packed as one complex column; NF
+// transforms per block interleaved lane by lane so that each global access
+// of a wavefront covers NF consecutive column pairs.
+template <typename T, int L, int R, int NF>
+__global__ void __launch_bounds__(512) k_prop_col(PropArgs<T> P) {
+  constexpr int TL = L / R;
+  using V = LdsView<T, L, R, false, NF>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16 * 1];
   T* lre = reinterpret_cast<T*>(smem_raw);
-  ColMap<L, NF> map;
-  T* lim = lre + ColMap<L, NF>::size();
-  const int f = threadIdx.x % NF, lane = threadIdx.x / NF;
+  const int f = threadIdx.x % NF, j = threadIdx.x / NF;
+  V lds{lre, lre + V::size_per_component(NF), f};
   const int c = blockIdx.y;
   const int cp = blockIdx.x * NF + f;
   const bool active = cp < P.nx / 2;
   const int x0 = 2 * cp;
-  const T2<T>* in = reinterpret_cast<const T2<T>*>(P.tmp + c * P.plane);
-  T re[N2], im[N2];
-#pragma unroll
-  for (int n2 = 0; n2 < N2; ++n2) {
-    const int y = lane + N1 * n2;
-    T2<T> v;
-    v.x = T(0);
-    v.y = T(0);
-    if (active) v = in[(long(y) * P.nx + x0) >> 1];
-    re[n2] = v.x;
-    im[n2] = v.y;
-  }
-  fft_forward<T, L>(re, im, f, lane, map, P.tw_y, lre, lim);
-#pragma unroll
-  for (int m = 0; m < S::M; ++m)
-#pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) {
-      const T g = P.mult_y[freq_index<L>(lane, m, k1)];
-      re[m * N1 + k1] *= g;
-      im[m * N1 + k1] *= g;
-    }
-  fft_inverse<T, L>(re, im, f, lane, map, P.tw_y, lre, lim);
-  const T a = P.a[c];
   const T ca = T(P.scal[kMeanA]), cb = T(P.scal[kMeanB]);
-  T2<T>* out = reinterpret_cast<T2<T>*>(P.q[c] + long(P.j) * P.plane);
-  double qsum = 0.0;
-  if (active) {
-    const T2<T>* wa2 = reinterpret_cast<const T2<T>*>(P.wA);
-    const T2<T>* wb2 = reinterpret_cast<const T2<T>*>(P.wB);
+  Twiddles<T, L, R> twf, twi;
+  load_fwd_twiddles(twf, j, P.tw_y);
+  load_inv_twiddles(twi, j, P.tw_y);
+  T g[R];
 #pragma unroll
-    for (int n2 = 0; n2 < N2; ++n2) {
-      const int y = lane + N1 * n2;
-      const long i2 = (long(y) * P.nx + x0) >> 1;
-      T ea, eb;
-      if (a == T(1)) {
-        const T2<T> w = wa2[i2];
-        ea = exp(T(-0.5) * (w.x - ca));
-        eb = exp(T(-0.5) * (w.y - ca));
-      } else if (a == T(0)) {
-        const T2<T> w = wb2[i2];
-        ea = exp(T(-0.5) * (w.x - cb));
-        eb = exp(T(-0.5) * (w.y - cb));
-      } else {
-        const T2<T> u = wa2[i2], w = wb2[i2];
-        ea = boltz(u.x, w.x, a, ca, cb);
-        eb = boltz(u.y, w.y, a, ca, cb);
-      }
-      T2<T> o;
-      o.x = re[n2] * ea;
-      o.y = im[n2] * eb;
-      out[i2] = o;
-      qsum += double(o.x) + double(o.y);
+  for (int m = 0; m < R; ++m) g[m] = P.mult_y[j + TL * m];
+  T2<T>* tmp2 = reinterpret_cast<T2<T>*>(P.tmp + c * P.plane);
+  T re[R], im[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const long i2 = (long(j + TL * m) * P.nx + x0) >> 1;
+    re[m] = T(0);
+    im[m] = T(0);
+    if (active) {
+      T2<T> v;
+      if (P.first) v = efactor2(P, P.frac[c][0], ca, cb, i2);
+      else v = tmp2[i2];
+      re[m] = v.x;
+      im[m] = v.y;
     }
   }
-  if (P.j == P.nsteps - 1) {
-    // Q_P = dA * sum_r q_N(r) for this chain (block-uniform branch)
+  convolve(re, im, j, lds, twf, twi, g);
+  double qsum = 0.0;
+  if (P.mid) {
+    T2<T>* qo = reinterpret_cast<T2<T>*>(P.q[c] + long(P.a) * P.plane);
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const long i2 = (long(j + TL * m) * P.nx + x0) >> 1;
+      if (active) {
+        const T2<T> e = efactor2(P, P.frac[c][0], ca, cb, i2);
+        re[m] *= e.x;
+        im[m] *= e.y;
+        T2<T> o;
+        o.x = re[m];
+        o.y = im[m];
+        qo[i2] = o;
+        qsum += double(o.x) + double(o.y);
+      }
+    }
+    if (P.second) {
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const long i2 = (long(j + TL * m) * P.nx + x0) >> 1;
+        if (active) {
+          const T2<T> e = efactor2(P, P.frac[c][1], ca, cb, i2);
+          re[m] *= e.x;
+          im[m] *= e.y;
+        }
+      }
+      convolve(re, im, j, lds, twf, twi, g);
+    }
+  }
+  if ((!P.mid || P.second) && active) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const long i2 = (long(j + TL * m) * P.nx + x0) >> 1;
+      T2<T> o;
+      o.x = re[m];
+      o.y = im[m];
+      tmp2[i2] = o;
+    }
+  }
+  if (P.last) {
     double v[1] = {qsum};
-    const int nslots = gridDim.x;
-    double res[1];
-    if (grid_sum<1>(v, red, P.partials + c * nslots, blockIdx.x, nslots, P.counter + c, res) &&
-        threadIdx.x == 0)
-      P.qout[c] = res[0] * P.dA;
+    block_partial<1>(v, red, P.partials + c * gridDim.x, blockIdx.x);
   }
 }
 
@@ -264,6 +334,10 @@ __global__ void __launch_bounds__(256) k_prop_col(PropArgs<T> P) {
 // Densities (contour integrals, solvent) and S = sum_I Phi_I/D_I - S~.
 // ---------------------------------------------------------------------------
 template <typename T> struct DensArgs {
+  const double* qpart;  // per-block sums of q_N from the last column pass, 2 chains
+  int nqpart;           // blocks per chain
+  double dA;
+  double* scal_out;     // scal: receives Q_P (both chains)
   const T* q[2];
   const T* wS;
   const T* stilde;
@@ -279,6 +353,28 @@ template <typename T> struct DensArgs {
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_density(DensArgs<T> P) {
+  __shared__ double red[16 * 2];
+  __shared__ double qp_s;
+  {
+    // Q_P from the column-pass partials, in fixed order (same in every block)
+    double acc[2];
+    double tmp[2] = {0.0, 0.0};
+    for (int s = threadIdx.x; s < P.nqpart; s += blockDim.x) {
+      tmp[0] += P.qpart[s];
+      tmp[1] += P.qpart[P.nqpart + s];
+    }
+    acc[0] = tmp[0];
+    acc[1] = tmp[1];
+    block_sum<2>(acc, red);
+    if (threadIdx.x == 0) {
+      qp_s = acc[0] * P.dA;
+      if (blockIdx.x == 0) {
+        P.scal_out[kQPf] = acc[0] * P.dA;
+        P.scal_out[kQPb] = acc[1] * P.dA;
+      }
+    }
+    __syncthreads();
+  }
   const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= P.n) return;
   const int N = P.N;
@@ -299,7 +395,7 @@ __global__ void __launch_bounds__(256) k_density(DensArgs<T> P) {
     sA += P.wnA[N] * prod;
     sB += P.wnB[N] * prod;
   }
-  const T cP = T(P.V * P.phiP / P.scal[kQPf]);
+  const T cP = T(P.V * P.phiP / qp_s);
   const T cS = T(P.V * P.phiSbar / P.scal[kQS]);
   const T pA = cP * sA, pB = cP * sB;
   const T pS = cS * exp(-(P.wS[i] - T(P.scal[kGaugeS])));
@@ -317,8 +413,6 @@ template <typename T> struct StatArgs {
   long n;
   double* scal;
   double* partials;
-  unsigned* counter;
-  double dA;
 };
 
 template <typename T>
@@ -333,14 +427,7 @@ __global__ void __launch_bounds__(256) k_field_stats(StatArgs<T> P) {
     v[2] += double(ws);
     v[3] += double(exp(-(ws - T(cS))));
   }
-  double res[4];
-  if (grid_sum<4>(v, red, P.partials, blockIdx.x, gridDim.x, P.counter, res) && threadIdx.x == 0) {
-    P.scal[kMeanA] = res[0] / double(P.n);
-    P.scal[kMeanB] = res[1] / double(P.n);
-    P.scal[kMeanS] = res[2] / double(P.n);
-    P.scal[kQS] = res[3] * P.dA;
-    P.scal[kGaugeS] = cS;
-  }
+  block_partial<4>(v, red, P.partials, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -357,9 +444,8 @@ template <typename T> struct UpdArgs {
   const T* u;      // 2 planes u^{n-1} (lattice units)
   T* wout;         // 3 planes omega^{n+1}
   T* stilde;       // sum_I Phi~_I / D_I
-  double* scal;
+  const double* scal;
   double* partials;
-  unsigned* counter;
   int nx, ny;
   long n;
   T chi[3][3];
@@ -367,7 +453,6 @@ template <typename T> struct UpdArgs {
   T coef[3];       // D_I dt / dx^2
   T invD[3];
   int advect;      // 0: no flow coupling
-  double dA;
 };
 
 template <typename T>
@@ -454,16 +539,7 @@ __global__ void __launch_bounds__(256) k_advect_update(UpdArgs<T> P) {
       if (I == 2) v[3] = double(exp(-(wn - cS)));
     }
   }
-  const int slot = blockIdx.y * gridDim.x + blockIdx.x;
-  const int nslots = gridDim.x * gridDim.y;
-  double res[4];
-  if (grid_sum<4>(v, red, P.partials, slot, nslots, P.counter, res) && threadIdx.x == 0) {
-    P.scal[kGaugeS] = double(cS);
-    P.scal[kMeanA] = res[0] / double(P.n);
-    P.scal[kMeanB] = res[1] / double(P.n);
-    P.scal[kMeanS] = res[2] / double(P.n);
-    P.scal[kQS] = res[3] * P.dA;
-  }
+  block_partial<4>(v, red, P.partials, blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -485,131 +561,131 @@ template <typename T> struct ForceArgs {
   int nf;
 };
 
-template <typename T, int L>
-__global__ void __launch_bounds__(256) k_force_row_fwd(ForceArgs<T> P) {
-  using S = Split<L>;
-  constexpr int N1 = S::N1, N2 = S::N2;
+template <typename T, int L, int R>
+__global__ void __launch_bounds__(512) k_force_row_fwd(ForceArgs<T> P) {
+  constexpr int TL = L / R;
+  using V = LdsView<T, L, R, true, 1>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lre = reinterpret_cast<T*>(smem_raw);
-  RowMap<L> map;
-  T* lim = lre + RowMap<L>::size(P.nf);
-  const int f = threadIdx.x / N1, lane = threadIdx.x % N1;
+  const int f = threadIdx.x / TL, j = threadIdx.x % TL;
+  V lds{lre, lre + V::size_per_component(P.nf), f};
   const int y = blockIdx.x * P.nf + f;
   const bool active = y < P.ny;
-  T re[N2], im[N2];
+  Twiddles<T, L, R> twf;
+  load_fwd_twiddles(twf, j, P.tw_x);
+  T re[R], im[R];
 #pragma unroll
-  for (int n2 = 0; n2 < N2; ++n2) {
-    re[n2] = active ? P.S[long(y) * P.nx + lane + N1 * n2] : T(0);
-    im[n2] = T(0);
+  for (int m = 0; m < R; ++m) {
+    re[m] = active ? P.S[long(y) * P.nx + j + TL * m] : T(0);
+    im[m] = T(0);
   }
-  fft_forward<T, L>(re, im, f, lane, map, P.tw_x, lre, lim);
+  fft_forward(re, im, j, lds, twf);
   if (active) {
 #pragma unroll
-    for (int m = 0; m < S::M; ++m)
-#pragma unroll
-      for (int k1 = 0; k1 < N1; ++k1) {
-        T2<T> o;
-        o.x = re[m * N1 + k1];
-        o.y = im[m * N1 + k1];
-        P.spec[long(y) * P.nx + freq_index<L>(lane, m, k1)] = o;
-      }
+    for (int m = 0; m < R; ++m) {
+      T2<T> o;
+      o.x = re[m];
+      o.y = im[m];
+      P.spec[long(y) * P.nx + j + TL * m] = o;
+    }
   }
 }
 
-template <typename T, int L, int NF>
-__global__ void __launch_bounds__(256) k_force_col(ForceArgs<T> P) {
-  using S = Split<L>;
-  constexpr int N1 = S::N1, N2 = S::N2;
+template <typename T, int L, int R, int NF>
+__global__ void __launch_bounds__(512) k_force_col(ForceArgs<T> P) {
+  constexpr int TL = L / R;
+  using V = LdsView<T, L, R, false, NF>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lre = reinterpret_cast<T*>(smem_raw);
-  ColMap<L, NF> map;
-  T* lim = lre + ColMap<L, NF>::size();
-  const int f = threadIdx.x % NF, lane = threadIdx.x / NF;
+  const int f = threadIdx.x % NF, j = threadIdx.x / NF;
+  V lds{lre, lre + V::size_per_component(NF), f};
   const int kxi = blockIdx.x * NF + f;   // column = x wavenumber index
   const bool active = kxi < P.nx;
-  T re[N2], im[N2];
+  Twiddles<T, L, R> twf, twi;
+  load_fwd_twiddles(twf, j, P.tw_y);
+  load_inv_twiddles(twi, j, P.tw_y);
+  T re[R], im[R];
 #pragma unroll
-  for (int n2 = 0; n2 < N2; ++n2) {
+  for (int m = 0; m < R; ++m) {
     T2<T> v;
     v.x = T(0);
     v.y = T(0);
-    if (active) v = P.spec[long(lane + N1 * n2) * P.nx + kxi];
-    re[n2] = v.x;
-    im[n2] = v.y;
+    if (active) v = P.spec[long(j + TL * m) * P.nx + kxi];
+    re[m] = v.x;
+    im[m] = v.y;
   }
-  fft_forward<T, L>(re, im, f, lane, map, P.tw_y, lre, lim);
+  fft_forward(re, im, j, lds, twf);
   const int mx = kxi < P.nx / 2 ? kxi : kxi - P.nx;
   const double kx = P.kx0 * mx;
   const bool nyq_x = (kxi == P.nx / 2);
 #pragma unroll
-  for (int m = 0; m < S::M; ++m)
-#pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) {
-      const int kyi = freq_index<L>(lane, m, k1);
-      const int my = kyi < P.ny / 2 ? kyi : kyi - P.ny;
-      const double ky = P.ky0 * my;
-      const double k2 = kx * kx + ky * ky;
-      const double inv = k2 > 0.0 ? P.pref / k2 : 0.0;
-      const T al = nyq_x ? T(0) : T(inv * kx);
-      const T be = (kyi == P.ny / 2) ? T(0) : T(inv * ky);
-      const T sr = re[m * N1 + k1], si = im[m * N1 + k1];
-      // G = i al S + i (i be S) = (i al - be) S
-      re[m * N1 + k1] = -al * si - be * sr;
-      im[m * N1 + k1] = al * sr - be * si;
-    }
-  fft_inverse<T, L>(re, im, f, lane, map, P.tw_y, lre, lim);
+  for (int m = 0; m < R; ++m) {
+    const int kyi = j + TL * m;
+    const int my = kyi < P.ny / 2 ? kyi : kyi - P.ny;
+    const double ky = P.ky0 * my;
+    const double k2 = kx * kx + ky * ky;
+    const double inv = k2 > 0.0 ? P.pref / k2 : 0.0;
+    const T al = nyq_x ? T(0) : T(inv * kx);
+    const T be = (kyi == P.ny / 2) ? T(0) : T(inv * ky);
+    const T sr = re[m], si = im[m];
+    // G = i al S + i (i be S) = (i al - be) S: real part f_x, imaginary part f_y
+    re[m] = -al * si - be * sr;
+    im[m] = al * sr - be * si;
+  }
+  fft_inverse(re, im, j, lds, twi);
   if (active) {
 #pragma unroll
-    for (int n2 = 0; n2 < N2; ++n2) {
+    for (int m = 0; m < R; ++m) {
       T2<T> o;
-      o.x = re[n2];
-      o.y = im[n2];
-      P.spec[long(lane + N1 * n2) * P.nx + kxi] = o;
+      o.x = re[m];
+      o.y = im[m];
+      P.spec[long(j + TL * m) * P.nx + kxi] = o;
     }
   }
 }
 
-template <typename T, int L>
-__global__ void __launch_bounds__(256) k_force_row_inv(ForceArgs<T> P) {
-  using S = Split<L>;
-  constexpr int N1 = S::N1, N2 = S::N2;
+template <typename T, int L, int R>
+__global__ void __launch_bounds__(512) k_force_row_inv(ForceArgs<T> P) {
+  constexpr int TL = L / R;
+  using V = LdsView<T, L, R, true, 1>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lre = reinterpret_cast<T*>(smem_raw);
-  RowMap<L> map;
-  T* lim = lre + RowMap<L>::size(P.nf);
-  const int f = threadIdx.x / N1, lane = threadIdx.x % N1;
+  const int f = threadIdx.x / TL, j = threadIdx.x % TL;
+  V lds{lre, lre + V::size_per_component(P.nf), f};
   const int y = blockIdx.x * P.nf + f;
   const bool active = y < P.ny;
-  T re[N2], im[N2];
+  Twiddles<T, L, R> twi;
+  load_inv_twiddles(twi, j, P.tw_x);
+  T re[R], im[R];
 #pragma unroll
-  for (int m = 0; m < S::M; ++m)
-#pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) {
-      T2<T> v;
-      v.x = T(0);
-      v.y = T(0);
-      if (active) v = P.spec[long(y) * P.nx + freq_index<L>(lane, m, k1)];
-      re[m * N1 + k1] = v.x;
-      im[m * N1 + k1] = v.y;
-    }
-  fft_inverse<T, L>(re, im, f, lane, map, P.tw_x, lre, lim);
+  for (int m = 0; m < R; ++m) {
+    T2<T> v;
+    v.x = T(0);
+    v.y = T(0);
+    if (active) v = P.spec[long(y) * P.nx + j + TL * m];
+    re[m] = v.x;
+    im[m] = v.y;
+  }
+  fft_inverse(re, im, j, lds, twi);
   if (active) {
     const T conv = T(P.conv);
     const T fext = T(y < P.ny / 2 ? -P.gext : P.gext);
 #pragma unroll
-    for (int n2 = 0; n2 < N2; ++n2) {
-      const long i = long(y) * P.nx + lane + N1 * n2;
-      P.F[i] = re[n2] * conv + fext;
-      P.F[P.n + i] = im[n2] * conv;
+    for (int m = 0; m < R; ++m) {
+      const long i = long(y) * P.nx + j + TL * m;
+      P.F[i] = re[m] * conv + fext;
+      P.F[P.n + i] = im[m] * conv;
     }
   }
 }
 
 // ---------------------------------------------------------------------------
 // D2Q9 lattice Boltzmann: pull stream + BGK collision with second-order force.
+// Populations are stored as deviations g_i = f_i - w_i from the rest state
+// (rho = 1, u = 0) so that FP32 keeps the small momentum of slow flows.
 // ---------------------------------------------------------------------------
 template <typename T> struct LbArgs {
-  const T* fin;    // 9 planes f* (previous post-collision)
+  const T* fin;    // 9 planes g* = f* - w (previous post-collision)
   T* fout;         // 9 planes
   const T* F;      // 2 planes
   T* rho;
@@ -630,20 +706,22 @@ __global__ void __launch_bounds__(256) k_lb(LbArgs<T> P) {
   const long ym = long((y - 1) & (P.ny - 1)) * P.nx, yp = long((y + 1) & (P.ny - 1)) * P.nx;
   const long yc = long(y) * P.nx;
   // pull: f_i(x) = f*_i(x - c_i); c = (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1)
-  T f[9];
-  f[0] = P.fin[0 * P.n + yc + x];
-  f[1] = P.fin[1 * P.n + yc + xm];
-  f[2] = P.fin[2 * P.n + ym + x];
-  f[3] = P.fin[3 * P.n + yc + xp];
-  f[4] = P.fin[4 * P.n + yp + x];
-  f[5] = P.fin[5 * P.n + ym + xm];
-  f[6] = P.fin[6 * P.n + ym + xp];
-  f[7] = P.fin[7 * P.n + yp + xp];
-  f[8] = P.fin[8 * P.n + yp + xm];
+  T g[9];
+  g[0] = P.fin[0 * P.n + yc + x];
+  g[1] = P.fin[1 * P.n + yc + xm];
+  g[2] = P.fin[2 * P.n + ym + x];
+  g[3] = P.fin[3 * P.n + yc + xp];
+  g[4] = P.fin[4 * P.n + yp + x];
+  g[5] = P.fin[5 * P.n + ym + xm];
+  g[6] = P.fin[6 * P.n + ym + xp];
+  g[7] = P.fin[7 * P.n + yp + xp];
+  g[8] = P.fin[8 * P.n + yp + xm];
   const T Fx = P.F[i], Fy = P.F[P.n + i];
-  const T rho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-  const T jx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
-  const T jy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
+  // sum_i w_i = 1 and sum_i w_i c_i = 0, so the deviations carry rho - 1 and the momentum
+  const T drho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+  const T rho = T(1) + drho;
+  const T jx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
+  const T jy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
   const T ir = T(1) / rho;
   const T ux = (jx + T(0.5) * Fx) * ir;
   const T uy = (jy + T(0.5) * Fy) * ir;
@@ -654,11 +732,12 @@ __global__ void __launch_bounds__(256) k_lb(LbArgs<T> P) {
   for (int k = 0; k < 9; ++k) {
     const T w = k == 0 ? T(4.0 / 9.0) : (k < 5 ? T(1.0 / 9.0) : T(1.0 / 36.0));
     const T cu = T(cx[k]) * ux + T(cy[k]) * uy;
-    const T feq = w * rho * (T(1) + T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
+    // f^eq - w = w (rho - 1) + w rho (3 c.u + 4.5 (c.u)^2 - 1.5 u^2)
+    const T geq = w * drho + w * rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
     const T cF = T(cx[k]) * Fx + T(cy[k]) * Fy;
     const T cmuF = (T(cx[k]) - ux) * Fx + (T(cy[k]) - uy) * Fy;
     const T src = w * (T(3) * cmuF + T(9) * cu * cF);
-    P.fout[k * P.n + i] = f[k] - (f[k] - feq) * P.omega + P.fpre * src;
+    P.fout[k * P.n + i] = g[k] - (g[k] - geq) * P.omega + P.fpre * src;
   }
   P.rho[i] = rho;
   P.u[i] = ux;
