@@ -6,10 +6,12 @@ chi reading L, g = 1e-5 f*, seeded Gaussian noise sigma = 1e-3 (seed 1003).
 A "step" is one full hybrid step (advection + EPD update, both chain
 propagators, densities, force reconstruction, D2Q9 LB) on the resident state.
 
-Prints ONE JSON line.  `roofline` covers the kernel family with the largest
-share of GPU time, timed with HIP events on the library's stream over the
-first launches of the timed region; `cpu_baseline` is the FP64 NumPy oracle
-on a bounded sample of the same workload on the host.
+Prints ONE JSON line.  `value` is timed with events around K graph-replayed
+steps.  `roofline` covers the kernel family with the largest share of GPU
+time; its kernel durations come from HIP start/stop events that each launch
+records at the kernel's own start and end (stream launches of the same
+workload right after the timed region).  `cpu_baseline` is the FP64 NumPy
+oracle on a bounded sample of the same workload on the host.
 """
 import argparse
 import json
@@ -21,23 +23,47 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "lattice site-updates/s per hybrid step, plain vs surrogate at <=1e-3 density err"
+
+# HBM traffic of the dominant kernel measured with rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE (one counter per run), scaled by the same counters' readings for a
+# plain 256 MiB copy (FETCH x2.0, WRITE x1.0); see profiles/prop_col_cfg3_traffic.md.
+# Valid only while the kernel sources hash to `source_sha256`.
+MEASURED_TRAFFIC = {
+    ("cfg3", "prop_col"): dict(bytes_per_launch=17291173, source_sha256="473bfc94ccdeb072a69fd59b0ea1ec85b6a01dfb68370ac9eb365a3cbbd0c151"),
+}
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes per site per launch of each kernel family, in units of the
-# element size P (forward and backward chains counted together):
-#   prop_row / prop_col : 2 chains x (read P + write P)            = 4P
-#   density             : read 2(N+1) chain planes, write 3 + S   = 2(N+1)P + 4P
-#   advect_update       : read Phi 3, omega 3, u 2; write omega 3, S~ 1 = 12P
-#   force (3 passes)    : 11P in total
-#   lb                  : read 9 + F 2, write 9 + rho + u 2        = 23P
-def bytes_per_site(kind, N, P):
+# Algorithmic bytes per site per hybrid STEP of each kernel family, in units
+# of the element size P (forward and backward chains counted together):
+#   advect_update : read Phi 3, omega 3, u 2; write omega 3, S~ 1        = 12P
+#   boltzmann     : read omega_A, omega_B; write their half-step factors =  4P
+#   prop_row/col  : per chain, the first launch reads a factor plane and
+#                   writes the scratch plane (2P); a fused boundary launch
+#                   reads scratch + factor and writes q_{a+1} + scratch (4P);
+#                   the last reads scratch + factor and writes q_N (3P)
+#   density       : read 2N chain planes + omega_S + S~, write Phi 3 + S = (2N + 6)P
+#   force_*       : 3P + 4P + 4P (row FFT of S, column pass, row inverse)
+#   lb            : read 9 populations + F 2; write 9 + rho + u 2        = 23P
+def step_bytes_per_site(kind, N, P):
+    last_row = (N - 1) % 2 == 1           # the final propagator launch is x-oriented
+    n_fused_row = sum(1 for s in range(N - 1) if s % 2 == 1)
+    n_fused_col = sum(1 for s in range(N - 1) if s % 2 == 0)
+    per_chain_row = 2 + 4 * n_fused_row + (3 if last_row else 0)
+    per_chain_col = 4 * n_fused_col + (0 if last_row else 3)
     return {
-        "prop_row": 4 * P, "prop_col": 4 * P,
-        "density": (2 * (N + 1) + 4) * P,
-        "advect_update": 12 * P,
+        "advect_update": 12 * P, "boltzmann": 4 * P,
+        "prop_row": 2 * per_chain_row * P, "prop_col": 2 * per_chain_col * P,
+        "density": (2 * N + 6) * P,
         "force_row_fwd": 3 * P, "force_col": 4 * P, "force_row_inv": 4 * P,
         "lb": 23 * P,
     }.get(kind)
+
+
+def kernel_source_sha256():
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1804_02883_amd", "csrc")
+    data = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("fft.hpp", "kernels.hpp"))
+    return hashlib.sha256(data).hexdigest()
 
 
 def cpu_baseline(preset_name, steps):
@@ -68,7 +94,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--tune-cache", default=None)
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1804_02883_amd", "tune", "gfx950.txt"),
+                    help="autotuner results file (read first, new results appended)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -101,25 +128,35 @@ def main():
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
     sim.sync()
-    # per-kernel event timing (stream launches, after the timed region)
-    sim.profile_start(args.profile_launches)
-    sim.step(max(1, args.profile_launches // (2 * N + 8)))
+    # per-kernel durations: HIP start/stop events recorded by each kernel launch
+    # itself (stream launches of the same workload, right after the timed region)
+    prof_steps = max(1, min(50, args.profile_launches // (N + 9)))
+    sim.profile_start(prof_steps * (N + 9) + 16)
+    sim.step(prof_steps)
     prof = sim.profile_read()
     ms_per_step = ms / args.steps
     value = n * args.steps / (ms / 1e3)
 
-    # dominant kernel family by recorded GPU time
-    fam = max((k for k in prof if bytes_per_site(k, N, P) is not None), key=lambda k: prof[k]["total_ms"])
-    avg_s = prof[fam]["avg_ms"] / 1e3
-    alg_bytes = bytes_per_site(fam, N, P) * n
-    achieved = alg_bytes / avg_s / 1e9
+    # dominant kernel family by GPU time; achieved = its algorithmic bytes over
+    # the profiled steps / its summed kernel durations
+    fams = [k for k in prof if step_bytes_per_site(k, N, P) is not None]
+    fam = max(fams, key=lambda k: prof[k]["total_ms"])
+    alg_bytes = step_bytes_per_site(fam, N, P) * n * prof_steps
+    achieved = alg_bytes / (prof[fam]["total_ms"] / 1e3) / 1e9
+    tr = MEASURED_TRAFFIC.get((args.workload, fam))
+    traffic = tr["bytes_per_launch"] if tr and tr["source_sha256"] == kernel_source_sha256() else None
     roofline = dict(bound="hbm", kernel=fam, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                     avg_launch_us=round(prof[fam]["avg_ms"] * 1e3, 3),
-                    alg_bytes_per_launch=alg_bytes)
-    breakdown = {k: dict(launches=v["launches"], avg_us=round(v["avg_ms"] * 1e3, 3),
-                         share=round(v["total_ms"] / max(sum(x["total_ms"] for x in prof.values()), 1e-30), 4))
+                    launches_per_step=prof[fam]["launches"] // prof_steps,
+                    alg_bytes_per_launch=int(alg_bytes / prof[fam]["launches"]))
+    tot = sum(x["total_ms"] for x in prof.values())
+    breakdown = {k: dict(launches_per_step=v["launches"] / prof_steps, avg_us=round(v["avg_ms"] * 1e3, 3),
+                         share=round(v["total_ms"] / tot, 4),
+                         gbs=(round(step_bytes_per_site(k, N, P) * n * prof_steps / (v["total_ms"] / 1e3) / 1e9, 1)
+                              if step_bytes_per_site(k, N, P) else None))
                  for k, v in prof.items()}
+    breakdown["kernel_sum_us_per_step"] = round(1e3 * tot / prof_steps, 2)
     d = sim.diag()
     sim.close()
 

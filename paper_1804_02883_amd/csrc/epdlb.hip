@@ -1,4 +1,5 @@
 // Host runtime and C ABI of libepdlb.so (see include/epdlb.h).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -54,7 +55,7 @@ double unit_open0(uint64_t bits) { return (double((bits >> 11)) + 1.0) * 0x1.0p-
 // Device arena layout (all offsets 256-byte aligned).
 // ---------------------------------------------------------------------------
 struct Layout {
-  size_t omega[2], phi, stilde, S, q[2], tmp, spec, F, fstar[2], rho, u;
+  size_t omega[2], phi, stilde, S, q[2], tmp, spec, F, fstar[2], rho, u, boltz;
   size_t mult_x, mult_y, tw_x, tw_y, wnA, wnB, scal, partials, counters;
   size_t total;
   size_t n_partials;
@@ -88,6 +89,7 @@ Layout make_layout(const epdlb_params& p) {
   L.fstar[1] = take(9 * plane);
   L.rho = take(plane);
   L.u = take(2 * plane);
+  L.boltz = take(2 * plane);
   L.mult_x = take(size_t(p.nx) * es);
   L.mult_y = take(size_t(p.ny) * es);
   L.tw_x = take(size_t(p.nx) * 2 * es);
@@ -143,24 +145,46 @@ struct epdlb_ctx {
 
 namespace {
 
-enum Kind { K_STATS, K_ADVECT, K_FINISH, K_PROP_ROW, K_PROP_COL, K_DENSITY, K_FROW_FWD, K_FCOL, K_FROW_INV,
-            K_LB, K_NUM };
-const char* const kKindName[K_NUM] = {"field_stats",   "advect_update", "finish_stats", "prop_row",
-                                      "prop_col",      "density",       "force_row_fwd", "force_col",
-                                      "force_row_inv", "lb"};
+enum Kind { K_STATS, K_ADVECT, K_FINISH, K_BOLTZ, K_PROP_ROW, K_PROP_COL, K_DENSITY, K_FROW_FWD, K_FCOL,
+            K_FROW_INV, K_LB, K_NUM };
+const char* const kKindName[K_NUM] = {"field_stats", "advect_update", "finish_stats",  "boltzmann",
+                                      "prop_row",    "prop_col",      "density",       "force_row_fwd",
+                                      "force_col",   "force_row_inv", "lb"};
 
-// Event pair around one launch while the profiler has room; never blocks.
+// Profiling: while the profiler has room, the next kernel launch records a
+// start/stop event pair at the kernel's own start and end (AMD's extended
+// launch), so the times are kernel durations even when the host is slower
+// than the GPU.  Recording never blocks.
+thread_local hipEvent_t tl_ev_start = nullptr;
+thread_local hipEvent_t tl_ev_stop = nullptr;
+
+template <typename F, typename... Args>
+void launch_k(F kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, Args... args) {
+  if (tl_ev_start) {
+    hipExtLaunchKernelGGL(kernel, grid, block, uint32_t(lds), s, tl_ev_start, tl_ev_stop, 0u, args...);
+    tl_ev_start = tl_ev_stop = nullptr;  // one launch per armed pair
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+  }
+}
+
 struct ProfScope {
   epdlb_ctx* c;
   int kind;
   bool rec;
   ProfScope(epdlb_ctx* ctx, int k) : c(ctx), kind(k) {
     rec = c->prof_on && size_t(2 * c->prof_used + 1) < c->prof_ev.size();
-    if (rec) (void)hipEventRecord(c->prof_ev[2 * c->prof_used], c->stream);
+    if (rec) {
+      tl_ev_start = c->prof_ev[2 * c->prof_used];
+      tl_ev_stop = c->prof_ev[2 * c->prof_used + 1];
+    }
   }
   ~ProfScope() {
     if (!rec) return;
-    (void)hipEventRecord(c->prof_ev[2 * c->prof_used + 1], c->stream);
+    if (tl_ev_start) {  // armed but not consumed: nothing recorded
+      tl_ev_start = tl_ev_stop = nullptr;
+      return;
+    }
     c->prof_kind[c->prof_used] = kind;
     ++c->prof_used;
   }
@@ -203,36 +227,42 @@ hipError_t prep_lds(K kernel, size_t bytes) {
 
 template <typename T, int L, int R>
 constexpr bool fft_ok() {
-  return (R == 8 || (R == 16 && sizeof(T) == 4)) && L >= R;
+  return (R == 8 || ((R == 16 || R == 4 || R == 2) && sizeof(T) == 4)) && L >= R;
 }
+constexpr int kMaxColThreads = 1024;
 
 template <typename T, int L, int R>
 hipError_t launch_prop_row_r(const PropArgs<T>& a, hipStream_t s) {
   if constexpr (fft_ok<T, L, R>()) {
     using V = LdsView<T, L, R, true, 1>;
-    const size_t lds = 2 * size_t(V::size_per_component(a.nf)) * sizeof(T);
+    const size_t lds = 2 * size_t(V::size_elems(a.nf)) * sizeof(T);
     hipError_t e = prep_lds(k_prop_row<T, L, R>, lds);
     if (e != hipSuccess) return e;
     const int tiles = (a.ny / 2 + a.nf - 1) / a.nf;
-    hipLaunchKernelGGL((k_prop_row<T, L, R>), dim3(tiles, 2), dim3(a.nf * (L / R)), lds, s, a);
+    launch_k((k_prop_row<T, L, R>), dim3(tiles, 2), dim3(a.nf * (L / R)), lds, s, a);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;
 }
 template <typename T, int L>
 hipError_t launch_prop_row(const PropArgs<T>& a, int R, hipStream_t s) {
-  return R == 16 ? launch_prop_row_r<T, L, 16>(a, s) : launch_prop_row_r<T, L, 8>(a, s);
+  switch (R) {
+    case 16: return launch_prop_row_r<T, L, 16>(a, s);
+    case 4: return launch_prop_row_r<T, L, 4>(a, s);
+    case 2: return launch_prop_row_r<T, L, 2>(a, s);
+  }
+  return launch_prop_row_r<T, L, 8>(a, s);
 }
 
 template <typename T, int L, int R, int NF>
 hipError_t launch_prop_col_rn(const PropArgs<T>& a, hipStream_t s) {
-  if constexpr (fft_ok<T, L, R>() && NF * (L / R) <= 512 && (sizeof(T) == 4 || NF == 4)) {
+  if constexpr (fft_ok<T, L, R>() && NF * (L / R) <= kMaxColThreads && (sizeof(T) == 4 || NF == 4)) {
     using V = LdsView<T, L, R, false, NF>;
-    const size_t lds = 2 * size_t(V::size_per_component(NF)) * sizeof(T);
+    const size_t lds = 2 * size_t(V::size_elems(NF)) * sizeof(T);
     hipError_t e = prep_lds(k_prop_col<T, L, R, NF>, lds);
     if (e != hipSuccess) return e;
     const int tiles = (a.nx / 2 + NF - 1) / NF;
-    hipLaunchKernelGGL((k_prop_col<T, L, R, NF>), dim3(tiles, 2), dim3(NF * (L / R)), lds, s, a);
+    launch_k((k_prop_col<T, L, R, NF>), dim3(tiles, 2), dim3(NF * (L / R)), lds, s, a);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;
@@ -248,17 +278,22 @@ hipError_t launch_prop_col_r(const PropArgs<T>& a, hipStream_t s) {
 }
 template <typename T, int L>
 hipError_t launch_prop_col(const PropArgs<T>& a, int R, hipStream_t s) {
-  return R == 16 ? launch_prop_col_r<T, L, 16>(a, s) : launch_prop_col_r<T, L, 8>(a, s);
+  switch (R) {
+    case 16: return launch_prop_col_r<T, L, 16>(a, s);
+    case 4: return launch_prop_col_r<T, L, 4>(a, s);
+    case 2: return launch_prop_col_r<T, L, 2>(a, s);
+  }
+  return launch_prop_col_r<T, L, 8>(a, s);
 }
 
 template <typename T, int L, int R>
 hipError_t launch_force_row_fwd_r(const ForceArgs<T>& a, hipStream_t s) {
   if constexpr (fft_ok<T, L, R>()) {
     using V = LdsView<T, L, R, true, 1>;
-    const size_t lds = 2 * size_t(V::size_per_component(a.nf)) * sizeof(T);
+    const size_t lds = 2 * size_t(V::size_elems(a.nf)) * sizeof(T);
     hipError_t e = prep_lds(k_force_row_fwd<T, L, R>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_force_row_fwd<T, L, R>), dim3((a.ny + a.nf - 1) / a.nf), dim3(a.nf * (L / R)),
+    launch_k((k_force_row_fwd<T, L, R>), dim3((a.ny + a.nf - 1) / a.nf), dim3(a.nf * (L / R)),
                        lds, s, a);
     return hipGetLastError();
   }
@@ -266,16 +301,21 @@ hipError_t launch_force_row_fwd_r(const ForceArgs<T>& a, hipStream_t s) {
 }
 template <typename T, int L>
 hipError_t launch_force_row_fwd(const ForceArgs<T>& a, int R, hipStream_t s) {
-  return R == 16 ? launch_force_row_fwd_r<T, L, 16>(a, s) : launch_force_row_fwd_r<T, L, 8>(a, s);
+  switch (R) {
+    case 16: return launch_force_row_fwd_r<T, L, 16>(a, s);
+    case 4: return launch_force_row_fwd_r<T, L, 4>(a, s);
+    case 2: return launch_force_row_fwd_r<T, L, 2>(a, s);
+  }
+  return launch_force_row_fwd_r<T, L, 8>(a, s);
 }
 template <typename T, int L, int R>
 hipError_t launch_force_row_inv_r(const ForceArgs<T>& a, hipStream_t s) {
   if constexpr (fft_ok<T, L, R>()) {
     using V = LdsView<T, L, R, true, 1>;
-    const size_t lds = 2 * size_t(V::size_per_component(a.nf)) * sizeof(T);
+    const size_t lds = 2 * size_t(V::size_elems(a.nf)) * sizeof(T);
     hipError_t e = prep_lds(k_force_row_inv<T, L, R>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_force_row_inv<T, L, R>), dim3((a.ny + a.nf - 1) / a.nf), dim3(a.nf * (L / R)),
+    launch_k((k_force_row_inv<T, L, R>), dim3((a.ny + a.nf - 1) / a.nf), dim3(a.nf * (L / R)),
                        lds, s, a);
     return hipGetLastError();
   }
@@ -283,16 +323,21 @@ hipError_t launch_force_row_inv_r(const ForceArgs<T>& a, hipStream_t s) {
 }
 template <typename T, int L>
 hipError_t launch_force_row_inv(const ForceArgs<T>& a, int R, hipStream_t s) {
-  return R == 16 ? launch_force_row_inv_r<T, L, 16>(a, s) : launch_force_row_inv_r<T, L, 8>(a, s);
+  switch (R) {
+    case 16: return launch_force_row_inv_r<T, L, 16>(a, s);
+    case 4: return launch_force_row_inv_r<T, L, 4>(a, s);
+    case 2: return launch_force_row_inv_r<T, L, 2>(a, s);
+  }
+  return launch_force_row_inv_r<T, L, 8>(a, s);
 }
 template <typename T, int L, int R, int NF>
 hipError_t launch_force_col_rn(const ForceArgs<T>& a, hipStream_t s) {
-  if constexpr (fft_ok<T, L, R>() && NF * (L / R) <= 512 && (sizeof(T) == 4 || NF == 4)) {
+  if constexpr (fft_ok<T, L, R>() && NF * (L / R) <= kMaxColThreads && (sizeof(T) == 4 || NF == 4)) {
     using V = LdsView<T, L, R, false, NF>;
-    const size_t lds = 2 * size_t(V::size_per_component(NF)) * sizeof(T);
+    const size_t lds = 2 * size_t(V::size_elems(NF)) * sizeof(T);
     hipError_t e = prep_lds(k_force_col<T, L, R, NF>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_force_col<T, L, R, NF>), dim3((a.nx + NF - 1) / NF), dim3(NF * (L / R)), lds, s,
+    launch_k((k_force_col<T, L, R, NF>), dim3((a.nx + NF - 1) / NF), dim3(NF * (L / R)), lds, s,
                        a);
     return hipGetLastError();
   }
@@ -309,7 +354,12 @@ hipError_t launch_force_col_r(const ForceArgs<T>& a, hipStream_t s) {
 }
 template <typename T, int L>
 hipError_t launch_force_col(const ForceArgs<T>& a, int R, hipStream_t s) {
-  return R == 16 ? launch_force_col_r<T, L, 16>(a, s) : launch_force_col_r<T, L, 8>(a, s);
+  switch (R) {
+    case 16: return launch_force_col_r<T, L, 16>(a, s);
+    case 4: return launch_force_col_r<T, L, 4>(a, s);
+    case 2: return launch_force_col_r<T, L, 2>(a, s);
+  }
+  return launch_force_col_r<T, L, 8>(a, s);
 }
 
 #define EPDLB_SWITCH_L(L, FN, T, ...)                 \
@@ -353,9 +403,9 @@ int stage_stats(epdlb_ctx* c) {
   a.partials = c->ptr<double>(c->L.partials);
   const int blocks = int(std::min<long>(1024, (n + 255) / 256));
   ProfScope ps(c, K_STATS);
-  hipLaunchKernelGGL((k_field_stats<T>), dim3(blocks), dim3(256), 0, c->stream, a);
+  launch_k((k_field_stats<T>), dim3(blocks), dim3(256), 0, c->stream, a);
   HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL(k_finish_stats, dim3(1), dim3(256), 0, c->stream, a.partials, blocks, a.scal, n,
+  launch_k(k_finish_stats, dim3(1), dim3(256), 0, c->stream, a.partials, blocks, a.scal, n,
                      c->p.dx * c->p.dx);
   HIPCHK(hipGetLastError());
   return EPDLB_OK;
@@ -388,12 +438,12 @@ int stage_advect_update(epdlb_ctx* c) {
   a.advect = p.couple_lb ? 1 : 0;
   {
     ProfScope ps(c, K_ADVECT);
-    hipLaunchKernelGGL((k_advect_update<T>), dim3(p.nx / kTX, p.ny / kTY), dim3(kTX * kTY), 0, c->stream, a);
+    launch_k((k_advect_update<T>), dim3(p.nx / kTX, p.ny / kTY), dim3(kTX * kTY), 0, c->stream, a);
   }
   HIPCHK(hipGetLastError());
   {
     ProfScope ps(c, K_FINISH);
-    hipLaunchKernelGGL(k_finish_stats, dim3(1), dim3(256), 0, c->stream, a.partials,
+    launch_k(k_finish_stats, dim3(1), dim3(256), 0, c->stream, a.partials,
                        (p.nx / kTX) * (p.ny / kTY), c->ptr<double>(c->L.scal), n, p.dx * p.dx);
   }
   HIPCHK(hipGetLastError());
@@ -408,6 +458,8 @@ PropArgs<T> make_prop_args(epdlb_ctx* c) {
   PropArgs<T> a;
   a.wA = c->ptr<T>(c->L.omega[c->cur]);
   a.wB = a.wA + n;
+  a.EA = c->ptr<T>(c->L.boltz);
+  a.EB = a.EA + n;
   a.scal = c->ptr<double>(c->L.scal);
   a.q[0] = c->ptr<T>(c->L.q[0]);
   a.q[1] = c->ptr<T>(c->L.q[1]);
@@ -433,6 +485,12 @@ int stage_densities(epdlb_ctx* c, bool with_S) {
   const int N = p.n_contour;
   const long n = long(p.nx) * p.ny;
   PropArgs<T> a = make_prop_args<T>(c);
+  {
+    ProfScope ps(c, K_BOLTZ);
+    launch_k((k_boltzmann<T>), dim3((n + 255) / 256), dim3(256), 0, c->stream, a.wA,
+                       c->ptr<T>(c->L.boltz), a.scal, n);
+  }
+  HIPCHK(hipGetLastError());
   auto seg = [&](int chain, int step) { return T(c->seg_a[chain == 0 ? step : N - 1 - step]); };
   auto launch = [&](bool row) -> int {
     if (row) {
@@ -492,7 +550,7 @@ int stage_densities(epdlb_ctx* c, bool with_S) {
   d.invDS = 1.0 / p.D_S;
   {
     ProfScope ps(c, K_DENSITY);
-    hipLaunchKernelGGL((k_density<T>), dim3((n + 255) / 256), dim3(256), 0, c->stream, d);
+    launch_k((k_density<T>), dim3((n + 255) / 256), dim3(256), 0, c->stream, d);
   }
   HIPCHK(hipGetLastError());
   return EPDLB_OK;
@@ -558,7 +616,7 @@ int stage_lb(epdlb_ctx* c) {
   a.fpre = T(1.0 - 0.5 / p.lb_tau);
   {
     ProfScope ps(c, K_LB);
-    hipLaunchKernelGGL((k_lb<T>), dim3((n + 255) / 256), dim3(256), 0, c->stream, a);
+    launch_k((k_lb<T>), dim3((n + 255) / 256), dim3(256), 0, c->stream, a);
   }
   HIPCHK(hipGetLastError());
   c->fcur = 1 - c->fcur;
@@ -1168,11 +1226,11 @@ int epdlb_autotune(epdlb_ctx* c, int32_t reps, const char* cache_path) {
     const int transforms = fam == F_PROP_ROW ? c->p.ny / 2 : c->p.ny;
     double best = 1e30;
     epdlb_ctx::Shape best_sh = family_shape(c, fam);
-    const int Rs[2] = {8, 16};
+    const int Rs[4] = {2, 4, 8, 16};
     for (int R : Rs) {
-      if (R == 16 && !fp32) continue;
+      if (R != 8 && !fp32) continue;
       if (row) {
-        for (int nf = 1; nf * (L / R) <= 256 && nf <= transforms; nf *= 2) {
+        for (int nf = 1; nf * (L / R) <= 512 && nf <= transforms; nf *= 2) {
           const double us = time_candidate(c, fam, R, nf, reps);
           if (verbose) std::fprintf(stderr, "[tune] %s R=%d nf=%d: %.3f us\n", kFamilyName[fam], R, nf, us);
           if (us > 0 && us < best) best = us, best_sh = {R, nf};

@@ -140,21 +140,22 @@ template <int L, int R> struct Plan {
   __device__ static __forceinline__ int skew(int i) { return i + (i >> 6); }
 };
 
-// LDS view of one transform: element i of the real / imaginary component.
-//  * CONTIG:      transform f occupies [f*LP, (f+1)*LP) of each component
+// LDS view of one transform: complex element i (real and imaginary part
+// side by side, one 64-/128-bit access each).
+//  * CONTIG:      transform f occupies [f*LP, (f+1)*LP)
 //  * interleaved: transforms are the fastest index (f + NF*skew(i)), so that
 //                 lanes of one wavefront holding different transforms hit
 //                 consecutive banks
 template <typename T, int L, int R, bool CONTIG, int NF>
 struct LdsView {
-  T* re;
-  T* im;
+  T2<T>* buf;
   int f;
   __device__ __forceinline__ int at(int i) const {
     if constexpr (CONTIG) return f * Plan<L, R>::LP + Plan<L, R>::skew(i);
     else return f + NF * Plan<L, R>::skew(i);
   }
-  __host__ __device__ static constexpr int size_per_component(int nf) {
+  // complex elements needed for nf transforms
+  __host__ __device__ static constexpr int size_elems(int nf) {
     return CONTIG ? Plan<L, R>::LP * nf : NF * Plan<L, R>::LP;
   }
 };
@@ -178,9 +179,9 @@ __device__ __forceinline__ void stockham_pass(T* re, T* im, int j, const V& lds,
         vr[s * r + q] = re[s + q * SUB];
         vi[s * r + q] = im[s + q * SUB];
       } else {
-        const int a = lds.at(jj + q * (L / r));
-        vr[s * r + q] = lds.re[a];
-        vi[s * r + q] = lds.im[a];
+        const T2<T> v = lds.buf[lds.at(jj + q * (L / r))];
+        vr[s * r + q] = v.x;
+        vi[s * r + q] = v.y;
       }
     }
     if constexpr (Ns > 1) {
@@ -226,9 +227,10 @@ __device__ __forceinline__ void stockham_pass(T* re, T* im, int j, const V& lds,
       const int base = (jj / Ns) * Ns * r + (jj & (Ns - 1));
 #pragma unroll
       for (int q = 0; q < r; ++q) {
-        const int a = lds.at(base + q * Ns);
-        lds.re[a] = vr[s * r + q];
-        lds.im[a] = vi[s * r + q];
+        T2<T> v;
+        v.x = vr[s * r + q];
+        v.y = vi[s * r + q];
+        lds.buf[lds.at(base + q * Ns)] = v;
       }
     }
     __syncthreads();

@@ -19,6 +19,18 @@ enum Scal : int {
 };
 
 // ---------------------------------------------------------------------------
+// XCD-aware tile order.  Workgroups are handed to the 8 XCDs of an MI355X
+// round-robin by linear id, and each XCD has its own L2.  Remapping so that
+// XCD k processes the k-th contiguous range of logical tiles keeps
+// neighbouring tiles (which share cache lines and halos) in one L2.
+// ---------------------------------------------------------------------------
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ int xcd_tile(int linear, int total) {
+  if (total % kNumXcd) return linear;
+  return (linear % kNumXcd) * (total / kNumXcd) + linear / kNumXcd;
+}
+
+// ---------------------------------------------------------------------------
 // Deterministic grid reduction: per-block sums -> partials -> last block.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
@@ -99,6 +111,8 @@ __global__ void __launch_bounds__(256) k_finish_stats(const double* partials, in
 template <typename T> struct PropArgs {
   const T* wA;
   const T* wB;
+  const T* EA;            // exp(-(w_A - c_A)/2), written once per propagation
+  const T* EB;            // exp(-(w_B - c_B)/2)
   const double* scal;     // kMeanA, kMeanB: gauge constants
   T* q[2];                // q_1..q_N of chain c at q[c] + (j-1)*plane
   T* tmp;                 // 2 planes (per chain): data between the two convolutions of a step
@@ -125,31 +139,33 @@ __device__ __forceinline__ T boltz(T wa, T wb, T a, T ca, T cb) {
 }
 
 // Half-step Boltzmann factor exp(-(w_seg - c_seg)/2) of a segment with A
-// fraction `fr` at flat index i.
+// fraction `fr` at flat index i: a plane load for pure A or B segments, the
+// mixed junction segment from the potentials.
 template <typename T>
 __device__ __forceinline__ T efactor(const PropArgs<T>& P, T fr, T ca, T cb, long i) {
-  if (fr == T(1)) return exp(T(-0.5) * (P.wA[i] - ca));
-  if (fr == T(0)) return exp(T(-0.5) * (P.wB[i] - cb));
+  if (fr == T(1)) return P.EA[i];
+  if (fr == T(0)) return P.EB[i];
   return boltz(P.wA[i], P.wB[i], fr, ca, cb);
 }
 template <typename T>
 __device__ __forceinline__ T2<T> efactor2(const PropArgs<T>& P, T fr, T ca, T cb, long i2) {
+  if (fr == T(1)) return reinterpret_cast<const T2<T>*>(P.EA)[i2];
+  if (fr == T(0)) return reinterpret_cast<const T2<T>*>(P.EB)[i2];
+  const T2<T> u = reinterpret_cast<const T2<T>*>(P.wA)[i2];
+  const T2<T> w = reinterpret_cast<const T2<T>*>(P.wB)[i2];
   T2<T> e;
-  if (fr == T(1)) {
-    const T2<T> w = reinterpret_cast<const T2<T>*>(P.wA)[i2];
-    e.x = exp(T(-0.5) * (w.x - ca));
-    e.y = exp(T(-0.5) * (w.y - ca));
-  } else if (fr == T(0)) {
-    const T2<T> w = reinterpret_cast<const T2<T>*>(P.wB)[i2];
-    e.x = exp(T(-0.5) * (w.x - cb));
-    e.y = exp(T(-0.5) * (w.y - cb));
-  } else {
-    const T2<T> u = reinterpret_cast<const T2<T>*>(P.wA)[i2];
-    const T2<T> w = reinterpret_cast<const T2<T>*>(P.wB)[i2];
-    e.x = boltz(u.x, w.x, fr, ca, cb);
-    e.y = boltz(u.y, w.y, fr, ca, cb);
-  }
+  e.x = boltz(u.x, w.x, fr, ca, cb);
+  e.y = boltz(u.y, w.y, fr, ca, cb);
   return e;
+}
+
+// Both half-step factor planes of the current potentials.
+template <typename T>
+__global__ void __launch_bounds__(256) k_boltzmann(const T* w, T* E, const double* scal, long n) {
+  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  E[i] = exp(T(-0.5) * (w[i] - T(scal[kMeanA])));
+  E[n + i] = exp(T(-0.5) * (w[n + i] - T(scal[kMeanB])));
 }
 
 // Convolution with the real, even multiplier g in the lane layout.
@@ -173,14 +189,14 @@ __global__ void __launch_bounds__(512) k_prop_row(PropArgs<T> P) {
   using V = LdsView<T, L, R, true, 1>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16 * 1];
-  T* lre = reinterpret_cast<T*>(smem_raw);
   const int f = threadIdx.x / TL, j = threadIdx.x % TL;
-  V lds{lre, lre + V::size_per_component(P.nf), f};
+  V lds{reinterpret_cast<T2<T>*>(smem_raw), f};
   const int c = blockIdx.y;
   const int rp = blockIdx.x * P.nf + f;
   const bool active = rp < P.ny / 2;
   const long r0 = long(2 * rp) * P.nx, r1 = r0 + P.nx;
   const T ca = T(P.scal[kMeanA]), cb = T(P.scal[kMeanB]);
+  const T fr0 = P.frac[c][0], fr1 = P.frac[c][1];
   Twiddles<T, L, R> twf, twi;
   load_fwd_twiddles(twf, j, P.tw_x);
   load_inv_twiddles(twi, j, P.tw_x);
@@ -188,20 +204,24 @@ __global__ void __launch_bounds__(512) k_prop_row(PropArgs<T> P) {
 #pragma unroll
   for (int m = 0; m < R; ++m) g[m] = P.mult_x[j + TL * m];
   T* tmp = P.tmp + c * P.plane;
+  // half-step factors of step a (loaded early: they overlap the first convolution)
+  T ea[R], eb[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const int x = j + TL * m;
+    ea[m] = active && (P.first || P.mid) ? efactor(P, fr0, ca, cb, r0 + x) : T(0);
+    eb[m] = active && (P.first || P.mid) ? efactor(P, fr0, ca, cb, r1 + x) : T(0);
+  }
   T re[R], im[R];
 #pragma unroll
   for (int m = 0; m < R; ++m) {
     const int x = j + TL * m;
-    re[m] = T(0);
-    im[m] = T(0);
-    if (active) {
-      if (P.first) {
-        re[m] = efactor(P, P.frac[c][0], ca, cb, r0 + x);
-        im[m] = efactor(P, P.frac[c][0], ca, cb, r1 + x);
-      } else {
-        re[m] = tmp[r0 + x];
-        im[m] = tmp[r1 + x];
-      }
+    if (P.first) {
+      re[m] = ea[m];
+      im[m] = eb[m];
+    } else {
+      re[m] = active ? tmp[r0 + x] : T(0);
+      im[m] = active ? tmp[r1 + x] : T(0);
     }
   }
   convolve(re, im, j, lds, twf, twi, g);
@@ -211,22 +231,27 @@ __global__ void __launch_bounds__(512) k_prop_row(PropArgs<T> P) {
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       const int x = j + TL * m;
+      re[m] *= ea[m];
+      im[m] *= eb[m];
       if (active) {
-        re[m] *= efactor(P, P.frac[c][0], ca, cb, r0 + x);
-        im[m] *= efactor(P, P.frac[c][0], ca, cb, r1 + x);
         qo[r0 + x] = re[m];
         qo[r1 + x] = im[m];
-        qsum += double(re[m]) + double(im[m]);
       }
+      qsum += double(re[m]) + double(im[m]);
     }
     if (P.second) {
+      if (fr1 != fr0) {
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+          const int x = j + TL * m;
+          ea[m] = active ? efactor(P, fr1, ca, cb, r0 + x) : T(0);
+          eb[m] = active ? efactor(P, fr1, ca, cb, r1 + x) : T(0);
+        }
+      }
 #pragma unroll
       for (int m = 0; m < R; ++m) {
-        const int x = j + TL * m;
-        if (active) {
-          re[m] *= efactor(P, P.frac[c][1], ca, cb, r0 + x);
-          im[m] *= efactor(P, P.frac[c][1], ca, cb, r1 + x);
-        }
+        re[m] *= ea[m];
+        im[m] *= eb[m];
       }
       convolve(re, im, j, lds, twf, twi, g);
     }
@@ -249,19 +274,20 @@ __global__ void __launch_bounds__(512) k_prop_row(PropArgs<T> P) {
 // transforms per block interleaved lane by lane so that each global access
 // of a wavefront covers NF consecutive column pairs.
 template <typename T, int L, int R, int NF>
-__global__ void __launch_bounds__(512) k_prop_col(PropArgs<T> P) {
+__global__ void __launch_bounds__(1024) k_prop_col(PropArgs<T> P) {
   constexpr int TL = L / R;
   using V = LdsView<T, L, R, false, NF>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16 * 1];
-  T* lre = reinterpret_cast<T*>(smem_raw);
   const int f = threadIdx.x % NF, j = threadIdx.x / NF;
-  V lds{lre, lre + V::size_per_component(NF), f};
-  const int c = blockIdx.y;
-  const int cp = blockIdx.x * NF + f;
+  V lds{reinterpret_cast<T2<T>*>(smem_raw), f};
+  const int lt = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int c = lt / gridDim.x, tile = lt % gridDim.x;
+  const int cp = tile * NF + f;
   const bool active = cp < P.nx / 2;
   const int x0 = 2 * cp;
   const T ca = T(P.scal[kMeanA]), cb = T(P.scal[kMeanB]);
+  const T fr0 = P.frac[c][0], fr1 = P.frac[c][1];
   Twiddles<T, L, R> twf, twi;
   load_fwd_twiddles(twf, j, P.tw_y);
   load_inv_twiddles(twi, j, P.tw_y);
@@ -269,16 +295,26 @@ __global__ void __launch_bounds__(512) k_prop_col(PropArgs<T> P) {
 #pragma unroll
   for (int m = 0; m < R; ++m) g[m] = P.mult_y[j + TL * m];
   T2<T>* tmp2 = reinterpret_cast<T2<T>*>(P.tmp + c * P.plane);
+  T2<T> e[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const long i2 = (long(j + TL * m) * P.nx + x0) >> 1;
+    e[m].x = T(0);
+    e[m].y = T(0);
+    if (active && (P.first || P.mid)) e[m] = efactor2(P, fr0, ca, cb, i2);
+  }
   T re[R], im[R];
 #pragma unroll
   for (int m = 0; m < R; ++m) {
     const long i2 = (long(j + TL * m) * P.nx + x0) >> 1;
-    re[m] = T(0);
-    im[m] = T(0);
-    if (active) {
+    if (P.first) {
+      re[m] = e[m].x;
+      im[m] = e[m].y;
+    } else {
       T2<T> v;
-      if (P.first) v = efactor2(P, P.frac[c][0], ca, cb, i2);
-      else v = tmp2[i2];
+      v.x = T(0);
+      v.y = T(0);
+      if (active) v = tmp2[i2];
       re[m] = v.x;
       im[m] = v.y;
     }
@@ -290,26 +326,26 @@ __global__ void __launch_bounds__(512) k_prop_col(PropArgs<T> P) {
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       const long i2 = (long(j + TL * m) * P.nx + x0) >> 1;
-      if (active) {
-        const T2<T> e = efactor2(P, P.frac[c][0], ca, cb, i2);
-        re[m] *= e.x;
-        im[m] *= e.y;
-        T2<T> o;
-        o.x = re[m];
-        o.y = im[m];
-        qo[i2] = o;
-        qsum += double(o.x) + double(o.y);
-      }
+      re[m] *= e[m].x;
+      im[m] *= e[m].y;
+      T2<T> o;
+      o.x = re[m];
+      o.y = im[m];
+      if (active) qo[i2] = o;
+      qsum += double(o.x) + double(o.y);
     }
     if (P.second) {
+      if (fr1 != fr0) {
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+          const long i2 = (long(j + TL * m) * P.nx + x0) >> 1;
+          if (active) e[m] = efactor2(P, fr1, ca, cb, i2);
+        }
+      }
 #pragma unroll
       for (int m = 0; m < R; ++m) {
-        const long i2 = (long(j + TL * m) * P.nx + x0) >> 1;
-        if (active) {
-          const T2<T> e = efactor2(P, P.frac[c][1], ca, cb, i2);
-          re[m] *= e.x;
-          im[m] *= e.y;
-        }
+        re[m] *= e[m].x;
+        im[m] *= e[m].y;
       }
       convolve(re, im, j, lds, twf, twi, g);
     }
@@ -326,7 +362,7 @@ __global__ void __launch_bounds__(512) k_prop_col(PropArgs<T> P) {
   }
   if (P.last) {
     double v[1] = {qsum};
-    block_partial<1>(v, red, P.partials + c * gridDim.x, blockIdx.x);
+    block_partial<1>(v, red, P.partials + c * gridDim.x, tile);
   }
 }
 
@@ -461,7 +497,8 @@ __global__ void __launch_bounds__(256) k_advect_update(UpdArgs<T> P) {
   __shared__ T sMu[3][kMY][kMX];
   __shared__ T sWt[3][kMY][kMX];
   __shared__ double red[16 * 4];
-  const int tx0 = blockIdx.x * kTX, ty0 = blockIdx.y * kTY;
+  const int lt = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int tx0 = (lt % gridDim.x) * kTX, ty0 = (lt / gridDim.x) * kTY;
   const int tid = threadIdx.x;
   for (int e = tid; e < kHX * kHY; e += blockDim.x) {
     const int lx = e % kHX, ly = e / kHX;
@@ -539,7 +576,7 @@ __global__ void __launch_bounds__(256) k_advect_update(UpdArgs<T> P) {
       if (I == 2) v[3] = double(exp(-(wn - cS)));
     }
   }
-  block_partial<4>(v, red, P.partials, blockIdx.y * gridDim.x + blockIdx.x);
+  block_partial<4>(v, red, P.partials, lt);
 }
 
 // ---------------------------------------------------------------------------
@@ -566,9 +603,8 @@ __global__ void __launch_bounds__(512) k_force_row_fwd(ForceArgs<T> P) {
   constexpr int TL = L / R;
   using V = LdsView<T, L, R, true, 1>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* lre = reinterpret_cast<T*>(smem_raw);
   const int f = threadIdx.x / TL, j = threadIdx.x % TL;
-  V lds{lre, lre + V::size_per_component(P.nf), f};
+  V lds{reinterpret_cast<T2<T>*>(smem_raw), f};
   const int y = blockIdx.x * P.nf + f;
   const bool active = y < P.ny;
   Twiddles<T, L, R> twf;
@@ -592,14 +628,13 @@ __global__ void __launch_bounds__(512) k_force_row_fwd(ForceArgs<T> P) {
 }
 
 template <typename T, int L, int R, int NF>
-__global__ void __launch_bounds__(512) k_force_col(ForceArgs<T> P) {
+__global__ void __launch_bounds__(1024) k_force_col(ForceArgs<T> P) {
   constexpr int TL = L / R;
   using V = LdsView<T, L, R, false, NF>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* lre = reinterpret_cast<T*>(smem_raw);
   const int f = threadIdx.x % NF, j = threadIdx.x / NF;
-  V lds{lre, lre + V::size_per_component(NF), f};
-  const int kxi = blockIdx.x * NF + f;   // column = x wavenumber index
+  V lds{reinterpret_cast<T2<T>*>(smem_raw), f};
+  const int kxi = xcd_tile(blockIdx.x, gridDim.x) * NF + f;   // column = x wavenumber index
   const bool active = kxi < P.nx;
   Twiddles<T, L, R> twf, twi;
   load_fwd_twiddles(twf, j, P.tw_y);
@@ -649,9 +684,8 @@ __global__ void __launch_bounds__(512) k_force_row_inv(ForceArgs<T> P) {
   constexpr int TL = L / R;
   using V = LdsView<T, L, R, true, 1>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* lre = reinterpret_cast<T*>(smem_raw);
   const int f = threadIdx.x / TL, j = threadIdx.x % TL;
-  V lds{lre, lre + V::size_per_component(P.nf), f};
+  V lds{reinterpret_cast<T2<T>*>(smem_raw), f};
   const int y = blockIdx.x * P.nf + f;
   const bool active = y < P.ny;
   Twiddles<T, L, R> twi;
