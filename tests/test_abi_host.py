@@ -64,7 +64,7 @@ def test_workspace_bytes_scale():
     b32, b64 = B.epdlb_workspace_bytes(p32), B.epdlb_workspace_bytes(p64)
     n = 1024 * 512
     N = 64
-    planes = 2 * N + 38  # omega 6, phi 3, S~ 1, S 1, q 2N, tmp 2, spec 2, F 2, f* 18, rho 1, u 2
+    planes = 2 * N + 40  # omega 6, phi 3, S~ 1, S 1, q 2N, tmp 2, spec 2, F 2, f* 18, rho 1, u 2, E 2
     assert planes * n * 4 <= b32 < planes * n * 4 + (1 << 22)
     assert abs(b64 - 2 * b32) < (1 << 22)
 
