@@ -103,18 +103,36 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1804_02883_amd import Simulation
-    from seeded_inputs import PRESETS
+    from paper_1804_02883_amd import Batch, Simulation
+    from seeded_inputs import PRESETS, replica_manifest
 
-    cfg = PRESETS[args.workload]
-    p = dict(cfg["params"])
-    n = p["nx"] * p["ny"]
+    torch.cuda.set_device(0)
+    if args.workload == "cfg4":
+        man = replica_manifest()
+        plist = [m["params"] for m in man]
+        p = dict(plist[0])
+        n = sum(q["nx"] * q["ny"] for q in plist)
+        sim = Batch(plist)
+        sim.seed([m["seed"] for m in man], man[0]["sigma"])
+        if not args.no_tune:
+            sim.autotune(20, args.tune_cache)
+        shapes = None
+        wl = (f"cfg4: {len(plist)} replicas from the seeded manifest (grids 64x64, 128x128, 256x128, "
+              f"512x256; g in [0, 5e-5] f*, f_A in {{0.3, 0.5}}), N=32, FP32, chi reading L, seeds 4000+r, "
+              f"{n} sites, plain (exact propagator)")
+        cfgd = dict(workload=wl, replicas=len(plist), sites=n, n_contour=32, path="plain")
+    else:
+        cfg = PRESETS[args.workload]
+        p = dict(cfg["params"])
+        n = p["nx"] * p["ny"]
+        sim = Simulation(p)
+        sim.seed(cfg["seed"], cfg["sigma"])
+        shapes = sim.shapes() if args.no_tune else sim.autotune(20, args.tune_cache)
+        wl = (f"{args.workload}: {cfg['name']}, chi reading L, g={p['g']}, "
+              f"seed {cfg['seed']} noise sigma {cfg['sigma']}, plain (exact propagator)")
+        cfgd = dict(workload=wl, nx=p["nx"], ny=p["ny"], n_contour=p["n_contour"], path="plain")
     N = p["n_contour"]
     P = 8 if p["precision"] == 0 else 4
-    torch.cuda.set_device(0)
-    sim = Simulation(p)
-    sim.seed(cfg["seed"], cfg["sigma"])
-    shapes = sim.shapes() if args.no_tune else sim.autotune(20, args.tune_cache)
     sim.step(args.warmup)
     sim.sync()
 
@@ -130,8 +148,9 @@ def main():
     sim.sync()
     # per-kernel durations: HIP start/stop events recorded by each kernel launch
     # itself (stream launches of the same workload, right after the timed region)
-    prof_steps = max(1, min(50, args.profile_launches // (N + 9)))
-    sim.profile_start(prof_steps * (N + 9) + 16)
+    per_step = (N + 9) * (1 if args.workload != "cfg4" else sim.info()[0])
+    prof_steps = max(1, min(50, args.profile_launches // per_step))
+    sim.profile_start(prof_steps * per_step + 16)
     sim.step(prof_steps)
     prof = sim.profile_read()
     ms_per_step = ms / args.steps
@@ -157,17 +176,14 @@ def main():
                               if step_bytes_per_site(k, N, P) else None))
                  for k, v in prof.items()}
     breakdown["kernel_sum_us_per_step"] = round(1e3 * tot / prof_steps, 2)
-    d = sim.diag()
+    d = sim.diag() if args.workload != "cfg4" else sim.diag(0)
     sim.close()
 
     out = dict(metric=METRIC, value=value, unit="site-updates/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=ms_per_step, higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f32" if P == 4 else "f64", data="synthetic",
-               config=dict(workload=f"{args.workload}: {cfg['name']}, chi reading L, g={p['g']}, "
-                                    f"seed {cfg['seed']} noise sigma {cfg['sigma']}, plain (exact propagator)",
-                           nx=p["nx"], ny=p["ny"], n_contour=N, path="plain"),
-               roofline=roofline, breakdown=breakdown, shapes=shapes, Q_P=d["Q_P"])
-    if not args.no_cpu_baseline:
+               config=cfgd, roofline=roofline, breakdown=breakdown, shapes=shapes, Q_P=d["Q_P"])
+    if not args.no_cpu_baseline and args.workload != "cfg4":
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_steps)
     print(json.dumps(out), flush=True)
 

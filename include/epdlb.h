@@ -182,6 +182,42 @@ int epdlb_profile_read(epdlb_ctx* ctx, epdlb_kernel_stat* out, int32_t cap, int3
 /* Release the context (device memory it allocated, its own stream). */
 void epdlb_destroy(epdlb_ctx* ctx);
 
+/* ---------------------------------------------------------------------------
+ * Batched replicas.  Many independent runs (the paper averages 50-100 runs per
+ * parameter set, Sec. IV) advanced together: replicas may differ in grid
+ * (nx, ny), drive g and A fraction f_A, and must agree in every other model
+ * parameter.  Replicas of one grid shape and A fraction share every kernel
+ * launch; one captured graph advances all of them per step pair.  Replica indices follow
+ * the order of `params`.
+ * ------------------------------------------------------------------------- */
+typedef struct epdlb_batch epdlb_batch;
+
+/* `params[n_replicas]`; `stream` as in epdlb_create.  Device memory is
+ * allocated by the batch. */
+int epdlb_batch_create(const epdlb_params* params, int32_t n_replicas, int device, void* stream,
+                       epdlb_batch** out);
+/* omega of replica r = sigma * noise(seeds[r]); Phi = Phi[omega]; LB at rest + u_init. */
+int epdlb_batch_seed(epdlb_batch* b, const uint64_t* seeds, double sigma);
+/* Replace one replica's potentials (after seeding); its LB restarts. */
+int epdlb_batch_set_fields(epdlb_batch* b, int32_t replica, const double* omega);
+/* Queue n hybrid steps of every replica on the batch stream. */
+int epdlb_batch_step(epdlb_batch* b, int64_t n);
+int epdlb_batch_sync(epdlb_batch* b);
+/* Per-replica reads, as the single-context reads (host FP64, nx*ny each). */
+int epdlb_batch_read_densities(epdlb_batch* b, int32_t replica, double* phiA, double* phiB, double* phiS);
+int epdlb_batch_read_fields(epdlb_batch* b, int32_t replica, double* wA, double* wB, double* wS);
+int epdlb_batch_read_velocity(epdlb_batch* b, int32_t replica, double* rho, double* ux, double* uy);
+int epdlb_batch_read_diag(epdlb_batch* b, int32_t replica, epdlb_diag* d);
+/* Autotune every shape group (see epdlb_autotune). */
+int epdlb_batch_autotune(epdlb_batch* b, int32_t reps, const char* cache_path);
+/* Per-kernel timing of the next steps (stream launches, group after group),
+ * merged over the groups; see epdlb_profile_start / epdlb_profile_read. */
+int epdlb_batch_profile_start(epdlb_batch* b, int32_t max_launches);
+int epdlb_batch_profile_read(epdlb_batch* b, epdlb_kernel_stat* out, int32_t cap, int32_t* n_out);
+/* Number of replica groups (grid shape, A fraction) and total lattice sites. */
+int epdlb_batch_info(epdlb_batch* b, int32_t* n_groups, int64_t* sites);
+void epdlb_batch_destroy(epdlb_batch* b);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char* epdlb_last_error(void);
 

@@ -113,6 +113,21 @@ SIGNATURES = {
     "epdlb_profile_read": (ctypes.c_int, [_vp, _P(epdlb_kernel_stat), ctypes.c_int32,
                                           _P(ctypes.c_int32)]),
     "epdlb_destroy": (None, [_vp]),
+    "epdlb_batch_create": (ctypes.c_int, [_P(epdlb_params), ctypes.c_int32, ctypes.c_int, _vp, _P(_vp)]),
+    "epdlb_batch_seed": (ctypes.c_int, [_vp, _P(ctypes.c_uint64), ctypes.c_double]),
+    "epdlb_batch_set_fields": (ctypes.c_int, [_vp, ctypes.c_int32, _dp]),
+    "epdlb_batch_step": (ctypes.c_int, [_vp, ctypes.c_int64]),
+    "epdlb_batch_sync": (ctypes.c_int, [_vp]),
+    "epdlb_batch_read_densities": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, _dp, _dp]),
+    "epdlb_batch_read_fields": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, _dp, _dp]),
+    "epdlb_batch_read_velocity": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, _dp, _dp]),
+    "epdlb_batch_read_diag": (ctypes.c_int, [_vp, ctypes.c_int32, _P(epdlb_diag)]),
+    "epdlb_batch_autotune": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_char_p]),
+    "epdlb_batch_info": (ctypes.c_int, [_vp, _P(ctypes.c_int32), _P(ctypes.c_int64)]),
+    "epdlb_batch_profile_start": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "epdlb_batch_profile_read": (ctypes.c_int, [_vp, _P(epdlb_kernel_stat), ctypes.c_int32,
+                                                _P(ctypes.c_int32)]),
+    "epdlb_batch_destroy": (None, [_vp]),
     "epdlb_last_error": (ctypes.c_char_p, []),
 }
 
@@ -402,3 +417,150 @@ class Simulation:
 
     def profile_read(self):
         return epdlb_profile_read(self.ctx)
+
+
+# ---- batched replicas ----------------------------------------------------------------------
+
+def epdlb_batch_create(params_list, device=0, stream=None):
+    arr = (epdlb_params * len(params_list))(*params_list)
+    h = _vp()
+    _check(load_library().epdlb_batch_create(arr, len(params_list), device, stream, ctypes.byref(h)),
+           "epdlb_batch_create")
+    return h
+
+
+def epdlb_batch_seed(b, seeds, sigma):
+    arr = (ctypes.c_uint64 * len(seeds))(*seeds)
+    _check(load_library().epdlb_batch_seed(b, arr, sigma), "epdlb_batch_seed")
+
+
+def epdlb_batch_set_fields(b, replica, omega, n):
+    w = _f64(omega, 3 * n)
+    _check(load_library().epdlb_batch_set_fields(b, replica, _ptr(w)), "epdlb_batch_set_fields")
+
+
+def epdlb_batch_step(b, n):
+    _check(load_library().epdlb_batch_step(b, n), "epdlb_batch_step")
+
+
+def epdlb_batch_sync(b):
+    _check(load_library().epdlb_batch_sync(b), "epdlb_batch_sync")
+
+
+def _bread3(fn, b, replica, shape):
+    out = np.empty((3,) + shape, dtype=np.float64)
+    _check(getattr(load_library(), fn)(b, replica, _ptr(out[0]), _ptr(out[1]), _ptr(out[2])), fn)
+    return out
+
+
+def epdlb_batch_read_densities(b, replica, shape):
+    return _bread3("epdlb_batch_read_densities", b, replica, shape)
+
+
+def epdlb_batch_read_fields(b, replica, shape):
+    return _bread3("epdlb_batch_read_fields", b, replica, shape)
+
+
+def epdlb_batch_read_velocity(b, replica, shape):
+    out = _bread3("epdlb_batch_read_velocity", b, replica, shape)
+    return out[0], out[1:]
+
+
+def epdlb_batch_read_diag(b, replica):
+    d = epdlb_diag()
+    _check(load_library().epdlb_batch_read_diag(b, replica, ctypes.byref(d)), "epdlb_batch_read_diag")
+    return dict(step=d.step, Q_P=d.Q_P, Q_P_bwd=d.Q_P_bwd, Q_S=d.Q_S, gauge_S=d.gauge_S,
+                mean_omega=tuple(d.mean_omega))
+
+
+def epdlb_batch_autotune(b, reps=20, cache_path=None):
+    cp = cache_path.encode() if cache_path else None
+    _check(load_library().epdlb_batch_autotune(b, reps, cp), "epdlb_batch_autotune")
+
+
+def epdlb_batch_profile_start(b, max_launches):
+    _check(load_library().epdlb_batch_profile_start(b, max_launches), "epdlb_batch_profile_start")
+
+
+def epdlb_batch_profile_read(b):
+    cap = 32
+    arr = (epdlb_kernel_stat * cap)()
+    n = ctypes.c_int32(0)
+    _check(load_library().epdlb_batch_profile_read(b, arr, cap, ctypes.byref(n)), "epdlb_batch_profile_read")
+    return {arr[i].name.decode(): dict(launches=arr[i].launches, total_ms=arr[i].total_ms,
+                                       min_ms=arr[i].min_ms, max_ms=arr[i].max_ms,
+                                       avg_ms=arr[i].total_ms / max(arr[i].launches, 1))
+            for i in range(n.value)}
+
+
+def epdlb_batch_info(b):
+    g = ctypes.c_int32(0)
+    s = ctypes.c_int64(0)
+    _check(load_library().epdlb_batch_info(b, ctypes.byref(g), ctypes.byref(s)), "epdlb_batch_info")
+    return g.value, s.value
+
+
+def epdlb_batch_destroy(b):
+    load_library().epdlb_batch_destroy(b)
+
+
+class Batch:
+    """Many replicas (uneven grids, own drive, A fraction and seed) advanced
+    together on one GPU; work is queued on torch's current stream."""
+
+    def __init__(self, params_list, device=0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("epdlb needs a ROCm GPU (gfx950); none is visible")
+        self.params = [p if isinstance(p, epdlb_params) else make_params(p) for p in params_list]
+        self.shapes = [(p.ny, p.nx) for p in self.params]
+        self.stream = torch.cuda.current_stream(torch.device("cuda", device))
+        self.b = epdlb_batch_create(self.params, device, _vp(self.stream.cuda_stream))
+
+    def close(self):
+        if getattr(self, "b", None) is not None:
+            epdlb_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def seed(self, seeds, sigma):
+        epdlb_batch_seed(self.b, seeds, sigma)
+
+    def set_fields(self, replica, omega):
+        ny, nx = self.shapes[replica]
+        epdlb_batch_set_fields(self.b, replica, omega, nx * ny)
+
+    def step(self, n=1):
+        epdlb_batch_step(self.b, n)
+
+    def sync(self):
+        epdlb_batch_sync(self.b)
+
+    def densities(self, replica):
+        return epdlb_batch_read_densities(self.b, replica, self.shapes[replica])
+
+    def fields(self, replica):
+        return epdlb_batch_read_fields(self.b, replica, self.shapes[replica])
+
+    def velocity(self, replica):
+        return epdlb_batch_read_velocity(self.b, replica, self.shapes[replica])
+
+    def diag(self, replica):
+        return epdlb_batch_read_diag(self.b, replica)
+
+    def autotune(self, reps=20, cache_path=None):
+        epdlb_batch_autotune(self.b, reps, cache_path)
+
+    def info(self):
+        return epdlb_batch_info(self.b)
+
+    def profile_start(self, max_launches):
+        epdlb_batch_profile_start(self.b, max_launches)
+
+    def profile_read(self):
+        return epdlb_batch_profile_read(self.b)

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "epdlb.h"
@@ -121,7 +122,10 @@ struct epdlb_ctx {
   int fcur = 0;   // current f* buffer
   bool seeded = false;
   int64_t nstep = 0;
-  std::vector<double> seg_a;   // A fraction per segment
+  int nrep = 1;                // replicas of this grid shape sharing every launch
+  size_t rstride = 0;          // bytes from one replica's arena to the next
+  std::vector<epdlb_params> rp;  // per-replica parameters (g, f_A may differ)
+  size_t roff(int r) const { return size_t(r) * rstride; }
   // FFT launch shapes: R values per lane, nf transforms per block
   struct Shape {
     int R, nf;
@@ -211,6 +215,17 @@ int validate(const epdlb_params* p) {
   return EPDLB_OK;
 }
 
+// Segment A fractions a_j = clip(f_A N - j, 0, 1) of a parameter set.
+std::vector<double> segment_fractions(const epdlb_params& p) {
+  const int N = p.n_contour;
+  std::vector<double> a(N);
+  for (int j = 0; j < N; ++j) {
+    const double v = p.f_A * N - j;
+    a[j] = v < 0 ? 0.0 : (v > 1 ? 1.0 : v);
+  }
+  return a;
+}
+
 double g_lattice(const epdlb_params& p) { return p.g_units ? p.g : p.g * p.dt * p.dt / p.dx; }
 
 int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -229,7 +244,7 @@ template <typename T, int L, int R>
 constexpr bool fft_ok() {
   return (R == 8 || ((R == 16 || R == 4 || R == 2) && sizeof(T) == 4)) && L >= R;
 }
-constexpr int kMaxColThreads = 1024;
+constexpr int kMaxColThreads = 512;
 
 template <typename T, int L, int R>
 hipError_t launch_prop_row_r(const PropArgs<T>& a, hipStream_t s) {
@@ -239,7 +254,7 @@ hipError_t launch_prop_row_r(const PropArgs<T>& a, hipStream_t s) {
     hipError_t e = prep_lds(k_prop_row<T, L, R>, lds);
     if (e != hipSuccess) return e;
     const int tiles = (a.ny / 2 + a.nf - 1) / a.nf;
-    launch_k((k_prop_row<T, L, R>), dim3(tiles, 2), dim3(a.nf * (L / R)), lds, s, a);
+    launch_k((k_prop_row<T, L, R>), dim3(tiles, 2, a.nrep), dim3(a.nf * (L / R)), lds, s, a);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;
@@ -262,7 +277,7 @@ hipError_t launch_prop_col_rn(const PropArgs<T>& a, hipStream_t s) {
     hipError_t e = prep_lds(k_prop_col<T, L, R, NF>, lds);
     if (e != hipSuccess) return e;
     const int tiles = (a.nx / 2 + NF - 1) / NF;
-    launch_k((k_prop_col<T, L, R, NF>), dim3(tiles, 2), dim3(NF * (L / R)), lds, s, a);
+    launch_k((k_prop_col<T, L, R, NF>), dim3(tiles, 2, a.nrep), dim3(NF * (L / R)), lds, s, a);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;
@@ -293,7 +308,7 @@ hipError_t launch_force_row_fwd_r(const ForceArgs<T>& a, hipStream_t s) {
     const size_t lds = 2 * size_t(V::size_elems(a.nf)) * sizeof(T);
     hipError_t e = prep_lds(k_force_row_fwd<T, L, R>, lds);
     if (e != hipSuccess) return e;
-    launch_k((k_force_row_fwd<T, L, R>), dim3((a.ny + a.nf - 1) / a.nf), dim3(a.nf * (L / R)),
+    launch_k((k_force_row_fwd<T, L, R>), dim3((a.ny + a.nf - 1) / a.nf, 1, a.nrep), dim3(a.nf * (L / R)),
                        lds, s, a);
     return hipGetLastError();
   }
@@ -315,7 +330,7 @@ hipError_t launch_force_row_inv_r(const ForceArgs<T>& a, hipStream_t s) {
     const size_t lds = 2 * size_t(V::size_elems(a.nf)) * sizeof(T);
     hipError_t e = prep_lds(k_force_row_inv<T, L, R>, lds);
     if (e != hipSuccess) return e;
-    launch_k((k_force_row_inv<T, L, R>), dim3((a.ny + a.nf - 1) / a.nf), dim3(a.nf * (L / R)),
+    launch_k((k_force_row_inv<T, L, R>), dim3((a.ny + a.nf - 1) / a.nf, 1, a.nrep), dim3(a.nf * (L / R)),
                        lds, s, a);
     return hipGetLastError();
   }
@@ -337,7 +352,7 @@ hipError_t launch_force_col_rn(const ForceArgs<T>& a, hipStream_t s) {
     const size_t lds = 2 * size_t(V::size_elems(NF)) * sizeof(T);
     hipError_t e = prep_lds(k_force_col<T, L, R, NF>, lds);
     if (e != hipSuccess) return e;
-    launch_k((k_force_col<T, L, R, NF>), dim3((a.nx + NF - 1) / NF), dim3(NF * (L / R)), lds, s,
+    launch_k((k_force_col<T, L, R, NF>), dim3((a.nx + NF - 1) / NF, 1, a.nrep), dim3(NF * (L / R)), lds, s,
                        a);
     return hipGetLastError();
   }
@@ -401,12 +416,14 @@ int stage_stats(epdlb_ctx* c) {
   a.n = n;
   a.scal = c->ptr<double>(c->L.scal);
   a.partials = c->ptr<double>(c->L.partials);
+  a.nrep = c->nrep;
+  a.rs = long(c->rstride);
   const int blocks = int(std::min<long>(1024, (n + 255) / 256));
   ProfScope ps(c, K_STATS);
-  launch_k((k_field_stats<T>), dim3(blocks), dim3(256), 0, c->stream, a);
+  launch_k((k_field_stats<T>), dim3(blocks, 1, c->nrep), dim3(256), 0, c->stream, a);
   HIPCHK(hipGetLastError());
-  launch_k(k_finish_stats, dim3(1), dim3(256), 0, c->stream, a.partials, blocks, a.scal, n,
-                     c->p.dx * c->p.dx);
+  launch_k(k_finish_stats, dim3(1, 1, c->nrep), dim3(256), 0, c->stream, a.partials, blocks, a.scal, n,
+           c->p.dx * c->p.dx, long(c->rstride));
   HIPCHK(hipGetLastError());
   return EPDLB_OK;
 }
@@ -436,15 +453,17 @@ int stage_advect_update(epdlb_ctx* c) {
     a.invD[i] = T(1.0 / D[i]);
   }
   a.advect = p.couple_lb ? 1 : 0;
+  a.nrep = c->nrep;
+  a.rs = long(c->rstride);
   {
     ProfScope ps(c, K_ADVECT);
-    launch_k((k_advect_update<T>), dim3(p.nx / kTX, p.ny / kTY), dim3(kTX * kTY), 0, c->stream, a);
+    launch_k((k_advect_update<T>), dim3(p.nx / kTX, p.ny / kTY, c->nrep), dim3(kTX * kTY), 0, c->stream, a);
   }
   HIPCHK(hipGetLastError());
   {
     ProfScope ps(c, K_FINISH);
-    launch_k(k_finish_stats, dim3(1), dim3(256), 0, c->stream, a.partials,
-                       (p.nx / kTX) * (p.ny / kTY), c->ptr<double>(c->L.scal), n, p.dx * p.dx);
+    launch_k(k_finish_stats, dim3(1, 1, c->nrep), dim3(256), 0, c->stream, a.partials,
+             (p.nx / kTX) * (p.ny / kTY), c->ptr<double>(c->L.scal), n, p.dx * p.dx, long(c->rstride));
   }
   HIPCHK(hipGetLastError());
   c->cur = 1 - c->cur;
@@ -476,6 +495,8 @@ PropArgs<T> make_prop_args(epdlb_ctx* c) {
   a.first = a.mid = a.second = a.last = 0;
   a.frac[0][0] = a.frac[0][1] = a.frac[1][0] = a.frac[1][1] = T(1);
   a.nf = 1;
+  a.nrep = c->nrep;
+  a.rs = long(c->rstride);
   return a;
 }
 
@@ -487,11 +508,10 @@ int stage_densities(epdlb_ctx* c, bool with_S) {
   PropArgs<T> a = make_prop_args<T>(c);
   {
     ProfScope ps(c, K_BOLTZ);
-    launch_k((k_boltzmann<T>), dim3((n + 255) / 256), dim3(256), 0, c->stream, a.wA,
-                       c->ptr<T>(c->L.boltz), a.scal, n);
+    launch_k((k_boltzmann<T>), dim3((n + 255) / 256, 1, c->nrep), dim3(256), 0, c->stream, a.wA,
+             c->ptr<T>(c->L.boltz), a.scal, n, long(c->rstride));
   }
   HIPCHK(hipGetLastError());
-  auto seg = [&](int chain, int step) { return T(c->seg_a[chain == 0 ? step : N - 1 - step]); };
   auto launch = [&](bool row) -> int {
     if (row) {
       a.nf = c->sh_row.nf;
@@ -505,6 +525,9 @@ int stage_densities(epdlb_ctx* c, bool with_S) {
     return EPDLB_OK;
   };
   // step 0 starts with its x convolution of E(step 0)
+  // segment A fractions (uniform over the replicas of a launch)
+  const std::vector<double> segA = segment_fractions(p);
+  auto seg = [&](int chain, int step) { return T(segA[chain == 0 ? step : N - 1 - step]); };
   a.a = 0;
   a.first = 1;
   a.mid = a.second = a.last = 0;
@@ -548,9 +571,11 @@ int stage_densities(epdlb_ctx* c, bool with_S) {
   d.invDA = 1.0 / p.D_A;
   d.invDB = 1.0 / p.D_B;
   d.invDS = 1.0 / p.D_S;
+  d.nrep = c->nrep;
+  d.rs = long(c->rstride);
   {
     ProfScope ps(c, K_DENSITY);
-    launch_k((k_density<T>), dim3((n + 255) / 256), dim3(256), 0, c->stream, d);
+    launch_k((k_density<T>), dim3((n + 255) / 256, 1, c->nrep), dim3(256), 0, c->stream, d);
   }
   HIPCHK(hipGetLastError());
   return EPDLB_OK;
@@ -572,8 +597,10 @@ ForceArgs<T> make_force_args(epdlb_ctx* c) {
   a.ky0 = 2.0 * M_PI / (p.ny * p.dx);
   a.pref = p.kT_over_v / p.dt / (double(p.nx) * p.ny);
   a.conv = p.couple_lb ? p.dt * p.dt / p.dx : 0.0;
-  a.gext = g_lattice(p);
+  a.scal = c->ptr<double>(c->L.scal);
   a.nf = 1;
+  a.nrep = c->nrep;
+  a.rs = long(c->rstride);
   return a;
 }
 
@@ -614,9 +641,11 @@ int stage_lb(epdlb_ctx* c) {
   a.n = n;
   a.omega = T(1.0 / p.lb_tau);
   a.fpre = T(1.0 - 0.5 / p.lb_tau);
+  a.nrep = c->nrep;
+  a.rs = long(c->rstride);
   {
     ProfScope ps(c, K_LB);
-    launch_k((k_lb<T>), dim3((n + 255) / 256), dim3(256), 0, c->stream, a);
+    launch_k((k_lb<T>), dim3((n + 255) / 256, 1, c->nrep), dim3(256), 0, c->stream, a);
   }
   HIPCHK(hipGetLastError());
   c->fcur = 1 - c->fcur;
@@ -729,8 +758,8 @@ void drop_graphs(epdlb_ctx* c) {
 
 std::string tune_key(const epdlb_ctx* c, int fam) {
   char buf[128];
-  std::snprintf(buf, sizeof(buf), "gfx950 %d %d %d %d %s", c->p.nx, c->p.ny, c->p.n_contour, c->p.precision,
-                kFamilyName[fam]);
+  std::snprintf(buf, sizeof(buf), "gfx950 %d %d %d %d x%d %s", c->p.nx, c->p.ny, c->p.n_contour,
+                c->p.precision, c->nrep, kFamilyName[fam]);
   return buf;
 }
 
@@ -762,6 +791,17 @@ int download(epdlb_ctx* c, size_t off, double* dst, size_t count) {
 size_t elem(const epdlb_ctx* c) { return c->p.precision == 0 ? 8 : 4; }
 
 // Constant tables: twiddles, heat-kernel multipliers, node weights.
+// FP64 scalars of replica r: zero, except the external-force amplitude.
+int reset_scal(epdlb_ctx* c, int r) {
+  double sc[kNumScal] = {0};
+  sc[kGext] = g_lattice(c->rp[r]);
+  HIPCHK(hipMemcpyAsync(c->base + c->roff(r) + c->L.scal, sc, sizeof(sc), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return EPDLB_OK;
+}
+
+// Constant tables of every replica: twiddles, heat-kernel multipliers,
+// contour node weights; scalars.
 int upload_tables(epdlb_ctx* c) {
   const epdlb_params& p = c->p;
   const int N = p.n_contour;
@@ -782,33 +822,30 @@ int upload_tables(epdlb_ctx* c) {
       out[2 * e + 1] = -std::sin(ang);
     }
   };
-  std::vector<double> v;
-  mult(p.nx, v);
-  CHK(upload(c, c->L.mult_x, v.data(), v.size()));
-  mult(p.ny, v);
-  CHK(upload(c, c->L.mult_y, v.data(), v.size()));
-  tw(p.nx, v);
-  CHK(upload(c, c->L.tw_x, v.data(), v.size()));
-  tw(p.ny, v);
-  CHK(upload(c, c->L.tw_y, v.data(), v.size()));
-  // segment A fractions and node weights (trapezoid over each segment)
-  c->seg_a.assign(N, 0.0);
-  for (int j = 0; j < N; ++j) {
-    double a = p.f_A * N - j;
-    c->seg_a[j] = a < 0 ? 0.0 : (a > 1 ? 1.0 : a);
+  std::vector<double> mx, my, tx, ty;
+  mult(p.nx, mx);
+  mult(p.ny, my);
+  tw(p.nx, tx);
+  tw(p.ny, ty);
+  for (int r = 0; r < c->nrep; ++r) {
+    const size_t o = c->roff(r);
+    CHK(upload(c, o + c->L.mult_x, mx.data(), mx.size()));
+    CHK(upload(c, o + c->L.mult_y, my.data(), my.size()));
+    CHK(upload(c, o + c->L.tw_x, tx.data(), tx.size()));
+    CHK(upload(c, o + c->L.tw_y, ty.data(), ty.size()));
+    // node weights: trapezoid over each segment, split by its A fraction
+    const std::vector<double> a = segment_fractions(c->rp[r]);
+    std::vector<double> wA(N + 1, 0.0), wB(N + 1, 0.0);
+    for (int j = 0; j < N; ++j) {
+      wA[j] += 0.5 * ds * a[j];
+      wA[j + 1] += 0.5 * ds * a[j];
+      wB[j] += 0.5 * ds * (1.0 - a[j]);
+      wB[j + 1] += 0.5 * ds * (1.0 - a[j]);
+    }
+    CHK(upload(c, o + c->L.wnA, wA.data(), wA.size()));
+    CHK(upload(c, o + c->L.wnB, wB.data(), wB.size()));
+    CHK(reset_scal(c, r));
   }
-  std::vector<double> wA(N + 1, 0.0), wB(N + 1, 0.0);
-  for (int j = 0; j < N; ++j) {
-    wA[j] += 0.5 * ds * c->seg_a[j];
-    wA[j + 1] += 0.5 * ds * c->seg_a[j];
-    wB[j] += 0.5 * ds * (1.0 - c->seg_a[j]);
-    wB[j + 1] += 0.5 * ds * (1.0 - c->seg_a[j]);
-  }
-  CHK(upload(c, c->L.wnA, wA.data(), wA.size()));
-  CHK(upload(c, c->L.wnB, wB.data(), wB.size()));
-  HIPCHK(hipMemsetAsync(c->base + c->L.scal, 0, kNumScal * sizeof(double), c->stream));
-  HIPCHK(hipMemsetAsync(c->base + c->L.counters, 0, 16 * sizeof(unsigned), c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
   return EPDLB_OK;
 }
 
@@ -829,9 +866,10 @@ int upload_populations(epdlb_ctx* c, size_t off, const double* f) {
   return upload(c, off, g.data(), g.size());
 }
 
-// LB at f^eq(rho = 1, u_init); u_init the analytic reverse-Poiseuille profile.
-int init_lb(epdlb_ctx* c) {
-  const epdlb_params& p = c->p;
+// LB of replica r at f^eq(rho = 1, u_init); u_init the analytic
+// reverse-Poiseuille profile, into the current population buffer.
+int init_lb(epdlb_ctx* c, int r) {
+  const epdlb_params& p = c->rp[r];
   const size_t n = size_t(p.nx) * p.ny;
   std::vector<double> ux(p.ny, 0.0);
   if (p.init_flow) {
@@ -844,8 +882,6 @@ int init_lb(epdlb_ctx* c) {
     }
   }
   static const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-  static const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
-                              1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
   std::vector<double> f(9 * n), u(2 * n, 0.0), rho(n, 1.0);
   for (int y = 0; y < p.ny; ++y)
     for (int x = 0; x < p.nx; ++x) {
@@ -854,13 +890,32 @@ int init_lb(epdlb_ctx* c) {
       u[i] = vx;
       for (int k = 0; k < 9; ++k) {
         const double cu = cx[k] * vx;
-        f[k * n + i] = w[k] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * vx * vx);
+        f[k * n + i] = kW9[k] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * vx * vx);
       }
     }
-  c->fcur = 0;
-  CHK(upload_populations(c, c->L.fstar[0], f.data()));
-  CHK(upload(c, c->L.u, u.data(), u.size()));
-  CHK(upload(c, c->L.rho, rho.data(), rho.size()));
+  const size_t o = c->roff(r);
+  CHK(upload_populations(c, o + c->L.fstar[c->fcur], f.data()));
+  CHK(upload(c, o + c->L.u, u.data(), u.size()));
+  CHK(upload(c, o + c->L.rho, rho.data(), rho.size()));
+  return EPDLB_OK;
+}
+
+// New potentials for the replicas whose entry of `omega` is non-null: Phi =
+// Phi[omega] (recomputed for the whole group) and their LB restarted.
+int set_fields_group(epdlb_ctx* c, const double* const* omega) {
+  HIPCHK(hipSetDevice(c->device));
+  const size_t n = size_t(c->p.nx) * c->p.ny;
+  for (int r = 0; r < c->nrep; ++r) {
+    if (!omega[r]) continue;
+    CHK(upload(c, c->roff(r) + c->L.omega[c->cur], omega[r], 3 * n));
+    CHK(reset_scal(c, r));
+  }
+  CHK(compute_stats(c));
+  CHK(c->p.precision == 0 ? stage_densities<double>(c, false) : stage_densities<float>(c, false));
+  for (int r = 0; r < c->nrep; ++r)
+    if (omega[r]) CHK(init_lb(c, r));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->seeded = true;
   return EPDLB_OK;
 }
 
@@ -901,12 +956,172 @@ int get_graph(epdlb_ctx* c, int steps, hipGraphExec_t* out) {
   return EPDLB_OK;
 }
 
+// Default launch shapes (R = 8 values per lane).  Row passes: nf transforms of
+// L/R lanes per block (<= 256 lanes); column passes: NF transforms
+// interleaved, NF*L/R <= 512 lanes, NF = 8 where it fits.
+void default_shapes(epdlb_ctx* c) {
+  const epdlb_params* p = &c->p;
+  auto row_nf = [&](int L, int transforms) {
+    const int tl = L / 8;
+    return clampi(256 / tl, 1, transforms);
+  };
+  auto col_nf = [&](int L) { return (L / 8) * 8 <= 512 ? 8 : 4; };
+  c->sh_row = {8, row_nf(p->nx, p->ny / 2)};
+  c->sh_col = {8, p->precision == 0 ? 4 : col_nf(p->ny)};
+  c->sh_frow = {8, row_nf(p->nx, p->ny)};
+  c->sh_fcol = {8, p->precision == 0 ? 4 : col_nf(p->ny)};
+}
+
 int check_finite(epdlb_ctx* c) {
-  double s[kNumScal];
-  HIPCHK(hipMemcpyAsync(s, c->base + c->L.scal, sizeof(s), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  for (int i = 0; i < kNumScal; ++i)
-    if (!std::isfinite(s[i])) return fail(EPDLB_ENONFINITE, "non-finite partition function or field mean");
+  for (int r = 0; r < c->nrep; ++r) {
+    double s[kNumScal];
+    HIPCHK(hipMemcpyAsync(s, c->base + c->roff(r) + c->L.scal, sizeof(s), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < kNumScal; ++i)
+      if (!std::isfinite(s[i])) return fail(EPDLB_ENONFINITE, "non-finite partition function or field mean");
+  }
+  return EPDLB_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Batched replicas: replicas of one grid shape form a group that shares every
+// launch (blockIdx.z = replica); groups are independent branches of one
+// captured graph per step pair, forked from and joined to the batch stream.
+// ---------------------------------------------------------------------------
+struct epdlb_batch {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<epdlb_ctx*> groups;
+  std::vector<std::pair<int, int>> where;  // replica -> (group, index in group)
+  struct G {
+    int steps;
+    hipGraphExec_t exec;
+  };
+  std::vector<G> graphs;
+  hipStream_t cap = nullptr;
+  std::vector<hipStream_t> fork;
+  hipEvent_t ev_fork = nullptr;
+  std::vector<hipEvent_t> ev_join;
+  int64_t nstep = 0;
+  bool seeded = false;
+  bool prof = false;  // profiling: stream launches, group after group
+};
+
+namespace {
+
+bool same_model(const epdlb_params& a, const epdlb_params& b) {
+  return a.n_contour == b.n_contour && a.phi_P == b.phi_P && a.chi_AB == b.chi_AB && a.chi_AS == b.chi_AS &&
+         a.chi_BS == b.chi_BS && a.kappa_H == b.kappa_H && a.D_S == b.D_S && a.D_A == b.D_A &&
+         a.D_B == b.D_B && a.R_G == b.R_G && a.dx == b.dx && a.dt == b.dt && a.kT_over_v == b.kT_over_v &&
+         a.lb_tau == b.lb_tau && a.g_units == b.g_units && a.precision == b.precision &&
+         a.init_flow == b.init_flow && a.couple_lb == b.couple_lb;
+}
+
+// A group context over `rp` (same grid shape), arena allocated here.
+int make_group(const std::vector<epdlb_params>& rp, int device, epdlb_ctx** out) {
+  epdlb_ctx* c = new (std::nothrow) epdlb_ctx();
+  if (!c) return fail(EPDLB_ENOMEM, "host allocation failed");
+  c->p = rp[0];
+  c->rp = rp;
+  c->nrep = int(rp.size());
+  c->device = device;
+  if (const char* env = std::getenv("EPDLB_GRAPH")) c->use_graph = std::atoi(env) != 0;
+  c->L = make_layout(c->p);
+  c->rstride = c->L.total;
+  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return fail(EPDLB_EHIP, "hipStreamCreate failed");
+  }
+  c->own_stream = true;
+  void* m = nullptr;
+  if (hipMalloc(&m, c->rstride * c->nrep) != hipSuccess) {
+    epdlb_destroy(c);
+    return fail(EPDLB_ENOMEM, "hipMalloc of a replica group arena failed");
+  }
+  c->base = static_cast<unsigned char*>(m);
+  c->own_mem = true;
+  default_shapes(c);
+  const int r = upload_tables(c);
+  if (r != EPDLB_OK) {
+    epdlb_destroy(c);
+    return r;
+  }
+  *out = c;
+  return EPDLB_OK;
+}
+
+void drop_batch_graphs(epdlb_batch* b) {
+  for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+  b->graphs.clear();
+}
+
+// One graph of `steps` steps of every group, groups as parallel branches.
+int batch_graph(epdlb_batch* b, int steps, hipGraphExec_t* out) {
+  for (auto& g : b->graphs)
+    if (g.steps == steps) {
+      *out = g.exec;
+      return EPDLB_OK;
+    }
+  const size_t G = b->groups.size();
+  if (!b->cap) {
+    HIPCHK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+    b->fork.resize(G);
+    b->ev_join.resize(G);
+    for (size_t i = 0; i < G; ++i) {
+      HIPCHK(hipStreamCreateWithFlags(&b->fork[i], hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&b->ev_join[i], hipEventDisableTiming));
+    }
+  }
+  std::vector<int> cur0(G), fcur0(G);
+  std::vector<hipStream_t> own(G);
+  for (size_t i = 0; i < G; ++i) {
+    cur0[i] = b->groups[i]->cur;
+    fcur0[i] = b->groups[i]->fcur;
+    own[i] = b->groups[i]->stream;
+    b->groups[i]->stream = b->fork[i];
+    b->groups[i]->prof_on = false;
+  }
+  HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
+  int r = EPDLB_OK;
+  if (hipEventRecord(b->ev_fork, b->cap) != hipSuccess) r = fail(EPDLB_EHIP, "fork event");
+  for (size_t i = 0; i < G && r == EPDLB_OK; ++i) {
+    epdlb_ctx* c = b->groups[i];
+    if (hipStreamWaitEvent(b->fork[i], b->ev_fork, 0) != hipSuccess) r = fail(EPDLB_EHIP, "fork wait");
+    for (int st = 0; st < steps && r == EPDLB_OK; ++st)
+      for (int k = EPDLB_STAGE_ADVECT_UPDATE; k <= EPDLB_STAGE_LB && r == EPDLB_OK; ++k) r = run_stage(c, k);
+    if (r == EPDLB_OK && hipEventRecord(b->ev_join[i], b->fork[i]) != hipSuccess) r = fail(EPDLB_EHIP, "join");
+    if (r == EPDLB_OK && hipStreamWaitEvent(b->cap, b->ev_join[i], 0) != hipSuccess)
+      r = fail(EPDLB_EHIP, "join wait");
+  }
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->cap, &graph);
+  for (size_t i = 0; i < G; ++i) {
+    b->groups[i]->stream = own[i];
+    b->groups[i]->cur = cur0[i];
+    b->groups[i]->fcur = fcur0[i];
+  }
+  if (r != EPDLB_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return r;
+  }
+  HIPCHK(e);
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  HIPCHK(e2);
+  b->graphs.push_back({steps, exec});
+  *out = exec;
+  return EPDLB_OK;
+}
+
+int batch_replica(epdlb_batch* b, int32_t r, epdlb_ctx** c, int* idx) {
+  if (!b || r < 0 || size_t(r) >= b->where.size()) return fail(EPDLB_EINVAL, "bad batch or replica index");
+  *c = b->groups[b->where[r].first];
+  *idx = b->where[r].second;
   return EPDLB_OK;
 }
 
@@ -985,9 +1200,12 @@ int epdlb_create(const epdlb_params* p, int device, void* stream, void* workspac
   epdlb_ctx* c = new (std::nothrow) epdlb_ctx();
   if (!c) return fail(EPDLB_ENOMEM, "host allocation failed");
   c->p = *p;
+  c->rp.assign(1, *p);
+  c->nrep = 1;
   c->device = device;
   if (const char* env = std::getenv("EPDLB_GRAPH")) c->use_graph = std::atoi(env) != 0;
   c->L = make_layout(*p);
+  c->rstride = c->L.total;
   if (stream) {
     c->stream = reinterpret_cast<hipStream_t>(stream);
   } else {
@@ -1012,18 +1230,7 @@ int epdlb_create(const epdlb_params* p, int device, void* stream, void* workspac
     c->base = static_cast<unsigned char*>(m);
     c->own_mem = true;
   }
-  // launch shapes (defaults; R = 8 values per lane).  Row passes: nf
-  // transforms of L/R lanes per block (<= 256 lanes); column passes: NF
-  // transforms interleaved, NF*L/R <= 512 lanes, NF = 8 where it fits.
-  auto row_nf = [&](int L, int transforms) {
-    const int tl = L / 8;
-    return clampi(256 / tl, 1, transforms);
-  };
-  auto col_nf = [&](int L) { return (L / 8) * 8 <= 512 ? 8 : 4; };
-  c->sh_row = {8, row_nf(p->nx, p->ny / 2)};
-  c->sh_col = {8, p->precision == 0 ? 4 : col_nf(p->ny)};
-  c->sh_frow = {8, row_nf(p->nx, p->ny)};
-  c->sh_fcol = {8, p->precision == 0 ? 4 : col_nf(p->ny)};
+  default_shapes(c);
   int r = upload_tables(c);
   if (r != EPDLB_OK) {
     epdlb_destroy(c);
@@ -1035,16 +1242,9 @@ int epdlb_create(const epdlb_params* p, int device, void* stream, void* workspac
 
 int epdlb_set_fields(epdlb_ctx* c, const double* omega) {
   if (!c || !omega) return fail(EPDLB_EINVAL, "NULL argument");
-  HIPCHK(hipSetDevice(c->device));
-  const size_t n = size_t(c->p.nx) * c->p.ny;
   c->cur = 0;
-  CHK(upload(c, c->L.omega[0], omega, 3 * n));
-  HIPCHK(hipMemsetAsync(c->base + c->L.scal, 0, kNumScal * sizeof(double), c->stream));
-  CHK(compute_stats(c));
-  CHK(c->p.precision == 0 ? stage_densities<double>(c, false) : stage_densities<float>(c, false));
-  CHK(init_lb(c));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  c->seeded = true;
+  c->fcur = 0;
+  CHK(set_fields_group(c, &omega));
   c->nstep = 0;
   return check_finite(c);
 }
@@ -1067,7 +1267,7 @@ int epdlb_set_state(epdlb_ctx* c, const double* omega, const double* phi, const 
   CHK(upload(c, c->L.phi, phi, 3 * n));
   CHK(upload_populations(c, c->L.fstar[0], fstar));
   CHK(upload(c, c->L.u, u, 2 * n));
-  HIPCHK(hipMemsetAsync(c->base + c->L.scal, 0, kNumScal * sizeof(double), c->stream));
+  CHK(reset_scal(c, 0));
   CHK(compute_stats(c));
   HIPCHK(hipStreamSynchronize(c->stream));
   c->seeded = true;
@@ -1338,6 +1538,272 @@ void epdlb_destroy(epdlb_ctx* c) {
   if (c->own_mem && c->base) (void)hipFree(c->base);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
+}
+
+int epdlb_batch_create(const epdlb_params* params, int32_t n_replicas, int device, void* stream,
+                       epdlb_batch** out) {
+  if (!params || n_replicas < 1 || !out) return fail(EPDLB_EINVAL, "bad batch arguments");
+  *out = nullptr;
+  for (int r = 0; r < n_replicas; ++r) {
+    CHK(validate(&params[r]));
+    if (!same_model(params[0], params[r]))
+      return fail(EPDLB_EINVAL, "replicas may differ only in nx, ny, g and f_A");
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= device || device < 0)
+    return fail(EPDLB_ENODEV, "no HIP device with that index");
+  HIPCHK(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(EPDLB_ENODEV, std::string("library built for gfx950, device is ") + prop.gcnArchName);
+  epdlb_batch* b = new (std::nothrow) epdlb_batch();
+  if (!b) return fail(EPDLB_ENOMEM, "host allocation failed");
+  b->device = device;
+  if (stream) {
+    b->stream = reinterpret_cast<hipStream_t>(stream);
+  } else {
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete b;
+      return fail(EPDLB_EHIP, "hipStreamCreate failed");
+    }
+    b->own_stream = true;
+  }
+  // group by grid shape and A fraction (which fixes every launch's segment
+  // fractions), keeping first-appearance order
+  std::vector<std::tuple<int, int, double>> shapes;
+  std::vector<std::vector<int>> members;
+  b->where.resize(n_replicas);
+  for (int r = 0; r < n_replicas; ++r) {
+    const std::tuple<int, int, double> sh{params[r].nx, params[r].ny, params[r].f_A};
+    size_t g = 0;
+    while (g < shapes.size() && shapes[g] != sh) ++g;
+    if (g == shapes.size()) {
+      shapes.push_back(sh);
+      members.emplace_back();
+    }
+    b->where[r] = {int(g), int(members[g].size())};
+    members[g].push_back(r);
+  }
+  for (size_t g = 0; g < shapes.size(); ++g) {
+    std::vector<epdlb_params> rp;
+    for (int r : members[g]) rp.push_back(params[r]);
+    epdlb_ctx* c = nullptr;
+    const int rc = make_group(rp, device, &c);
+    if (rc != EPDLB_OK) {
+      epdlb_batch_destroy(b);
+      return rc;
+    }
+    b->groups.push_back(c);
+  }
+  *out = b;
+  return EPDLB_OK;
+}
+
+int epdlb_batch_seed(epdlb_batch* b, const uint64_t* seeds, double sigma) {
+  if (!b || !seeds) return fail(EPDLB_EINVAL, "NULL argument");
+  for (size_t g = 0; g < b->groups.size(); ++g) {
+    epdlb_ctx* c = b->groups[g];
+    const size_t n3 = size_t(3) * c->p.nx * c->p.ny;
+    std::vector<std::vector<double>> w(c->nrep, std::vector<double>(n3));
+    std::vector<const double*> ptrs(c->nrep);
+    for (size_t r = 0; r < b->where.size(); ++r)
+      if (b->where[r].first == int(g)) {
+        const int i = b->where[r].second;
+        CHK(epdlb_noise_fill(seeds[r], sigma, c->p.nx, c->p.ny, w[i].data()));
+        ptrs[i] = w[i].data();
+      }
+    c->cur = 0;
+    c->fcur = 0;
+    CHK(set_fields_group(c, ptrs.data()));
+    c->nstep = 0;
+    CHK(check_finite(c));
+  }
+  b->nstep = 0;
+  b->seeded = true;
+  return EPDLB_OK;
+}
+
+int epdlb_batch_set_fields(epdlb_batch* b, int32_t replica, const double* omega) {
+  epdlb_ctx* c;
+  int i;
+  CHK(batch_replica(b, replica, &c, &i));
+  if (!omega || !b->seeded) return fail(EPDLB_ESTATE, "seed the batch before replacing one replica");
+  std::vector<const double*> ptrs(c->nrep, nullptr);
+  ptrs[i] = omega;
+  CHK(set_fields_group(c, ptrs.data()));
+  return check_finite(c);
+}
+
+int epdlb_batch_step(epdlb_batch* b, int64_t n) {
+  if (!b) return fail(EPDLB_EINVAL, "batch is NULL");
+  if (!b->seeded) return fail(EPDLB_ESTATE, "step before seed");
+  if (n < 0) return fail(EPDLB_EINVAL, "negative step count");
+  HIPCHK(hipSetDevice(b->device));
+  if (b->prof) {
+    // profiled steps: each group's launches on the batch stream, in order
+    for (int64_t s = 0; s < n; ++s) {
+      for (auto* c : b->groups) {
+        hipStream_t own = c->stream;
+        c->stream = b->stream;
+        int r = EPDLB_OK;
+        for (int k = EPDLB_STAGE_ADVECT_UPDATE; k <= EPDLB_STAGE_LB && r == EPDLB_OK; ++k) r = run_stage(c, k);
+        c->stream = own;
+        CHK(r);
+        ++c->nstep;
+      }
+      ++b->nstep;
+    }
+    drop_batch_graphs(b);  // parities may have changed
+    return EPDLB_OK;
+  }
+  // the graphs' branches start after work already queued on the batch stream
+  while (n > 0) {
+    const int k = n >= 2 ? 2 : 1;
+    hipGraphExec_t g;
+    CHK(batch_graph(b, k, &g));
+    HIPCHK(hipGraphLaunch(g, b->stream));
+    if (k == 1) {
+      for (auto* c : b->groups) {
+        c->cur = 1 - c->cur;
+        c->fcur = 1 - c->fcur;
+      }
+      drop_batch_graphs(b);  // parities changed: recapture from the new state
+    }
+    for (auto* c : b->groups) c->nstep += k;
+    b->nstep += k;
+    n -= k;
+  }
+  return EPDLB_OK;
+}
+
+int epdlb_batch_sync(epdlb_batch* b) {
+  if (!b) return fail(EPDLB_EINVAL, "batch is NULL");
+  HIPCHK(hipStreamSynchronize(b->stream));
+  for (auto* c : b->groups) CHK(check_finite(c));
+  return EPDLB_OK;
+}
+
+int epdlb_batch_read_densities(epdlb_batch* b, int32_t replica, double* pa, double* pb, double* ps) {
+  epdlb_ctx* c;
+  int i;
+  CHK(batch_replica(b, replica, &c, &i));
+  if (!pa || !pb || !ps) return fail(EPDLB_EINVAL, "NULL argument");
+  HIPCHK(hipStreamSynchronize(b->stream));
+  const size_t n = size_t(c->p.nx) * c->p.ny, pl = n * elem(c), o = c->roff(i) + c->L.phi;
+  CHK(download(c, o, pa, n));
+  CHK(download(c, o + pl, pb, n));
+  return download(c, o + 2 * pl, ps, n);
+}
+
+int epdlb_batch_read_fields(epdlb_batch* b, int32_t replica, double* wa, double* wb, double* ws) {
+  epdlb_ctx* c;
+  int i;
+  CHK(batch_replica(b, replica, &c, &i));
+  if (!wa || !wb || !ws) return fail(EPDLB_EINVAL, "NULL argument");
+  HIPCHK(hipStreamSynchronize(b->stream));
+  const size_t n = size_t(c->p.nx) * c->p.ny, pl = n * elem(c), o = c->roff(i) + c->L.omega[c->cur];
+  CHK(download(c, o, wa, n));
+  CHK(download(c, o + pl, wb, n));
+  return download(c, o + 2 * pl, ws, n);
+}
+
+int epdlb_batch_read_velocity(epdlb_batch* b, int32_t replica, double* rho, double* ux, double* uy) {
+  epdlb_ctx* c;
+  int i;
+  CHK(batch_replica(b, replica, &c, &i));
+  if (!rho || !ux || !uy) return fail(EPDLB_EINVAL, "NULL argument");
+  HIPCHK(hipStreamSynchronize(b->stream));
+  const size_t n = size_t(c->p.nx) * c->p.ny, pl = n * elem(c), o = c->roff(i);
+  CHK(download(c, o + c->L.rho, rho, n));
+  CHK(download(c, o + c->L.u, ux, n));
+  return download(c, o + c->L.u + pl, uy, n);
+}
+
+int epdlb_batch_read_diag(epdlb_batch* b, int32_t replica, epdlb_diag* d) {
+  epdlb_ctx* c;
+  int i;
+  CHK(batch_replica(b, replica, &c, &i));
+  if (!d) return fail(EPDLB_EINVAL, "NULL argument");
+  HIPCHK(hipStreamSynchronize(b->stream));
+  double s[kNumScal];
+  HIPCHK(hipMemcpyAsync(s, c->base + c->roff(i) + c->L.scal, sizeof(s), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  d->step = b->nstep;
+  d->Q_P = s[kQPf];
+  d->Q_P_bwd = s[kQPb];
+  d->Q_S = s[kQS];
+  d->gauge_S = s[kGaugeS];
+  d->mean_omega[0] = s[kMeanA];
+  d->mean_omega[1] = s[kMeanB];
+  d->mean_omega[2] = s[kMeanS];
+  return EPDLB_OK;
+}
+
+int epdlb_batch_autotune(epdlb_batch* b, int32_t reps, const char* cache_path) {
+  if (!b) return fail(EPDLB_EINVAL, "batch is NULL");
+  HIPCHK(hipStreamSynchronize(b->stream));
+  for (auto* c : b->groups) CHK(epdlb_autotune(c, reps, cache_path));
+  drop_batch_graphs(b);
+  return EPDLB_OK;
+}
+
+int epdlb_batch_profile_start(epdlb_batch* b, int32_t max_launches) {
+  if (!b) return fail(EPDLB_EINVAL, "batch is NULL");
+  for (auto* c : b->groups) CHK(epdlb_profile_start(c, max_launches));
+  b->prof = true;
+  return EPDLB_OK;
+}
+
+int epdlb_batch_profile_read(epdlb_batch* b, epdlb_kernel_stat* out, int32_t cap, int32_t* n_out) {
+  if (!b || !out || !n_out || cap < 1) return fail(EPDLB_EINVAL, "bad profile arguments");
+  HIPCHK(hipStreamSynchronize(b->stream));
+  std::vector<epdlb_kernel_stat> all;
+  for (auto* c : b->groups) {
+    epdlb_kernel_stat tmp[32];
+    int32_t n = 0;
+    CHK(epdlb_profile_read(c, tmp, 32, &n));
+    for (int i = 0; i < n; ++i) {
+      bool merged = false;
+      for (auto& a : all)
+        if (std::strcmp(a.name, tmp[i].name) == 0) {
+          a.launches += tmp[i].launches;
+          a.total_ms += tmp[i].total_ms;
+          a.min_ms = std::min(a.min_ms, tmp[i].min_ms);
+          a.max_ms = std::max(a.max_ms, tmp[i].max_ms);
+          merged = true;
+        }
+      if (!merged) all.push_back(tmp[i]);
+    }
+  }
+  int n = 0;
+  for (auto& a : all)
+    if (n < cap) out[n++] = a;
+  *n_out = n;
+  b->prof = false;
+  return EPDLB_OK;
+}
+
+int epdlb_batch_info(epdlb_batch* b, int32_t* n_groups, int64_t* sites) {
+  if (!b || !n_groups || !sites) return fail(EPDLB_EINVAL, "NULL argument");
+  *n_groups = int32_t(b->groups.size());
+  int64_t s = 0;
+  for (auto* c : b->groups) s += int64_t(c->nrep) * c->p.nx * c->p.ny;
+  *sites = s;
+  return EPDLB_OK;
+}
+
+void epdlb_batch_destroy(epdlb_batch* b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  drop_batch_graphs(b);
+  for (auto* c : b->groups) epdlb_destroy(c);
+  for (auto s : b->fork) (void)hipStreamDestroy(s);
+  for (auto e : b->ev_join) (void)hipEventDestroy(e);
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
 }
 
 const char* epdlb_last_error(void) { return g_err.c_str(); }

@@ -15,6 +15,7 @@ enum Scal : int {
   kMeanA = 0, kMeanB = 1, kMeanS = 2,  // site means of the current omega planes
   kQS = 3, kGaugeS = 4,                 // Q_S and the constant it was computed with
   kQPf = 5, kQPb = 6,                   // Q_P from the forward and backward chains
+  kGext = 7,                            // reverse-Poiseuille force amplitude, lattice units
   kNumScal = 8
 };
 
@@ -25,6 +26,13 @@ enum Scal : int {
 // neighbouring tiles (which share cache lines and halos) in one L2.
 // ---------------------------------------------------------------------------
 constexpr int kNumXcd = 8;
+
+// Replicas of one grid shape share a launch: replica z's planes, tables and
+// scalars sit `rs` bytes after replica z-1's (blockIdx.z = z).
+template <class X>
+__device__ __forceinline__ X* sh(X* p, long off) {
+  return (X*)((const char*)p + off);
+}
 __device__ __forceinline__ int xcd_tile(int linear, int total) {
   if (total % kNumXcd) return linear;
   return (linear % kNumXcd) * (total / kNumXcd) + linear / kNumXcd;
@@ -87,8 +95,10 @@ __device__ __forceinline__ void sum_partials(const double* partials, int nslots,
 // Finishes the field statistics: partials of (sum w_A, sum w_B, sum w_S,
 // sum exp(-(w_S - gauge))) -> means, Q_S and the gauge it used.  One block.
 __global__ void __launch_bounds__(256) k_finish_stats(const double* partials, int nslots, double* scal,
-                                                      long n, double dA) {
+                                                      long n, double dA, long rs) {
   __shared__ double red[16 * 4];
+  partials = sh(partials, long(blockIdx.z) * rs);
+  scal = sh(scal, long(blockIdx.z) * rs);
   double acc[4];
   sum_partials<4>(partials, nslots, acc, red);
   if (threadIdx.x == 0) {
@@ -130,7 +140,16 @@ template <typename T> struct PropArgs {
   T frac[2][2];           // A fraction of the segment used by chain c at step a (+0/+1)
   double* partials;       // last: per-block sums of q_N, chain c at [c*gridDim.x]
   int nf;                 // transforms per block (row kernels)
+  int nrep;               // replicas in the launch (gridDim.z)
+  long rs;                // replica stride in bytes
+  __device__ void shift(long o) {
+    wA = sh(wA, o), wB = sh(wB, o), EA = sh(EA, o), EB = sh(EB, o), scal = sh(scal, o);
+    q[0] = sh(q[0], o), q[1] = sh(q[1], o), tmp = sh(tmp, o), mult_x = sh(mult_x, o);
+    mult_y = sh(mult_y, o), tw_x = sh(tw_x, o), tw_y = sh(tw_y, o);
+    partials = sh(partials, o);
+  }
 };
+
 
 template <typename T>
 __device__ __forceinline__ T boltz(T wa, T wb, T a, T ca, T cb) {
@@ -161,7 +180,9 @@ __device__ __forceinline__ T2<T> efactor2(const PropArgs<T>& P, T fr, T ca, T cb
 
 // Both half-step factor planes of the current potentials.
 template <typename T>
-__global__ void __launch_bounds__(256) k_boltzmann(const T* w, T* E, const double* scal, long n) {
+__global__ void __launch_bounds__(256) k_boltzmann(const T* w, T* E, const double* scal, long n, long rs) {
+  const long o = long(blockIdx.z) * rs;
+  w = sh(w, o), E = sh(E, o), scal = sh(scal, o);
   const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   E[i] = exp(T(-0.5) * (w[i] - T(scal[kMeanA])));
@@ -191,12 +212,13 @@ __global__ void __launch_bounds__(512) k_prop_row(PropArgs<T> P) {
   __shared__ double red[16 * 1];
   const int f = threadIdx.x / TL, j = threadIdx.x % TL;
   V lds{reinterpret_cast<T2<T>*>(smem_raw), f};
+  P.shift(long(blockIdx.z) * P.rs);
   const int c = blockIdx.y;
   const int rp = blockIdx.x * P.nf + f;
   const bool active = rp < P.ny / 2;
   const long r0 = long(2 * rp) * P.nx, r1 = r0 + P.nx;
   const T ca = T(P.scal[kMeanA]), cb = T(P.scal[kMeanB]);
-  const T fr0 = P.frac[c][0], fr1 = P.frac[c][1];
+  const T fr0 = c == 0 ? P.frac[0][0] : P.frac[1][0], fr1 = c == 0 ? P.frac[0][1] : P.frac[1][1];
   Twiddles<T, L, R> twf, twi;
   load_fwd_twiddles(twf, j, P.tw_x);
   load_inv_twiddles(twi, j, P.tw_x);
@@ -227,7 +249,7 @@ __global__ void __launch_bounds__(512) k_prop_row(PropArgs<T> P) {
   convolve(re, im, j, lds, twf, twi, g);
   double qsum = 0.0;
   if (P.mid) {
-    T* qo = P.q[c] + long(P.a) * P.plane;
+    T* qo = (c == 0 ? P.q[0] : P.q[1]) + long(P.a) * P.plane;
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       const int x = j + TL * m;
@@ -274,20 +296,21 @@ __global__ void __launch_bounds__(512) k_prop_row(PropArgs<T> P) {
 // transforms per block interleaved lane by lane so that each global access
 // of a wavefront covers NF consecutive column pairs.
 template <typename T, int L, int R, int NF>
-__global__ void __launch_bounds__(1024) k_prop_col(PropArgs<T> P) {
+__global__ void __launch_bounds__(512) k_prop_col(PropArgs<T> P) {
   constexpr int TL = L / R;
   using V = LdsView<T, L, R, false, NF>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16 * 1];
   const int f = threadIdx.x % NF, j = threadIdx.x / NF;
   V lds{reinterpret_cast<T2<T>*>(smem_raw), f};
+  P.shift(long(blockIdx.z) * P.rs);
   const int lt = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
   const int c = lt / gridDim.x, tile = lt % gridDim.x;
   const int cp = tile * NF + f;
   const bool active = cp < P.nx / 2;
   const int x0 = 2 * cp;
   const T ca = T(P.scal[kMeanA]), cb = T(P.scal[kMeanB]);
-  const T fr0 = P.frac[c][0], fr1 = P.frac[c][1];
+  const T fr0 = c == 0 ? P.frac[0][0] : P.frac[1][0], fr1 = c == 0 ? P.frac[0][1] : P.frac[1][1];
   Twiddles<T, L, R> twf, twi;
   load_fwd_twiddles(twf, j, P.tw_y);
   load_inv_twiddles(twi, j, P.tw_y);
@@ -322,7 +345,7 @@ __global__ void __launch_bounds__(1024) k_prop_col(PropArgs<T> P) {
   convolve(re, im, j, lds, twf, twi, g);
   double qsum = 0.0;
   if (P.mid) {
-    T2<T>* qo = reinterpret_cast<T2<T>*>(P.q[c] + long(P.a) * P.plane);
+    T2<T>* qo = reinterpret_cast<T2<T>*>((c == 0 ? P.q[0] : P.q[1]) + long(P.a) * P.plane);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       const long i2 = (long(j + TL * m) * P.nx + x0) >> 1;
@@ -385,12 +408,21 @@ template <typename T> struct DensArgs {
   long n;        // sites
   int N;
   double V, phiP, phiSbar, invDA, invDB, invDS;
+  int nrep;
+  long rs;
+  __device__ void shift(long o) {
+    qpart = sh(qpart, o), scal_out = sh(scal_out, o), q[0] = sh(q[0], o), q[1] = sh(q[1], o);
+    wS = sh(wS, o), stilde = sh(stilde, o), phi = sh(phi, o), scal = sh(scal, o);
+    wnA = sh(wnA, o), wnB = sh(wnB, o);
+    if (S) S = sh(S, o);
+  }
 };
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_density(DensArgs<T> P) {
   __shared__ double red[16 * 2];
   __shared__ double qp_s;
+  P.shift(long(blockIdx.z) * P.rs);
   {
     // Q_P from the column-pass partials, in fixed order (same in every block)
     double acc[2];
@@ -449,11 +481,15 @@ template <typename T> struct StatArgs {
   long n;
   double* scal;
   double* partials;
+  int nrep;
+  long rs;
+  __device__ void shift(long o) { w = sh(w, o), scal = sh(scal, o), partials = sh(partials, o); }
 };
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_field_stats(StatArgs<T> P) {
   __shared__ double red[16 * 4];
+  P.shift(long(blockIdx.z) * P.rs);
   const double cS = P.scal[kMeanS];
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < P.n; i += long(gridDim.x) * blockDim.x) {
@@ -489,6 +525,12 @@ template <typename T> struct UpdArgs {
   T coef[3];       // D_I dt / dx^2
   T invD[3];
   int advect;      // 0: no flow coupling
+  int nrep;
+  long rs;
+  __device__ void shift(long o) {
+    phi = sh(phi, o), w = sh(w, o), u = sh(u, o), wout = sh(wout, o), stilde = sh(stilde, o);
+    scal = sh(scal, o), partials = sh(partials, o);
+  }
 };
 
 template <typename T>
@@ -497,6 +539,7 @@ __global__ void __launch_bounds__(256) k_advect_update(UpdArgs<T> P) {
   __shared__ T sMu[3][kMY][kMX];
   __shared__ T sWt[3][kMY][kMX];
   __shared__ double red[16 * 4];
+  P.shift(long(blockIdx.z) * P.rs);
   const int lt = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
   const int tx0 = (lt % gridDim.x) * kTX, ty0 = (lt / gridDim.x) * kTY;
   const int tid = threadIdx.x;
@@ -594,8 +637,14 @@ template <typename T> struct ForceArgs {
   double kx0, ky0;      // 2 pi/(nx dx), 2 pi/(ny dx)
   double pref;          // (kT/v)/dt / (nx ny)
   double conv;          // dt^2/dx (physical -> lattice), 0 if uncoupled
-  double gext;          // external force amplitude in lattice units
+  const double* scal;   // kGext: external force amplitude in lattice units
   int nf;
+  int nrep;
+  long rs;
+  __device__ void shift(long o) {
+    S = sh(S, o), spec = sh(spec, o), F = sh(F, o), tw_x = sh(tw_x, o), tw_y = sh(tw_y, o);
+    scal = sh(scal, o);
+  }
 };
 
 template <typename T, int L, int R>
@@ -605,6 +654,7 @@ __global__ void __launch_bounds__(512) k_force_row_fwd(ForceArgs<T> P) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int f = threadIdx.x / TL, j = threadIdx.x % TL;
   V lds{reinterpret_cast<T2<T>*>(smem_raw), f};
+  P.shift(long(blockIdx.z) * P.rs);
   const int y = blockIdx.x * P.nf + f;
   const bool active = y < P.ny;
   Twiddles<T, L, R> twf;
@@ -628,12 +678,13 @@ __global__ void __launch_bounds__(512) k_force_row_fwd(ForceArgs<T> P) {
 }
 
 template <typename T, int L, int R, int NF>
-__global__ void __launch_bounds__(1024) k_force_col(ForceArgs<T> P) {
+__global__ void __launch_bounds__(512) k_force_col(ForceArgs<T> P) {
   constexpr int TL = L / R;
   using V = LdsView<T, L, R, false, NF>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int f = threadIdx.x % NF, j = threadIdx.x / NF;
   V lds{reinterpret_cast<T2<T>*>(smem_raw), f};
+  P.shift(long(blockIdx.z) * P.rs);
   const int kxi = xcd_tile(blockIdx.x, gridDim.x) * NF + f;   // column = x wavenumber index
   const bool active = kxi < P.nx;
   Twiddles<T, L, R> twf, twi;
@@ -686,6 +737,7 @@ __global__ void __launch_bounds__(512) k_force_row_inv(ForceArgs<T> P) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int f = threadIdx.x / TL, j = threadIdx.x % TL;
   V lds{reinterpret_cast<T2<T>*>(smem_raw), f};
+  P.shift(long(blockIdx.z) * P.rs);
   const int y = blockIdx.x * P.nf + f;
   const bool active = y < P.ny;
   Twiddles<T, L, R> twi;
@@ -703,7 +755,8 @@ __global__ void __launch_bounds__(512) k_force_row_inv(ForceArgs<T> P) {
   fft_inverse(re, im, j, lds, twi);
   if (active) {
     const T conv = T(P.conv);
-    const T fext = T(y < P.ny / 2 ? -P.gext : P.gext);
+    const double g = P.scal[kGext];
+    const T fext = T(y < P.ny / 2 ? -g : g);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       const long i = long(y) * P.nx + j + TL * m;
@@ -728,10 +781,16 @@ template <typename T> struct LbArgs {
   long n;
   T omega;         // 1/tau
   T fpre;          // 1 - 1/(2 tau)
+  int nrep;
+  long rs;
+  __device__ void shift(long o) {
+    fin = sh(fin, o), fout = sh(fout, o), F = sh(F, o), rho = sh(rho, o), u = sh(u, o);
+  }
 };
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_lb(LbArgs<T> P) {
+  P.shift(long(blockIdx.z) * P.rs);
   const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= P.n) return;
   const int x = int(i & (P.nx - 1));
