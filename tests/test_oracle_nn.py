@@ -1,0 +1,101 @@
+"""Pins of the surrogate oracle: gradients by central differences, the
+dilated periodic convolution by brute-force loops, Adam by its definition on a
+quadratic, and the renormalised densities' exact means."""
+import numpy as np
+
+from oracle import nn_oracle as NN
+
+
+def small_params(rng, chans=(5, 4, 4, 3, 2)):
+    ps = []
+    for ci, co in zip(chans[:-1], chans[1:]):
+        ps.append((0.4 * rng.standard_normal((9, ci, co)), 0.1 * rng.standard_normal(co)))
+    return ps
+
+
+def test_conv_matches_loops():
+    rng = np.random.default_rng(0)
+    a = rng.standard_normal((6, 7, 3))
+    W = rng.standard_normal((9, 3, 2))
+    b = rng.standard_normal(2)
+    for d in (1, 2, 4):
+        out = NN.conv(a, W, b, d)
+        ref = np.zeros((6, 7, 2))
+        for y in range(6):
+            for x in range(7):
+                acc = b.copy()
+                for t, (ty, tx) in enumerate(NN.TAPS):
+                    acc += a[(y + ty * d) % 6, (x + tx * d) % 7] @ W[t]
+                ref[y, x] = acc
+        assert np.max(np.abs(out - ref)) < 1e-13
+
+
+def test_gradients_by_central_differences():
+    rng = np.random.default_rng(1)
+    params = small_params(rng)
+    x = rng.standard_normal((8, 8, 5))
+    target = 0.05 + 0.01 * rng.random((8, 8, 2))
+
+    def loss(ps):
+        o, _ = NN.forward(ps, x)
+        return NN.loss_and_grad_output(o, target, 0.1)[0]
+
+    o, cache = NN.forward(params, x)
+    _, go = NN.loss_and_grad_output(o, target, 0.1)
+    grads = NN.backward(params, cache, go)
+    h = 1e-6
+    for l in range(4):
+        W, b = params[l]
+        for idx in [(0, 0, 0), (4, W.shape[1] - 1, W.shape[2] - 1), (7, 1, 0)]:
+            Wp = W.copy(); Wp[idx] += h
+            Wm = W.copy(); Wm[idx] -= h
+            pp = list(params); pp[l] = (Wp, b)
+            pm = list(params); pm[l] = (Wm, b)
+            fd = (loss(pp) - loss(pm)) / (2 * h)
+            assert abs(fd - grads[l][0][idx]) < 1e-6 * max(1.0, abs(fd)), (l, idx, fd, grads[l][0][idx])
+        bp = b.copy(); bp[0] += h
+        bm = b.copy(); bm[0] -= h
+        pp = list(params); pp[l] = (W, bp)
+        pm = list(params); pm[l] = (W, bm)
+        fd = (loss(pp) - loss(pm)) / (2 * h)
+        assert abs(fd - grads[l][1][0]) < 1e-6 * max(1.0, abs(fd))
+
+
+def test_input_gradient_is_adjoint():
+    """<g, conv(a)> = <conv_input_grad(g), a> + <g, bias> for random a, g (adjoint identity)."""
+    rng = np.random.default_rng(2)
+    a = rng.standard_normal((8, 6, 3))
+    g = rng.standard_normal((8, 6, 4))
+    W = rng.standard_normal((9, 3, 4))
+    for d in (1, 2, 8):
+        lhs = np.sum(g * NN.conv(a, W, np.zeros(4), d))
+        rhs = np.sum(NN.conv_input_grad(g, W, d) * a)
+        assert abs(lhs - rhs) < 1e-10 * abs(lhs)
+        gw = NN.conv_weight_grad(a, g, d)
+        assert abs(np.sum(gw * W) - lhs) < 1e-10 * abs(lhs)
+
+
+def test_adam_on_quadratic():
+    """Adam's first step moves each coordinate by lr against the gradient sign
+    (bias-corrected m/sqrt(v) = g/|g|); many steps reach the minimum."""
+    theta = np.array([3.0, -2.0])
+    m = np.zeros(2)
+    v = np.zeros(2)
+    t1, m, v = NN.adam_update(theta, 2 * theta, m, v, 1, 0.1)
+    assert np.allclose(t1, theta - 0.1 * np.sign(theta), atol=1e-7)
+    th = t1
+    for t in range(2, 600):
+        th, m, v = NN.adam_update(th, 2 * th, m, v, t, 0.05)
+    assert np.max(np.abs(th)) < 1e-2
+
+
+def test_surrogate_densities_have_exact_means():
+    rng = np.random.default_rng(3)
+    params = small_params(rng)
+    omega = 0.3 * rng.standard_normal((3, 8, 8))
+    p = dict(f_A=0.3, phi_P=0.15, n_contour=16)
+    phi = NN.predict_densities(params, omega, p)
+    assert abs(phi[0].mean() - 0.3 * 0.15) < 1e-15
+    assert abs(phi[1].mean() - 0.7 * 0.15) < 1e-15
+    assert abs(phi[2].mean() - 0.85) < 1e-15
+    assert np.all(phi > 0)
