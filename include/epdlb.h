@@ -68,6 +68,17 @@ typedef struct {
   int32_t precision;     /* 0: FP64 everywhere; 1: FP32 fields, FP64 reductions */
   int32_t init_flow;     /* 1: start LB from the analytic profile (Eq. flow_field) */
   int32_t couple_lb;     /* 1: flow advects the fields and the polymer force drives the flow */
+  /* Density evaluation.  0: chain propagators every step (Sec. II).  1: the
+   * convolutional surrogate (epdlb_surrogate_set_weights) between exact
+   * steps; an exact step every fallback_every steps and whenever the
+   * surrogate's incompressibility residual max|sum_I Phi_I - 1| exceeds the
+   * last exact step's by more than resid_tol.  The residual is read by the
+   * host every check_every steps, one interval behind the device, so a
+   * triggered exact step comes at most 2*check_every steps late. */
+  int32_t density_mode;
+  int32_t fallback_every; /* default 50 */
+  int32_t check_every;    /* default 10 */
+  double resid_tol;       /* default 1e-3 */
 } epdlb_params;
 
 /* Scalars maintained on the device (FP64). */
@@ -78,6 +89,13 @@ typedef struct {
   double Q_S;            /* solvent partition function (with gauge_S below) */
   double gauge_S;        /* constant subtracted from omega_S for Q_S */
   double mean_omega[3];  /* site means of omega_A, omega_B, omega_S */
+  /* density_mode 1 (zero otherwise) */
+  int64_t n_exact;       /* exact steps since seeding */
+  int64_t n_triggered;   /* of which forced by the residual test */
+  double nn_err_last;    /* max over sites, A and B, of |Phi_NN - Phi_exact| at the last exact step */
+  double nn_err_max;     /* maximum of nn_err_last over all exact steps (and the seed) */
+  double resid_nn_max;   /* max |sum_I Phi_I - 1| over surrogate steps since seeding */
+  double resid_exact;    /* the same for the last exact step */
 } epdlb_diag;
 
 /* Stage identifiers for epdlb_run_stage (one hybrid step = 1, 2, 3, 4). */
@@ -217,6 +235,61 @@ int epdlb_batch_profile_read(epdlb_batch* b, epdlb_kernel_stat* out, int32_t cap
 /* Number of replica groups (grid shape, A fraction) and total lattice sites. */
 int epdlb_batch_info(epdlb_batch* b, int32_t* n_groups, int64_t* sites);
 void epdlb_batch_destroy(epdlb_batch* b);
+
+/* ---------------------------------------------------------------------------
+ * Density surrogate.  A 4-layer dilated (1, 2, 4, 8) 3x3 convolutional
+ * network, 64 channels, SiLU, in BF16 with FP32 accumulation (MFMA), maps
+ * the potentials to the copolymer densities: inputs w_I - <w_I> (I = A, B,
+ * S), f_A and 1/N; outputs Phi_hat_A, Phi_hat_B = softplus(o), rescaled to
+ * the exact means f_A phibar_P and (1 - f_A) phibar_P; Phi_S from its closed
+ * form (Sec. II, Eqs. for Phi_P, Phi_S and Q_S).  It stands in for the chain
+ * propagators (Sec. II, modified diffusion equations and split step) between
+ * exact steps.  At an exact step both are evaluated: the exact densities
+ * become the state, the network's error against them is recorded, and the
+ * force source S keeps differencing network densities at both ends of the
+ * step (the next step corrects S~ by the recorded difference).
+ *
+ * Weights: EPDLB_NN_PARAMS host floats, for layer l = 0..3 the tensor
+ * W_l[9][cin][cout] (tap t = 3*(ty+1) + (tx+1), offsets d_l*(ty, tx)) then
+ * b_l[cout]; cin = 5, 64, 64, 64; cout = 64, 64, 64, 2.
+ * ------------------------------------------------------------------------- */
+#define EPDLB_NN_PARAMS 77954
+
+/* Load weights into a context created with density_mode = 1 (copied; the
+ * caller keeps `w`).  Required before epdlb_step.  EINVAL on a count other
+ * than EPDLB_NN_PARAMS or a non-finite weight; ESTATE for density_mode 0. */
+int epdlb_surrogate_set_weights(epdlb_ctx* ctx, const float* w, int64_t count);
+
+/* Trainer: a device dataset of `capacity` (potentials -> densities) pairs on
+ * an nx x ny grid, mini-batches of up to max_batch pairs, mean squared error
+ * of (Phi_hat - Phi)/phi_scale over sites and species A, B, Adam
+ * (b1 = 0.9, b2 = 0.999, eps = 1e-8) on FP32 master weights.  The trainer
+ * allocates its device memory; `stream` as in epdlb_create. */
+typedef struct epdlb_nn epdlb_nn;
+int epdlb_nn_create(int32_t nx, int32_t ny, int32_t capacity, int32_t max_batch, int device, void* stream,
+                    epdlb_nn** out);
+/* Weights in the layout above (host floats); resets the Adam moments. */
+int epdlb_nn_set_weights(epdlb_nn* nn, const float* w, int64_t count);
+int epdlb_nn_get_weights(epdlb_nn* nn, float* w, int64_t count);
+/* Store a pair from host arrays: omega 3 planes (A, B, S), phi 2 planes (A, B), [y][x]. */
+int epdlb_nn_set_pair(epdlb_nn* nn, int32_t slot, const double* omega, const double* phi, double f_A,
+                      int32_t n_contour);
+/* Store the current (omega, exact Phi) of a density_mode 0 simulation on the
+ * same device and grid (device to device). */
+int epdlb_nn_capture(epdlb_nn* nn, int32_t slot, epdlb_ctx* sim);
+/* Forward pass over slots[count]: loss, max |Phi_hat - Phi| (unnormalised
+ * network output); with grad != NULL also the backward pass and the loss
+ * gradient (EPDLB_NN_PARAMS host floats, layout as the weights).  Synchronous. */
+int epdlb_nn_evaluate(epdlb_nn* nn, const int32_t* slots, int32_t count, double phi_scale, double* loss,
+                      double* max_err, float* grad);
+/* Forward, backward and one Adam step with learning rate lr; queued on the
+ * trainer's stream (slots[] is copied before return). */
+int epdlb_nn_train_step(epdlb_nn* nn, const int32_t* slots, int32_t count, double phi_scale, double lr);
+/* Loss and max error of the last training step's forward pass (synchronises). */
+int epdlb_nn_last_loss(epdlb_nn* nn, double* loss, double* max_err);
+/* Network output softplus(o) of one slot: phi_hat[2*nx*ny] (A then B). */
+int epdlb_nn_predict(epdlb_nn* nn, int32_t slot, double* phi_hat);
+void epdlb_nn_destroy(epdlb_nn* nn);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char* epdlb_last_error(void);

@@ -16,8 +16,22 @@ Inference renormalises Phi_hat to the exact means (<Phi_A> = f_A phibar_P,
 compressibility pins) and takes Phi_S from its closed form (Eq. phi_s).
 Adam: Kingma and Ba, "Adam: a method for stochastic optimization" (2015).
 Arrays are [y, x, channel] (channels last).
+
+`rnd` arguments (default: none) round the values a BF16 implementation
+stores between its steps -- network input, weights, hidden activations,
+pre-activations kept for the backward pass, and the propagated gradients --
+so that the oracle takes the same rounding decisions as such an
+implementation; every sum is still taken in FP64.
+
+surrogate_run() is the hybrid step of the main oracle with these densities
+between exact steps (an exact step every `fallback_every` steps): the force
+source S always differences network densities (at an exact step the exact
+densities become the state and S~ of the next step is corrected by the
+difference of the two estimators at this step).
 """
 import numpy as np
+
+from oracle import epdlb_oracle as O
 
 DILATIONS = (1, 2, 4, 8)
 TAPS = [(ty, tx) for ty in (-1, 0, 1) for tx in (-1, 0, 1)]
@@ -79,14 +93,27 @@ def make_input(omega, f_A, N):
     return x
 
 
-def forward(params, x):
+def bf16_round(a):
+    """Nearest bfloat16 (ties to even) of float32(a), returned as float64."""
+    f = np.ascontiguousarray(a, dtype=np.float32)
+    b = f.view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _ident(a):
+    return a
+
+
+def forward(params, x, rnd=None):
     """params: list of (W [9, ci, co], b [co]).  Returns (o, cache)."""
+    rnd = rnd or _ident
     a = x
     cache = []
     for l, (W, b) in enumerate(params):
         z = conv(a, W, b, DILATIONS[l])
         cache.append((a, z))
-        a = silu(z) if l < len(params) - 1 else z
+        a = rnd(silu(z)) if l < len(params) - 1 else z
     return a, cache
 
 
@@ -98,25 +125,28 @@ def loss_and_grad_output(o, phi_ab, phiP):
     return loss, 2.0 * r / phiP * sigmoid(o) / M
 
 
-def backward(params, cache, go):
+def backward(params, cache, go, rnd=None):
     """Gradients [(dW, db)] of the loss given dL/do."""
+    rnd = rnd or _ident
     grads = [None] * len(params)
-    g = go
+    g = rnd(go)
     for l in range(len(params) - 1, -1, -1):
         W, b = params[l]
         a_in, z = cache[l]
         if l < len(params) - 1:
-            g = g * silu_grad(z)
+            g = rnd(g * silu_grad(rnd(z)))
         grads[l] = (conv_weight_grad(a_in, g, DILATIONS[l]), g.sum(axis=(0, 1)))
         if l > 0:
             g = conv_input_grad(g, W, DILATIONS[l])
     return grads
 
 
-def predict_densities(params, omega, p, gauge_S=None):
+def predict_densities(params, omega, p, gauge_S=None, rnd=None):
     """Surrogate densities (3, ny, nx): renormalised NN output plus exact Phi_S."""
     x = make_input(omega, p["f_A"], p["n_contour"])
-    o, _ = forward(params, x)
+    if rnd:
+        x = rnd(x)
+    o, _ = forward(params, x, rnd)
     ph = softplus(o)
     phiA = ph[..., 0] * (p["f_A"] * p["phi_P"] / np.mean(ph[..., 0]))
     phiB = ph[..., 1] * ((1 - p["f_A"]) * p["phi_P"] / np.mean(ph[..., 1]))
@@ -134,3 +164,54 @@ def adam_update(theta, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1 - b1 ** t)
     vh = v / (1 - b2 ** t)
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def round_params(params, rnd):
+    """Weights as a BF16 implementation holds them (biases stay FP32)."""
+    return [(rnd(W), np.asarray(b, dtype=np.float32).astype(np.float64)) for W, b in params]
+
+
+def surrogate_run(p, params, omega0, nsteps, fallback_every, rnd=None, dens_fn=None, history=False):
+    """Hybrid steps with network densities between exact steps.
+
+    Returns the final state (as the main oracle's step) plus 'errs': the max
+    over sites and species A, B of |Phi_NN - Phi_exact| at the seed and at
+    every exact step.  dens_fn(omega) replaces the network (for pins);
+    history=True adds the lists 'omegas' (seed first) and 'Ss'."""
+    D = O.diffusivities(p)
+    if dens_fn is None:
+        def dens_fn(w):
+            return predict_densities(params, w, p, rnd=rnd)
+    s = O.init_state(p, omega0)
+    omegas, Ss = [s["omega"]], []
+    nn0 = dens_fn(s["omega"])
+    corr = sum((nn0[I] - s["phi"][I]) / D[I] for I in (0, 1))
+    errs = [float(np.max(np.abs(nn0[:2] - s["phi"][:2])))]
+    last_exact = True
+    couple = p.get("couple_lb", 1)
+    for k in range(nsteps):
+        exact = k % fallback_every == 0
+        u_adv = s["u"] if couple else np.zeros_like(s["u"])
+        phi_t, omega_t = O.advect(s["phi"], s["omega"], u_adv)
+        omega_new = O.field_update(phi_t, omega_t, p)
+        nn = dens_fn(omega_new)
+        S = sum((nn[I] - phi_t[I]) / D[I] for I in range(3))
+        if last_exact:
+            S = S - corr
+        if exact:
+            phi_new = O.densities(omega_new, p)["phi"]
+            corr = sum((nn[I] - phi_new[I]) / D[I] for I in (0, 1))
+            errs.append(float(np.max(np.abs(nn[:2] - phi_new[:2]))))
+        else:
+            phi_new = nn
+        F = O.lattice_force(S, p)
+        fstar, rho, u = O.lb_step(s["fstar"], F, p["lb_tau"])
+        s = dict(omega=omega_new, phi=phi_new, fstar=fstar, u=u, rho=rho, n=s["n"] + 1, S=S, F=F)
+        last_exact = exact
+        if history:
+            omegas.append(omega_new)
+            Ss.append(S)
+    s["errs"] = errs
+    if history:
+        s["omegas"], s["Ss"] = omegas, Ss
+    return s

@@ -33,6 +33,8 @@ EPDLB_AUX_STILDE = 1
 EPDLB_AUX_S = 2
 EPDLB_AUX_FORCE = 3
 
+EPDLB_NN_PARAMS = 77954
+
 
 class epdlb_params(ctypes.Structure):
     _fields_ = [
@@ -48,6 +50,8 @@ class epdlb_params(ctypes.Structure):
         ("lb_tau", ctypes.c_double), ("g", ctypes.c_double),
         ("g_units", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("init_flow", ctypes.c_int32), ("couple_lb", ctypes.c_int32),
+        ("density_mode", ctypes.c_int32), ("fallback_every", ctypes.c_int32),
+        ("check_every", ctypes.c_int32), ("resid_tol", ctypes.c_double),
     ]
 
 
@@ -57,6 +61,9 @@ class epdlb_diag(ctypes.Structure):
         ("Q_P", ctypes.c_double), ("Q_P_bwd", ctypes.c_double),
         ("Q_S", ctypes.c_double), ("gauge_S", ctypes.c_double),
         ("mean_omega", ctypes.c_double * 3),
+        ("n_exact", ctypes.c_int64), ("n_triggered", ctypes.c_int64),
+        ("nn_err_last", ctypes.c_double), ("nn_err_max", ctypes.c_double),
+        ("resid_nn_max", ctypes.c_double), ("resid_exact", ctypes.c_double),
     ]
 
 
@@ -83,6 +90,8 @@ _lib = None
 
 _P = ctypes.POINTER
 _dp = _P(ctypes.c_double)
+_fp = _P(ctypes.c_float)
+_ip = _P(ctypes.c_int32)
 _vp = ctypes.c_void_p
 
 SIGNATURES = {
@@ -128,6 +137,18 @@ SIGNATURES = {
     "epdlb_batch_profile_read": (ctypes.c_int, [_vp, _P(epdlb_kernel_stat), ctypes.c_int32,
                                                 _P(ctypes.c_int32)]),
     "epdlb_batch_destroy": (None, [_vp]),
+    "epdlb_surrogate_set_weights": (ctypes.c_int, [_vp, _fp, ctypes.c_int64]),
+    "epdlb_nn_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int, _vp, _P(_vp)]),
+    "epdlb_nn_set_weights": (ctypes.c_int, [_vp, _fp, ctypes.c_int64]),
+    "epdlb_nn_get_weights": (ctypes.c_int, [_vp, _fp, ctypes.c_int64]),
+    "epdlb_nn_set_pair": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, _dp, ctypes.c_double, ctypes.c_int32]),
+    "epdlb_nn_capture": (ctypes.c_int, [_vp, ctypes.c_int32, _vp]),
+    "epdlb_nn_evaluate": (ctypes.c_int, [_vp, _ip, ctypes.c_int32, ctypes.c_double, _dp, _dp, _fp]),
+    "epdlb_nn_train_step": (ctypes.c_int, [_vp, _ip, ctypes.c_int32, ctypes.c_double, ctypes.c_double]),
+    "epdlb_nn_last_loss": (ctypes.c_int, [_vp, _dp, _dp]),
+    "epdlb_nn_predict": (ctypes.c_int, [_vp, ctypes.c_int32, _dp]),
+    "epdlb_nn_destroy": (None, [_vp]),
     "epdlb_last_error": (ctypes.c_char_p, []),
 }
 
@@ -278,8 +299,14 @@ def epdlb_write_aux(ctx, which, data, shape):
 def epdlb_read_diag(ctx):
     d = epdlb_diag()
     _check(load_library().epdlb_read_diag(ctx, ctypes.byref(d)), "epdlb_read_diag")
+    return _diag_dict(d)
+
+
+def _diag_dict(d):
     return dict(step=d.step, Q_P=d.Q_P, Q_P_bwd=d.Q_P_bwd, Q_S=d.Q_S, gauge_S=d.gauge_S,
-                mean_omega=tuple(d.mean_omega))
+                mean_omega=tuple(d.mean_omega), n_exact=d.n_exact, n_triggered=d.n_triggered,
+                nn_err_last=d.nn_err_last, nn_err_max=d.nn_err_max, resid_nn_max=d.resid_nn_max,
+                resid_exact=d.resid_exact)
 
 
 def epdlb_autotune(ctx, reps=20, cache_path=None):
@@ -418,6 +445,137 @@ class Simulation:
     def profile_read(self):
         return epdlb_profile_read(self.ctx)
 
+    def surrogate_set_weights(self, w):
+        epdlb_surrogate_set_weights(self.ctx, w)
+
+
+# ---- density surrogate ---------------------------------------------------------------------
+
+def _f32(a, count):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if a.size != count:
+        raise ValueError(f"expected {count} values, got {a.size}")
+    return a
+
+
+def epdlb_surrogate_set_weights(ctx, w):
+    a = _f32(w, EPDLB_NN_PARAMS)
+    _check(load_library().epdlb_surrogate_set_weights(ctx, a.ctypes.data_as(_fp), a.size),
+           "epdlb_surrogate_set_weights")
+
+
+def epdlb_nn_create(nx, ny, capacity, max_batch, device=0, stream=None):
+    out = _vp()
+    _check(load_library().epdlb_nn_create(nx, ny, capacity, max_batch, device, stream, ctypes.byref(out)),
+           "epdlb_nn_create")
+    return out
+
+
+def epdlb_nn_set_weights(nn, w):
+    a = _f32(w, EPDLB_NN_PARAMS)
+    _check(load_library().epdlb_nn_set_weights(nn, a.ctypes.data_as(_fp), a.size), "epdlb_nn_set_weights")
+
+
+def epdlb_nn_get_weights(nn):
+    a = np.empty(EPDLB_NN_PARAMS, dtype=np.float32)
+    _check(load_library().epdlb_nn_get_weights(nn, a.ctypes.data_as(_fp), a.size), "epdlb_nn_get_weights")
+    return a
+
+
+def epdlb_nn_set_pair(nn, slot, omega, phi, f_A, n_contour, n):
+    w = _f64(omega, 3 * n)
+    ph = _f64(phi, 2 * n)
+    _check(load_library().epdlb_nn_set_pair(nn, slot, _ptr(w), _ptr(ph), f_A, n_contour), "epdlb_nn_set_pair")
+
+
+def epdlb_nn_capture(nn, slot, ctx):
+    _check(load_library().epdlb_nn_capture(nn, slot, ctx), "epdlb_nn_capture")
+
+
+def _slots(slots):
+    a = np.ascontiguousarray(slots, dtype=np.int32)
+    return a, a.ctypes.data_as(_ip)
+
+
+def epdlb_nn_evaluate(nn, slots, phi_scale, grad=False):
+    a, ap = _slots(slots)
+    loss, mx = ctypes.c_double(), ctypes.c_double()
+    g = np.empty(EPDLB_NN_PARAMS, dtype=np.float32) if grad else None
+    _check(load_library().epdlb_nn_evaluate(nn, ap, a.size, phi_scale, ctypes.byref(loss), ctypes.byref(mx),
+                                            g.ctypes.data_as(_fp) if grad else None), "epdlb_nn_evaluate")
+    return loss.value, mx.value, g
+
+
+def epdlb_nn_train_step(nn, slots, phi_scale, lr):
+    a, ap = _slots(slots)
+    _check(load_library().epdlb_nn_train_step(nn, ap, a.size, phi_scale, lr), "epdlb_nn_train_step")
+
+
+def epdlb_nn_last_loss(nn):
+    loss, mx = ctypes.c_double(), ctypes.c_double()
+    _check(load_library().epdlb_nn_last_loss(nn, ctypes.byref(loss), ctypes.byref(mx)), "epdlb_nn_last_loss")
+    return loss.value, mx.value
+
+
+def epdlb_nn_predict(nn, slot, shape):
+    out = np.empty((2,) + tuple(shape))
+    _check(load_library().epdlb_nn_predict(nn, slot, _ptr(out)), "epdlb_nn_predict")
+    return out
+
+
+def epdlb_nn_destroy(nn):
+    load_library().epdlb_nn_destroy(nn)
+
+
+class Trainer:
+    """Device dataset of (potentials -> densities) pairs and the surrogate's
+    training kernels; work is queued on torch's current stream."""
+
+    def __init__(self, nx, ny, capacity, max_batch, device=0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("epdlb needs a ROCm GPU (gfx950); none is visible")
+        self.shape = (ny, nx)
+        self.n = nx * ny
+        self.capacity = capacity
+        self.stream = torch.cuda.current_stream(torch.device("cuda", device))
+        self.nn = epdlb_nn_create(nx, ny, capacity, max_batch, device, _vp(self.stream.cuda_stream))
+
+    def close(self):
+        if getattr(self, "nn", None) is not None:
+            epdlb_nn_destroy(self.nn)
+            self.nn = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_weights(self, w):
+        epdlb_nn_set_weights(self.nn, w)
+
+    def get_weights(self):
+        return epdlb_nn_get_weights(self.nn)
+
+    def set_pair(self, slot, omega, phi_ab, f_A, n_contour):
+        epdlb_nn_set_pair(self.nn, slot, omega, phi_ab, f_A, n_contour, self.n)
+
+    def capture(self, slot, sim):
+        epdlb_nn_capture(self.nn, slot, sim.ctx)
+
+    def evaluate(self, slots, phi_scale, grad=False):
+        return epdlb_nn_evaluate(self.nn, slots, phi_scale, grad)
+
+    def train_step(self, slots, phi_scale, lr):
+        epdlb_nn_train_step(self.nn, slots, phi_scale, lr)
+
+    def last_loss(self):
+        return epdlb_nn_last_loss(self.nn)
+
+    def predict(self, slot):
+        return epdlb_nn_predict(self.nn, slot, self.shape)
+
 
 # ---- batched replicas ----------------------------------------------------------------------
 
@@ -469,8 +627,7 @@ def epdlb_batch_read_velocity(b, replica, shape):
 def epdlb_batch_read_diag(b, replica):
     d = epdlb_diag()
     _check(load_library().epdlb_batch_read_diag(b, replica, ctypes.byref(d)), "epdlb_batch_read_diag")
-    return dict(step=d.step, Q_P=d.Q_P, Q_P_bwd=d.Q_P_bwd, Q_S=d.Q_S, gauge_S=d.gauge_S,
-                mean_omega=tuple(d.mean_omega))
+    return _diag_dict(d)
 
 
 def epdlb_batch_autotune(b, reps=20, cache_path=None):

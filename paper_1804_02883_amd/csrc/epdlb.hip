@@ -14,6 +14,7 @@
 
 #include "epdlb.h"
 #include "kernels.hpp"
+#include "nn.hpp"
 
 using namespace epdlb;
 
@@ -58,6 +59,8 @@ double unit_open0(uint64_t bits) { return (double((bits >> 11)) + 1.0) * 0x1.0p-
 struct Layout {
   size_t omega[2], phi, stilde, S, q[2], tmp, spec, F, fstar[2], rho, u, boltz;
   size_t mult_x, mult_y, tw_x, tw_y, wnA, wnB, scal, partials, counters;
+  // surrogate mode only (density_mode 1)
+  size_t nn_x, nn_act[2], nn_w, nn_frag, nn_phin, nn_corr;
   size_t total;
   size_t n_partials;
 };
@@ -101,6 +104,15 @@ Layout make_layout(const epdlb_params& p) {
   L.n_partials = 4 * (n / 64 + 4096);
   L.partials = take(L.n_partials * sizeof(double));
   L.counters = take(16 * sizeof(unsigned));
+  if (p.density_mode == 1) {
+    L.nn_x = take(n * nn::kXC * 2);
+    L.nn_act[0] = take(n * nn::kHid * 2);
+    L.nn_act[1] = take(n * nn::kHid * 2);
+    L.nn_w = take(size_t(nn::kNnParams) * sizeof(float));
+    L.nn_frag = take(size_t(nn::kFwdFragElems) * 2);
+    L.nn_phin = take(2 * plane);
+    L.nn_corr = take(plane);
+  }
   L.total = off;
   return L;
 }
@@ -138,22 +150,35 @@ struct epdlb_ctx {
   std::vector<int> prof_kind;
   // captured multi-kernel steps, keyed by (steps, omega parity, f* parity)
   struct GraphEntry {
-    int steps, cur, fcur;
+    int steps, cur, fcur, kind;
     hipGraphExec_t exec;
   };
   std::vector<GraphEntry> graphs;
   hipStream_t cap_stream = nullptr;
   bool use_graph = true;
+  // surrogate mode
+  bool nn_ready = false;      // weights loaded
+  bool last_exact = true;     // previous step (or the seed) had exact densities
+  bool force_exact = false;   // residual test asks for an exact step
+  int64_t n_exact = 0, n_triggered = 0;
+  double resid_nn_max = 0.0;
+  double* snap = nullptr;     // pinned: device maxima at the last check point
+  hipEvent_t snap_ev = nullptr;
+  bool snap_pending = false;
   template <typename T> T* ptr(size_t off) const { return reinterpret_cast<T*>(base + off); }
 };
 
 namespace {
 
+int nn_after_seed(epdlb_ctx* c);
+
 enum Kind { K_STATS, K_ADVECT, K_FINISH, K_BOLTZ, K_PROP_ROW, K_PROP_COL, K_DENSITY, K_FROW_FWD, K_FCOL,
-            K_FROW_INV, K_LB, K_NUM };
+            K_FROW_INV, K_LB, K_NN_INPUT, K_NN_CONV0, K_NN_CONV, K_NN_OUT, K_NN_NORM, K_NN_RESET, K_NUM };
 const char* const kKindName[K_NUM] = {"field_stats", "advect_update", "finish_stats",  "boltzmann",
                                       "prop_row",    "prop_col",      "density",       "force_row_fwd",
-                                      "force_col",   "force_row_inv", "lb"};
+                                      "force_col",   "force_row_inv", "lb",            "nn_input",
+                                      "nn_conv0",    "nn_conv",       "nn_out",        "nn_norm",
+                                      "nn_reset"};
 
 // Profiling: while the profiler has room, the next kernel launch records a
 // start/stop event pair at the kernel's own start and end (AMD's extended
@@ -212,6 +237,10 @@ int validate(const epdlb_params* p) {
   if (!std::isfinite(p->g) || !std::isfinite(p->kT_over_v) || !std::isfinite(p->kappa_H) ||
       !std::isfinite(p->chi_AB) || !std::isfinite(p->chi_AS) || !std::isfinite(p->chi_BS))
     return fail(EPDLB_EINVAL, "non-finite parameter");
+  if (p->density_mode != 0 && p->density_mode != 1) return fail(EPDLB_EINVAL, "density_mode must be 0 or 1");
+  if (p->density_mode == 1 &&
+      (p->fallback_every < 1 || p->check_every < 1 || !(p->resid_tol > 0.0) || !std::isfinite(p->resid_tol)))
+    return fail(EPDLB_EINVAL, "surrogate mode needs fallback_every >= 1, check_every >= 1, resid_tol > 0");
   return EPDLB_OK;
 }
 
@@ -916,13 +945,17 @@ int set_fields_group(epdlb_ctx* c, const double* const* omega) {
     if (omega[r]) CHK(init_lb(c, r));
   HIPCHK(hipStreamSynchronize(c->stream));
   c->seeded = true;
+  if (c->p.density_mode == 1) CHK(nn_after_seed(c));
   return EPDLB_OK;
 }
 
+int run_sur_step(epdlb_ctx* c, int kind);
+
 // Capture `steps` hybrid steps from the current buffer parity into a graph.
-int get_graph(epdlb_ctx* c, int steps, hipGraphExec_t* out) {
+// kind 0: exact densities; 1..4: surrogate-mode steps (see run_sur_step).
+int get_graph(epdlb_ctx* c, int steps, int kind, hipGraphExec_t* out) {
   for (auto& g : c->graphs)
-    if (g.steps == steps && g.cur == c->cur && g.fcur == c->fcur) {
+    if (g.steps == steps && g.cur == c->cur && g.fcur == c->fcur && g.kind == kind) {
       *out = g.exec;
       return EPDLB_OK;
     }
@@ -934,8 +967,13 @@ int get_graph(epdlb_ctx* c, int steps, hipGraphExec_t* out) {
   c->prof_on = false;
   HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
   int r = EPDLB_OK;
-  for (int s = 0; s < steps && r == EPDLB_OK; ++s)
-    for (int st = EPDLB_STAGE_ADVECT_UPDATE; st <= EPDLB_STAGE_LB && r == EPDLB_OK; ++st) r = run_stage(c, st);
+  for (int s = 0; s < steps && r == EPDLB_OK; ++s) {
+    if (kind == 0) {
+      for (int st = EPDLB_STAGE_ADVECT_UPDATE; st <= EPDLB_STAGE_LB && r == EPDLB_OK; ++st) r = run_stage(c, st);
+    } else {
+      r = run_sur_step(c, kind);
+    }
+  }
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
   c->stream = user;
@@ -951,7 +989,7 @@ int get_graph(epdlb_ctx* c, int steps, hipGraphExec_t* out) {
   e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   HIPCHK(e);
-  c->graphs.push_back({steps, cur0, fcur0, exec});
+  c->graphs.push_back({steps, cur0, fcur0, kind, exec});
   *out = exec;
   return EPDLB_OK;
 }
@@ -984,6 +1022,8 @@ int check_finite(epdlb_ctx* c) {
 }
 
 }  // namespace
+
+#include "nn_host.hpp"
 
 // ---------------------------------------------------------------------------
 // Batched replicas: replicas of one grid shape form a group that shares every
@@ -1158,6 +1198,10 @@ int epdlb_params_default(epdlb_params* p) {
   p->precision = 0;
   p->init_flow = 1;
   p->couple_lb = 1;
+  p->density_mode = 0;
+  p->fallback_every = 50;
+  p->check_every = 10;
+  p->resid_tol = 1e-3;
   return EPDLB_OK;
 }
 
@@ -1231,6 +1275,13 @@ int epdlb_create(const epdlb_params* p, int device, void* stream, void* workspac
     c->own_mem = true;
   }
   default_shapes(c);
+  if (p->density_mode == 1) {
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->snap), 2 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&c->snap_ev, hipEventDisableTiming) != hipSuccess) {
+      epdlb_destroy(c);
+      return fail(EPDLB_ENOMEM, "pinned host buffer or event for the residual test failed");
+    }
+  }
   int r = upload_tables(c);
   if (r != EPDLB_OK) {
     epdlb_destroy(c);
@@ -1272,6 +1323,7 @@ int epdlb_set_state(epdlb_ctx* c, const double* omega, const double* phi, const 
   HIPCHK(hipStreamSynchronize(c->stream));
   c->seeded = true;
   c->nstep = 0;
+  if (c->p.density_mode == 1) CHK(nn_after_seed(c));
   return EPDLB_OK;
 }
 
@@ -1280,13 +1332,37 @@ int epdlb_step(epdlb_ctx* c, int64_t n) {
   if (!c->seeded) return fail(EPDLB_ESTATE, "step before seed/set_fields/set_state");
   if (n < 0) return fail(EPDLB_EINVAL, "negative step count");
   HIPCHK(hipSetDevice(c->device));
+  if (c->p.density_mode == 1) {
+    if (!c->nn_ready) return fail(EPDLB_ESTATE, "surrogate mode: weights not loaded (epdlb_surrogate_set_weights)");
+    for (int64_t s = 0; s < n; ++s) {
+      const bool exact = c->force_exact || c->nstep % c->p.fallback_every == 0;
+      const int kind = (exact ? 3 : 1) + (c->last_exact ? 1 : 0);
+      if (c->use_graph && !c->prof_on) {
+        hipGraphExec_t g;
+        CHK(get_graph(c, 1, kind, &g));
+        HIPCHK(hipGraphLaunch(g, c->stream));
+        c->cur = 1 - c->cur;
+        c->fcur = 1 - c->fcur;
+      } else {
+        CHK(run_sur_step(c, kind));
+      }
+      if (exact) {
+        ++c->n_exact;
+        c->force_exact = false;
+      }
+      c->last_exact = exact;
+      ++c->nstep;
+      if (c->nstep % c->p.check_every == 0) CHK(nn_check(c));
+    }
+    return EPDLB_OK;
+  }
   if (c->use_graph && !c->prof_on) {
     // replay captured two-step graphs (buffer parity returns to its start),
     // then a one-step graph for an odd remainder
     while (n > 0) {
       const int k = n >= 2 ? 2 : 1;
       hipGraphExec_t g;
-      CHK(get_graph(c, k, &g));
+      CHK(get_graph(c, k, 0, &g));
       HIPCHK(hipGraphLaunch(g, c->stream));
       if (k == 1) {
         c->cur = 1 - c->cur;
@@ -1387,6 +1463,12 @@ int epdlb_read_diag(epdlb_ctx* c, epdlb_diag* d) {
   d->mean_omega[0] = s[kMeanA];
   d->mean_omega[1] = s[kMeanB];
   d->mean_omega[2] = s[kMeanS];
+  d->n_exact = c->n_exact;
+  d->n_triggered = c->n_triggered;
+  d->nn_err_last = s[kNnErrLast];
+  d->nn_err_max = s[kNnErr];
+  d->resid_nn_max = std::max(c->resid_nn_max, s[kNnResid]);
+  d->resid_exact = s[kResidEx];
   return EPDLB_OK;
 }
 
@@ -1536,6 +1618,8 @@ void epdlb_destroy(epdlb_ctx* c) {
   for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->own_mem && c->base) (void)hipFree(c->base);
+  if (c->snap) (void)hipHostFree(c->snap);
+  if (c->snap_ev) (void)hipEventDestroy(c->snap_ev);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -1548,6 +1632,7 @@ int epdlb_batch_create(const epdlb_params* params, int32_t n_replicas, int devic
     CHK(validate(&params[r]));
     if (!same_model(params[0], params[r]))
       return fail(EPDLB_EINVAL, "replicas may differ only in nx, ny, g and f_A");
+    if (params[r].density_mode != 0) return fail(EPDLB_EINVAL, "batched replicas run the exact densities only");
   }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= device || device < 0)
@@ -1729,6 +1814,7 @@ int epdlb_batch_read_diag(epdlb_batch* b, int32_t replica, epdlb_diag* d) {
   double s[kNumScal];
   HIPCHK(hipMemcpyAsync(s, c->base + c->roff(i) + c->L.scal, sizeof(s), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
+  *d = epdlb_diag{};
   d->step = b->nstep;
   d->Q_P = s[kQPf];
   d->Q_P_bwd = s[kQPb];
@@ -1809,3 +1895,301 @@ void epdlb_batch_destroy(epdlb_batch* b) {
 const char* epdlb_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Density surrogate
+// ---------------------------------------------------------------------------
+int epdlb_surrogate_set_weights(epdlb_ctx* c, const float* w, int64_t count) {
+  if (!c || !w) return fail(EPDLB_EINVAL, "NULL argument");
+  if (c->p.density_mode != 1) return fail(EPDLB_ESTATE, "context was not created with density_mode = 1");
+  if (count != nn::kNnParams) return fail(EPDLB_EINVAL, "expected EPDLB_NN_PARAMS weights");
+  for (int64_t i = 0; i < count; ++i)
+    if (!std::isfinite(w[i])) return fail(EPDLB_EINVAL, "non-finite weight");
+  HIPCHK(hipSetDevice(c->device));
+  float* dw = c->ptr<float>(c->L.nn_w);
+  HIPCHK(hipMemcpyAsync(dw, w, sizeof(float) * count, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(nn_pack(dw, c->ptr<__bf16>(c->L.nn_frag), nullptr, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->nn_ready = true;
+  if (c->seeded) CHK(nn_after_seed(c));
+  return EPDLB_OK;
+}
+
+int epdlb_nn_create(int32_t nx, int32_t ny, int32_t capacity, int32_t max_batch, int device, void* stream,
+                    epdlb_nn** out) {
+  if (!out) return fail(EPDLB_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!is_pow2(nx) || nx < 32 || nx > 1024 || !is_pow2(ny) || ny < 16 || ny > 1024)
+    return fail(EPDLB_EINVAL, "nx, ny must be powers of two, 32 <= nx <= 1024, 16 <= ny <= 1024");
+  if (capacity < 1 || max_batch < 1 || max_batch > capacity) return fail(EPDLB_EINVAL, "bad capacity or batch");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= device || device < 0)
+    return fail(EPDLB_ENODEV, "no HIP device with that index");
+  HIPCHK(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(EPDLB_ENODEV, std::string("library built for gfx950, device is ") + prop.gcnArchName);
+  epdlb_nn* t = new (std::nothrow) epdlb_nn();
+  if (!t) return fail(EPDLB_ENOMEM, "host allocation failed");
+  t->device = device;
+  t->nx = nx;
+  t->ny = ny;
+  t->n = long(nx) * ny;
+  t->capacity = capacity;
+  t->max_batch = max_batch;
+  const size_t n = size_t(t->n);
+  const FragOffsets fo = frag_offsets();
+  size_t off = 0;
+  std::vector<size_t> offs;
+  auto take = [&](size_t bytes) {
+    offs.push_back(off);
+    off = align256(off + bytes);
+  };
+  const size_t P = nn::kNnParams;
+  for (int i = 0; i < 4; ++i) take(P * sizeof(float));        // w g m v
+  take(fo.ftotal * 2);                                        // ffrag
+  take(fo.btotal * 2);                                        // bfrag
+  take(size_t(capacity) * n * nn::kXC * 2);                   // x
+  take(size_t(capacity) * 2 * n * sizeof(float));             // tgt
+  for (int i = 0; i < 6; ++i) take(size_t(max_batch) * n * nn::kHid * 2);  // act, z
+  take(size_t(max_batch) * n * nn::kXC * 2);                  // g4
+  for (int i = 0; i < 2; ++i) take(size_t(max_batch) * n * nn::kHid * 2);  // gb
+  take(2 * n * sizeof(float));                                // pred
+  take(size_t(max_batch) * sizeof(int));                      // slots
+  take(2 * kConvMaxBlocks * sizeof(double));                  // lpart
+  take(size_t(kWgradMaxBlocks) * 9 * 64 * 64 * sizeof(float));  // wpart
+  take(size_t(kWgradMaxBlocks) * 64 * sizeof(float));         // wpartb
+  take((5 * n + 3) * sizeof(double));                         // stage
+  if (hipMalloc(&t->mem, off) != hipSuccess) {
+    delete t;
+    return fail(EPDLB_ENOMEM, "hipMalloc of the trainer arena failed");
+  }
+  unsigned char* b = static_cast<unsigned char*>(t->mem);
+  int k = 0;
+  t->w = reinterpret_cast<float*>(b + offs[k++]);
+  t->g = reinterpret_cast<float*>(b + offs[k++]);
+  t->m = reinterpret_cast<float*>(b + offs[k++]);
+  t->v = reinterpret_cast<float*>(b + offs[k++]);
+  t->ffrag = reinterpret_cast<__bf16*>(b + offs[k++]);
+  t->bfrag = reinterpret_cast<__bf16*>(b + offs[k++]);
+  t->x = reinterpret_cast<__bf16*>(b + offs[k++]);
+  t->tgt = reinterpret_cast<float*>(b + offs[k++]);
+  for (int i = 0; i < 3; ++i) {
+    t->act[i] = reinterpret_cast<__bf16*>(b + offs[k++]);
+    t->zz[i] = reinterpret_cast<__bf16*>(b + offs[k++]);
+  }
+  t->g4 = reinterpret_cast<__bf16*>(b + offs[k++]);
+  t->gb[0] = reinterpret_cast<__bf16*>(b + offs[k++]);
+  t->gb[1] = reinterpret_cast<__bf16*>(b + offs[k++]);
+  t->pred = reinterpret_cast<float*>(b + offs[k++]);
+  t->slots = reinterpret_cast<int*>(b + offs[k++]);
+  t->lpart = reinterpret_cast<double*>(b + offs[k++]);
+  t->wpart = reinterpret_cast<float*>(b + offs[k++]);
+  t->wpartb = reinterpret_cast<float*>(b + offs[k++]);
+  t->stage = reinterpret_cast<double*>(b + offs[k++]);
+  if (stream) {
+    t->stream = reinterpret_cast<hipStream_t>(stream);
+  } else {
+    if (hipStreamCreateWithFlags(&t->stream, hipStreamNonBlocking) != hipSuccess) {
+      epdlb_nn_destroy(t);
+      return fail(EPDLB_EHIP, "hipStreamCreate failed");
+    }
+    t->own_stream = true;
+  }
+  // zero weights and moments until set_weights
+  if (hipMemsetAsync(t->w, 0, 4 * align256(P * sizeof(float)), t->stream) != hipSuccess ||
+      nn_pack(t->w, t->ffrag, t->bfrag, t->stream) != hipSuccess || hipStreamSynchronize(t->stream) != hipSuccess) {
+    epdlb_nn_destroy(t);
+    return fail(EPDLB_EHIP, "clearing the trainer weights failed");
+  }
+  t->packed_bwd = true;
+  *out = t;
+  return EPDLB_OK;
+}
+
+int epdlb_nn_set_weights(epdlb_nn* t, const float* w, int64_t count) {
+  if (!t || !w) return fail(EPDLB_EINVAL, "NULL argument");
+  if (count != nn::kNnParams) return fail(EPDLB_EINVAL, "expected EPDLB_NN_PARAMS weights");
+  for (int64_t i = 0; i < count; ++i)
+    if (!std::isfinite(w[i])) return fail(EPDLB_EINVAL, "non-finite weight");
+  HIPCHK(hipSetDevice(t->device));
+  HIPCHK(hipMemcpyAsync(t->w, w, sizeof(float) * count, hipMemcpyHostToDevice, t->stream));
+  const size_t pb = align256(size_t(nn::kNnParams) * sizeof(float));
+  HIPCHK(hipMemsetAsync(t->m, 0, 2 * pb, t->stream));  // m and v are adjacent
+  HIPCHK(nn_pack(t->w, t->ffrag, t->bfrag, t->stream));
+  HIPCHK(hipStreamSynchronize(t->stream));
+  t->adam_t = 0;
+  t->packed_bwd = true;
+  return EPDLB_OK;
+}
+
+int epdlb_nn_get_weights(epdlb_nn* t, float* w, int64_t count) {
+  if (!t || !w) return fail(EPDLB_EINVAL, "NULL argument");
+  if (count != nn::kNnParams) return fail(EPDLB_EINVAL, "expected EPDLB_NN_PARAMS weights");
+  HIPCHK(hipSetDevice(t->device));
+  HIPCHK(hipMemcpyAsync(w, t->w, sizeof(float) * count, hipMemcpyDeviceToHost, t->stream));
+  HIPCHK(hipStreamSynchronize(t->stream));
+  return EPDLB_OK;
+}
+
+int epdlb_nn_set_pair(epdlb_nn* t, int32_t slot, const double* omega, const double* phi, double f_A,
+                      int32_t n_contour) {
+  if (!t || !omega || !phi) return fail(EPDLB_EINVAL, "NULL argument");
+  if (slot < 0 || slot >= t->capacity) return fail(EPDLB_EINVAL, "slot index out of range");
+  if (!(f_A > 0.0 && f_A < 1.0) || n_contour < 1) return fail(EPDLB_EINVAL, "bad f_A or n_contour");
+  HIPCHK(hipSetDevice(t->device));
+  const size_t n = size_t(t->n);
+  std::vector<double> h(5 * n + 3);
+  std::memcpy(h.data(), omega, 3 * n * sizeof(double));
+  std::memcpy(h.data() + 3 * n, phi, 2 * n * sizeof(double));
+  for (int I = 0; I < 3; ++I) {
+    double sum = 0.0;
+    for (size_t i = 0; i < n; ++i) sum += omega[I * n + i];
+    h[5 * n + I] = sum / double(n);
+  }
+  HIPCHK(hipMemcpyAsync(t->stage, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, t->stream));
+  hipLaunchKernelGGL(nn::k_nn_input<double>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, t->stream,
+                     (const double*)t->stage, (const double*)(t->stage + 5 * n), long(n), float(f_A),
+                     float(1.0 / n_contour), t->x + size_t(slot) * n * nn::kXC, (const double*)(t->stage + 3 * n),
+                     t->tgt + size_t(slot) * 2 * n);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(t->stream));
+  return EPDLB_OK;
+}
+
+int epdlb_nn_capture(epdlb_nn* t, int32_t slot, epdlb_ctx* c) {
+  if (!t || !c) return fail(EPDLB_EINVAL, "NULL argument");
+  if (slot < 0 || slot >= t->capacity) return fail(EPDLB_EINVAL, "slot index out of range");
+  if (c->p.nx != t->nx || c->p.ny != t->ny || c->device != t->device)
+    return fail(EPDLB_EINVAL, "simulation grid or device differs from the trainer's");
+  if (c->p.density_mode != 0) return fail(EPDLB_EINVAL, "pairs come from a simulation with exact densities");
+  if (!c->seeded) return fail(EPDLB_ESTATE, "simulation not seeded");
+  HIPCHK(hipSetDevice(t->device));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const long n = t->n;
+  const float fA = float(c->p.f_A), invN = float(1.0 / c->p.n_contour);
+  const double* mean = c->ptr<double>(c->L.scal) + kMeanA;
+  __bf16* x = t->x + size_t(slot) * n * nn::kXC;
+  float* tg = t->tgt + size_t(slot) * 2 * n;
+  if (c->p.precision == 0)
+    hipLaunchKernelGGL(nn::k_nn_input<double>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, t->stream,
+                       (const double*)c->ptr<double>(c->L.omega[c->cur]), mean, n, fA, invN, x,
+                       (const double*)c->ptr<double>(c->L.phi), tg);
+  else
+    hipLaunchKernelGGL(nn::k_nn_input<float>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, t->stream,
+                       (const float*)c->ptr<float>(c->L.omega[c->cur]), mean, n, fA, invN, x,
+                       (const float*)c->ptr<float>(c->L.phi), tg);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(t->stream));
+  return EPDLB_OK;
+}
+
+static int nn_read_loss(epdlb_nn* t, int count, double* loss, double* max_err) {
+  std::vector<double> h(2 * size_t(t->last_nblocks));
+  HIPCHK(hipMemcpyAsync(h.data(), t->lpart, h.size() * sizeof(double), hipMemcpyDeviceToHost, t->stream));
+  HIPCHK(hipStreamSynchronize(t->stream));
+  double s = 0.0, mx = 0.0;
+  for (int b = 0; b < t->last_nblocks; ++b) {
+    s += h[2 * b];
+    mx = std::max(mx, h[2 * b + 1]);
+  }
+  if (loss) *loss = s / (double(count) * double(t->n) * 2.0);
+  if (max_err) *max_err = mx;
+  return EPDLB_OK;
+}
+
+int epdlb_nn_evaluate(epdlb_nn* t, const int32_t* slots, int32_t count, double phi_scale, double* loss,
+                      double* max_err, float* grad) {
+  if (!t) return fail(EPDLB_EINVAL, "NULL argument");
+  if (!(phi_scale > 0.0)) return fail(EPDLB_EINVAL, "phi_scale must be > 0");
+  HIPCHK(hipSetDevice(t->device));
+  CHK(nn_upload_slots(t, slots, count));
+  CHK(nn_forward_train(t, count, phi_scale));
+  if (grad) {
+    CHK(nn_backward(t, count));
+    HIPCHK(hipMemcpyAsync(grad, t->g, sizeof(float) * nn::kNnParams, hipMemcpyDeviceToHost, t->stream));
+  }
+  return nn_read_loss(t, count, loss, max_err);
+}
+
+int epdlb_nn_train_step(epdlb_nn* t, const int32_t* slots, int32_t count, double phi_scale, double lr) {
+  if (!t) return fail(EPDLB_EINVAL, "NULL argument");
+  if (!(phi_scale > 0.0) || !(lr > 0.0)) return fail(EPDLB_EINVAL, "phi_scale and lr must be > 0");
+  HIPCHK(hipSetDevice(t->device));
+  CHK(nn_upload_slots(t, slots, count));
+  t->last_count = count;
+  CHK(nn_forward_train(t, count, phi_scale));
+  CHK(nn_backward(t, count));
+  ++t->adam_t;
+  const double b1 = 0.9, b2 = 0.999;
+  const float c1 = float(lr / (1.0 - std::pow(b1, t->adam_t)));
+  const float c2 = float(1.0 / (1.0 - std::pow(b2, t->adam_t)));
+  hipLaunchKernelGGL(nn::k_adam, dim3((nn::kNnParams + 255) / 256), dim3(256), 0, t->stream, t->w,
+                     (const float*)t->g, t->m, t->v, int(nn::kNnParams), float(b1), float(b2), c1, c2, 1e-8f);
+  HIPCHK(hipGetLastError());
+  HIPCHK(nn_pack(t->w, t->ffrag, t->bfrag, t->stream));
+  return EPDLB_OK;
+}
+
+int epdlb_nn_last_loss(epdlb_nn* t, double* loss, double* max_err) {
+  if (!t) return fail(EPDLB_EINVAL, "NULL argument");
+  if (t->last_count < 1) return fail(EPDLB_ESTATE, "no training step yet");
+  HIPCHK(hipSetDevice(t->device));
+  return nn_read_loss(t, t->last_count, loss, max_err);
+}
+
+int epdlb_nn_predict(epdlb_nn* t, int32_t slot, double* phi_hat) {
+  if (!t || !phi_hat) return fail(EPDLB_EINVAL, "NULL argument");
+  if (slot < 0 || slot >= t->capacity) return fail(EPDLB_EINVAL, "slot index out of range");
+  HIPCHK(hipSetDevice(t->device));
+  CHK(nn_upload_slots(t, &slot, 1));
+  const NnOffsets o = nn_offsets();
+  const FragOffsets fo = frag_offsets();
+  const long n = t->n;
+  const int tps = (t->nx / nn::kTW) * (t->ny / nn::kConvTH);
+  nn::ConvArgs a{};
+  a.nx = t->nx;
+  a.ny = t->ny;
+  a.tiles_per_sample = a.ntiles = tps;
+  a.bs = n * nn::kHid;
+  for (int l = 0; l < 3; ++l) {
+    a.in = l == 0 ? t->x : t->act[l - 1];
+    a.in_bs = n * (l == 0 ? nn::kXC : nn::kHid);
+    a.slots = l == 0 ? t->slots : nullptr;
+    a.wfrag = t->ffrag + fo.f[l];
+    a.bias = t->w + o.b[l];
+    a.out = t->act[l];
+    a.d = nn::dil_of(l);
+    const hipError_t e = l == 0 ? conv_hidden<nn::kXC, nn::EPI_FWD>(a, t->stream)
+                                : conv_hidden<nn::kHid, nn::EPI_FWD>(a, t->stream);
+    HIPCHK(e);
+  }
+  nn::OutArgs<float> q{};
+  q.in = t->act[2];
+  q.in_bs = n * nn::kHid;
+  q.wfrag = t->ffrag + fo.f[3];
+  q.bias = t->w + o.b[3];
+  q.phi = t->pred;
+  q.plane = n;
+  q.partials = t->lpart;
+  q.nx = t->nx;
+  q.ny = t->ny;
+  q.d = nn::dil_of(3);
+  q.tiles_per_sample = q.ntiles = tps;
+  int nb = 0;
+  HIPCHK((conv_out<float, nn::EPO_INFER>(q, t->stream, &nb)));
+  std::vector<float> h(2 * size_t(n));
+  HIPCHK(hipMemcpyAsync(h.data(), t->pred, h.size() * sizeof(float), hipMemcpyDeviceToHost, t->stream));
+  HIPCHK(hipStreamSynchronize(t->stream));
+  for (size_t i = 0; i < h.size(); ++i) phi_hat[i] = h[i];
+  return EPDLB_OK;
+}
+
+void epdlb_nn_destroy(epdlb_nn* t) {
+  if (!t) return;
+  if (t->stream) (void)hipStreamSynchronize(t->stream);
+  if (t->mem) (void)hipFree(t->mem);
+  if (t->own_stream && t->stream) (void)hipStreamDestroy(t->stream);
+  delete t;
+}

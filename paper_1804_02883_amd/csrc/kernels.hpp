@@ -16,7 +16,12 @@ enum Scal : int {
   kQS = 3, kGaugeS = 4,                 // Q_S and the constant it was computed with
   kQPf = 5, kQPb = 6,                   // Q_P from the forward and backward chains
   kGext = 7,                            // reverse-Poiseuille force amplitude, lattice units
-  kNumScal = 8
+  // surrogate mode (maxima of non-negative values, updated atomically)
+  kNnResid = 8,                         // max |sum Phi - 1| of surrogate steps since the last check
+  kResidEx = 9,                         // max |sum Phi - 1| of the last exact step
+  kNnErrLast = 10,                      // max |Phi_NN - Phi_exact| (A, B) at the last exact step
+  kNnErr = 11,                          // the same, maximum over all exact steps
+  kNumScal = 12
 };
 
 // ---------------------------------------------------------------------------

@@ -14,7 +14,8 @@ HEADER = os.path.join(ROOT, "include", "epdlb.h")
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "".join(open(os.path.join(ROOT, "include", f)).read()
+                   for f in sorted(os.listdir(os.path.join(ROOT, "include"))) if f.endswith(".h"))
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(epdlb_[a-z_]+)\s*\(", text)))
 
@@ -50,9 +51,12 @@ def test_defaults_and_validation():
     assert p.abi_version == 1 and p.nx == 32 and p.n_contour == 16
     assert abs(p.dx - 1 / 3) < 1e-16 and p.dt == 0.002 and p.D_A == 1 / 16
     assert B.epdlb_validate(p) == 0
+    assert (p.density_mode, p.fallback_every, p.check_every, p.resid_tol) == (0, 50, 10, 1e-3)
+    assert B.epdlb_validate(B.make_params(density_mode=1)) == 0
     for bad in [dict(nx=48), dict(nx=16), dict(ny=8), dict(n_contour=1), dict(f_A=1.0),
                 dict(phi_P=0.0), dict(lb_tau=0.5), dict(precision=2), dict(abi_version=7),
-                dict(g=float("nan"))]:
+                dict(g=float("nan")), dict(density_mode=2), dict(density_mode=1, fallback_every=0),
+                dict(density_mode=1, check_every=0), dict(density_mode=1, resid_tol=0.0)]:
         q = B.make_params(**bad)
         assert B.epdlb_validate(q) == B.EPDLB_EINVAL, bad
         assert B.epdlb_last_error() != ""
@@ -67,6 +71,11 @@ def test_workspace_bytes_scale():
     planes = 2 * N + 40  # omega 6, phi 3, S~ 1, S 1, q 2N, tmp 2, spec 2, F 2, f* 18, rho 1, u 2, E 2
     assert planes * n * 4 <= b32 < planes * n * 4 + (1 << 22)
     assert abs(b64 - 2 * b32) < (1 << 22)
+    # surrogate mode adds x (16 bf16), two 64-channel bf16 activations, the
+    # network's densities (2 planes) and the S correction (1 plane), weights
+    bs = B.epdlb_workspace_bytes(B.make_params(preset("cfg3"), density_mode=1))
+    extra = n * (16 * 2 + 2 * 64 * 2 + 3 * 4)
+    assert extra <= bs - b32 < extra + (1 << 20)
 
 
 def test_noise_matches_seeded_inputs():

@@ -3,6 +3,7 @@ dilated periodic convolution by brute-force loops, Adam by its definition on a
 quadratic, and the renormalised densities' exact means."""
 import numpy as np
 
+from oracle import epdlb_oracle as O
 from oracle import nn_oracle as NN
 
 
@@ -99,3 +100,57 @@ def test_surrogate_densities_have_exact_means():
     assert abs(phi[1].mean() - 0.7 * 0.15) < 1e-15
     assert abs(phi[2].mean() - 0.85) < 1e-15
     assert np.all(phi > 0)
+
+
+def test_bf16_rounding_values():
+    r = NN.bf16_round(np.array([1.0, 1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, np.pi, -2.5, 0.0, 65280.0 + 128]))
+    # ties go to the even mantissa: 1 + 2^-8 -> 1, 1 + 3*2^-8 -> 1 + 2^-6
+    assert list(r) == [1.0, 1.0, 1 + 2.0 ** -6, 3.140625, -2.5, 0.0, 65536.0]
+    x = np.random.default_rng(4).standard_normal(10000) * 10.0 ** np.random.default_rng(5).integers(-5, 5, 10000)
+    rel = np.abs(NN.bf16_round(x) - x) / np.abs(x)
+    assert rel.max() <= 2.0 ** -8 * (1 + 1e-6)
+
+
+def _small_p(**kw):
+    p = dict(O_defaults())
+    p.update(kw)
+    return p
+
+
+def O_defaults():
+    from seeded_inputs import preset
+    return preset("cfg1", nx=16, ny=16, n_contour=8)
+
+
+def test_surrogate_run_with_exact_densities_is_the_exact_run():
+    """A 'network' that returns the exact densities reproduces the plain hybrid step."""
+    p = _small_p()
+    w0 = 0.2 * np.random.default_rng(6).standard_normal((3, p["ny"], p["nx"]))
+    ref = O.init_state(p, w0)
+    for _ in range(5):
+        ref = O.step(ref, p)
+    s = NN.surrogate_run(p, None, w0, 5, 2, dens_fn=lambda w: O.densities(w, p)["phi"])
+    for k in ("omega", "phi", "fstar", "u", "S"):
+        assert np.max(np.abs(s[k] - ref[k])) <= 1e-13 * max(1.0, np.max(np.abs(ref[k]))), k
+    assert max(s["errs"]) < 1e-15
+
+
+def test_surrogate_force_differences_one_estimator():
+    """Frozen flow (no advection): with a biased estimator f = exact + delta,
+    S at every step, including those after exact steps, equals
+    sum_I (f(omega_k) - f(omega_{k-1}))/D_I: the estimator's bias cancels."""
+    p = _small_p(couple_lb=0)
+    rng = np.random.default_rng(7)
+    w0 = 0.2 * rng.standard_normal((3, p["ny"], p["nx"]))
+    delta = 1e-3 * rng.standard_normal((3, p["ny"], p["nx"]))
+    delta[2] = 0.0
+
+    def f(w):
+        return O.densities(w, p)["phi"] + delta
+
+    s = NN.surrogate_run(p, None, w0, 7, 3, dens_fn=f, history=True)
+    D = O.diffusivities(p)
+    for k in range(1, 8):
+        ref = sum((f(s["omegas"][k])[I] - f(s["omegas"][k - 1])[I]) / D[I] for I in range(3))
+        assert np.max(np.abs(s["Ss"][k - 1] - ref)) < 1e-12, k
+    assert np.allclose(s["errs"], np.max(np.abs(delta[:2])), rtol=0, atol=1e-16)
