@@ -165,6 +165,7 @@ struct epdlb_ctx {
   double* snap = nullptr;     // pinned: device maxima at the last check point
   hipEvent_t snap_ev = nullptr;
   bool snap_pending = false;
+  int64_t snap_exact = 0;     // exact steps taken when the snapshot was queued
   template <typename T> T* ptr(size_t off) const { return reinterpret_cast<T*>(base + off); }
 };
 

@@ -258,7 +258,8 @@ int nn_check(epdlb_ctx* c) {
     HIPCHK(hipEventSynchronize(c->snap_ev));
     const double r_nn = c->snap[0], r_ex = c->snap[1];
     c->resid_nn_max = std::max(c->resid_nn_max, r_nn);
-    if (r_nn - r_ex > c->p.resid_tol) {
+    // an exact step since the snapshot has already re-anchored the densities
+    if (r_nn - r_ex > c->p.resid_tol && c->n_exact == c->snap_exact) {
       c->force_exact = true;
       ++c->n_triggered;
     }
@@ -270,6 +271,7 @@ int nn_check(epdlb_ctx* c) {
   launch_k(nn::k_nn_reset, dim3(1), dim3(64), 0, c->stream, scal, 1);
   HIPCHK(hipGetLastError());
   c->snap_pending = true;
+  c->snap_exact = c->n_exact;
   return EPDLB_OK;
 }
 

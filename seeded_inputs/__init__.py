@@ -5,7 +5,7 @@ random initial noise and names the workload parameter sets. Both the CPU
 oracle and the GPU library consume what it produces.
 """
 from .noise import splitmix64_uniforms, gaussian_noise, initial_omega
-from .presets import PRESETS, preset, replica_manifest
+from .presets import PRESETS, base_params, preset, replica_manifest
 
 __all__ = ["splitmix64_uniforms", "gaussian_noise", "initial_omega",
-           "PRESETS", "preset", "replica_manifest"]
+           "PRESETS", "base_params", "preset", "replica_manifest"]

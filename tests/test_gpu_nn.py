@@ -1,0 +1,246 @@
+"""GPU tests of the density surrogate (BF16 MFMA kernels) against the FP64 oracle.
+
+The oracle network runs with the same BF16 storage roundings as the kernels
+(inputs, weights, stored activations and gradients; FP64 sums), so the
+remaining differences come from FP32 accumulation order, which can move a
+stored BF16 value by one unit (2^-8 relative) in a small fraction of
+elements.  Tolerances below are set from that.
+"""
+import numpy as np
+import pytest
+
+from oracle import epdlb_oracle as O
+from oracle import nn_oracle as NN
+from seeded_inputs import preset
+
+pytestmark = pytest.mark.gpu
+
+CH = [(5, 64), (64, 64), (64, 64), (64, 2)]
+
+
+def init_params(seed, phibar=0.05, out_scale=0.3):
+    """He-initialised hidden layers; output layer small with bias at softplus^-1(phibar)."""
+    rng = np.random.default_rng(seed)
+    ps = []
+    for l, (ci, co) in enumerate(CH):
+        W = rng.standard_normal((9, ci, co)) * np.sqrt(2.0 / (9 * ci))
+        b = 0.05 * rng.standard_normal(co)
+        if l == 3:
+            W *= out_scale
+            b = np.full(co, np.log(np.expm1(phibar)))
+        ps.append((W, b))
+    return ps
+
+
+def flatten(ps):
+    return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in ps]).astype(np.float32)
+
+
+def unflatten(v):
+    ps, off = [], 0
+    for ci, co in CH:
+        W = v[off:off + 9 * ci * co].reshape(9, ci, co).astype(np.float64)
+        off += 9 * ci * co
+        b = v[off:off + co].astype(np.float64)
+        off += co
+        ps.append((W, b))
+    return ps
+
+
+def smooth_field(rng, ny, nx, amp, kmax=4):
+    """Random periodic field from low Fourier modes."""
+    y, x = np.mgrid[0:ny, 0:nx]
+    f = np.zeros((ny, nx))
+    for _ in range(12):
+        kx, ky = rng.integers(-kmax, kmax + 1, 2)
+        f += rng.standard_normal() * np.cos(2 * np.pi * (kx * x / nx + ky * y / ny) + rng.uniform(0, 2 * np.pi))
+    return amp * f / np.max(np.abs(f))
+
+
+def make_pairs(nx, ny, count, seed, N=8, f_A=0.5, phi_P=0.1, amp=0.6):
+    p = preset("cfg1", nx=nx, ny=ny, n_contour=N, f_A=f_A, phi_P=phi_P)
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        w = np.stack([smooth_field(rng, ny, nx, amp) for _ in range(3)]) + 0.05 * rng.standard_normal((3, ny, nx))
+        phi = O.densities(w, p)["phi"]
+        out.append((w, phi[:2], p))
+    return out
+
+
+def oracle_forward(ps_r, w, p):
+    x = NN.bf16_round(NN.make_input(w, p["f_A"], p["n_contour"]))
+    o, cache = NN.forward(ps_r, x, NN.bf16_round)
+    return o, cache
+
+
+@pytest.fixture(scope="module")
+def trainer_64x32():
+    from paper_1804_02883_amd import Trainer
+    t = Trainer(64, 32, capacity=8, max_batch=4)
+    pairs = make_pairs(64, 32, 4, seed=11)
+    for s, (w, ph, p) in enumerate(pairs):
+        t.set_pair(s, w, ph, p["f_A"], p["n_contour"])
+    yield t, pairs
+    t.close()
+
+
+def test_forward_matches_oracle(trainer_64x32):
+    t, pairs = trainer_64x32
+    ps = init_params(1)
+    w32 = flatten(ps)
+    t.set_weights(w32)
+    ps_r = NN.round_params(unflatten(w32), NN.bf16_round)
+    for s in (0, 3):
+        w, _, p = pairs[s]
+        got = t.predict(s)  # softplus(o), [2][ny][nx]
+        o, _ = oracle_forward(ps_r, w, p)
+        ref = NN.softplus(np.moveaxis(o, -1, 0))
+        err = np.max(np.abs(got - ref))
+        print(f"slot {s}: max |Phi_hat gpu - oracle| = {err:.3e}, max Phi_hat = {ref.max():.3e}")
+        assert err <= 2e-4 * np.max(np.abs(ref))
+        # and against the unrounded FP64 network: BF16 storage error stays small
+        o64, _ = NN.forward(unflatten(w32), NN.make_input(w, p["f_A"], p["n_contour"]))
+        ref64 = NN.softplus(np.moveaxis(o64, -1, 0))
+        assert np.max(np.abs(got - ref64)) <= 2e-2 * np.max(np.abs(ref64))
+
+
+def test_gradients_match_oracle(trainer_64x32):
+    t, pairs = trainer_64x32
+    ps = init_params(2)
+    w32 = flatten(ps)
+    t.set_weights(w32)
+    slots = [0, 1, 2]
+    scale = 0.1
+    loss, maxerr, g = t.evaluate(slots, scale, grad=True)
+    ps_r = NN.round_params(unflatten(w32), NN.bf16_round)
+    acc = None
+    lsum = 0.0
+    for s in slots:
+        w, ph, p = pairs[s]
+        o, cache = oracle_forward(ps_r, w, p)
+        tgt = np.moveaxis(ph, 0, -1).astype(np.float32).astype(np.float64)
+        l, go = NN.loss_and_grad_output(o, tgt, scale)
+        gr = NN.backward(ps_r, cache, go / len(slots), NN.bf16_round)
+        lsum += l / len(slots)
+        acc = gr if acc is None else [(a[0] + b[0], a[1] + b[1]) for a, b in zip(acc, gr)]
+    print(f"loss gpu {loss:.6e} oracle {lsum:.6e}")
+    assert abs(loss - lsum) <= 1e-3 * lsum
+    gg = unflatten(g)
+    for l in range(4):
+        for k, name in ((0, "W"), (1, "b")):
+            ref = acc[l][k]
+            rel = np.linalg.norm(gg[l][k] - ref) / np.linalg.norm(ref)
+            print(f"layer {l} d{name}: rel L2 {rel:.3e}")
+            assert rel <= 2e-3, (l, name, rel)
+
+
+def test_adam_step_matches_oracle(trainer_64x32):
+    t, _ = trainer_64x32
+    w32 = flatten(init_params(3))
+    t.set_weights(w32)
+    slots = [1, 2]
+    _, _, g = t.evaluate(slots, 0.1, grad=True)
+    lr = 1e-3
+    t.train_step(slots, 0.1, lr)
+    w1 = t.get_weights()
+    ref, _, _ = NN.adam_update(w32.astype(np.float64), g.astype(np.float64), 0.0, 0.0, 1, lr)
+    err = np.max(np.abs(w1 - ref))
+    print(f"max |w1 gpu - oracle Adam| = {err:.3e}")
+    assert err <= 1e-3 * lr + 1e-7 * np.max(np.abs(w32))
+
+
+def test_training_reduces_loss():
+    from paper_1804_02883_amd import Trainer
+    t = Trainer(32, 32, capacity=8, max_batch=4)
+    pairs = make_pairs(32, 32, 8, seed=21)
+    for s, (w, ph, p) in enumerate(pairs):
+        t.set_pair(s, w, ph, p["f_A"], p["n_contour"])
+    t.set_weights(flatten(init_params(4)))
+    l0, e0, _ = t.evaluate(list(range(4)), 0.1)
+    rng = np.random.default_rng(0)
+    for it in range(300):
+        t.train_step(rng.choice(8, 4, replace=False), 0.1, 2e-3)
+    l1, e1, _ = t.evaluate(list(range(4)), 0.1)
+    print(f"loss {l0:.3e} -> {l1:.3e}; max err {e0:.3e} -> {e1:.3e}")
+    assert np.isfinite(l1) and l1 < 0.2 * l0
+    t.close()
+
+
+def sim_params(**kw):
+    base = dict(preset("cfg1"), density_mode=1, fallback_every=3, check_every=1, resid_tol=1e9)
+    base.update(kw)
+    return base
+
+
+def test_surrogate_steps_match_oracle_fp64():
+    from paper_1804_02883_amd import Simulation
+    from seeded_inputs import initial_omega
+    p = sim_params()
+    ps = init_params(5, phibar=0.05, out_scale=0.2)
+    w32 = flatten(ps)
+    w0 = initial_omega(p["nx"], p["ny"], 77, 0.05)
+    sim = Simulation(p)
+    sim.surrogate_set_weights(w32)
+    sim.set_fields(w0)
+    steps = 7
+    sim.step(steps)
+    sim.sync()
+    phi = sim.densities()
+    om = sim.fields()
+    d = sim.diag()
+    ref = NN.surrogate_run(p, NN.round_params(unflatten(w32), NN.bf16_round), w0, steps, 3, rnd=NN.bf16_round)
+    dphi = np.max(np.abs(phi - ref["phi"]))
+    dom = np.max(np.abs(om - ref["omega"]))
+    print(f"surrogate FP64: max dPhi {dphi:.3e}, max domega {dom:.3e}, errs gpu {d['nn_err_max']:.3e} "
+          f"oracle {max(ref['errs']):.3e}, n_exact {d['n_exact']}")
+    assert d["n_exact"] == 3 and d["n_triggered"] == 0
+    assert dphi <= 1e-6 and dom <= 1e-6
+    assert abs(d["nn_err_max"] - max(ref["errs"])) <= 1e-5
+    # mass: species means are exact by construction
+    assert abs(phi[0].mean() - p["f_A"] * p["phi_P"]) < 1e-14
+    sim.close()
+
+
+def test_residual_test_forces_exact_steps():
+    from paper_1804_02883_amd import Simulation
+    # a network whose densities vary far more than the exact ones: its
+    # incompressibility residual exceeds the exact step's
+    p = sim_params(fallback_every=1000, check_every=1, resid_tol=1e-6)
+    sim = Simulation(p)
+    sim.surrogate_set_weights(flatten(init_params(6, out_scale=200.0)))
+    sim.seed(1001, 1e-3)
+    sim.step(12)
+    sim.sync()
+    d = sim.diag()
+    print(d)
+    assert d["resid_nn_max"] > d["resid_exact"] + 1e-6
+    # step 0 is exact; every trigger asks for one exact step (the last may
+    # still be pending); snapshots older than an exact step do not trigger
+    assert d["n_triggered"] >= 2
+    assert d["n_exact"] - 1 in (d["n_triggered"], d["n_triggered"] - 1)
+    sim.close()
+
+
+def test_surrogate_fp32_graph_and_stream_paths_agree():
+    """Captured-graph replay and direct stream launches give identical results."""
+    import os
+    from paper_1804_02883_amd import Simulation
+    p = sim_params(nx=64, ny=64, n_contour=32, precision=1, fallback_every=5, check_every=5)
+    w32 = flatten(init_params(7))
+    out = []
+    for graph in ("1", "0"):
+        os.environ["EPDLB_GRAPH"] = graph
+        sim = Simulation(p)
+        sim.surrogate_set_weights(w32)
+        sim.seed(1002, 1e-3)
+        sim.step(13)
+        sim.sync()
+        out.append((sim.densities(), sim.velocity(), sim.diag()))
+        sim.close()
+    os.environ.pop("EPDLB_GRAPH")
+    assert np.array_equal(out[0][0], out[1][0])
+    assert all(np.array_equal(a, b) for a, b in zip(out[0][1], out[1][1]))
+    assert out[0][2]["n_exact"] == 3
+    phi = out[0][0]
+    assert abs(phi[0].mean() - p["f_A"] * p["phi_P"]) < 1e-6
