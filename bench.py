@@ -1,10 +1,15 @@
-"""Benchmark: lattice site-updates/s of the plain hybrid LB/EPD step on one MI355X.
+"""Benchmark: lattice site-updates/s of the hybrid LB/EPD step on one MI355X.
 
 Workload (default): 1024 x 512 periodic grid, FP32 fields with FP64
 partition-function reductions, N = 64 contour steps, f_A = 0.3, phi_P = 0.15,
 chi reading L, g = 1e-5 f*, seeded Gaussian noise sigma = 1e-3 (seed 1003).
 A "step" is one full hybrid step (advection + EPD update, both chain
 propagators, densities, force reconstruction, D2Q9 LB) on the resident state.
+The line also carries the plain-versus-surrogate comparison on the 512 x 512
+quench (`surrogate`), which `--workload cfg5q` reports as the main line:
+there `value` is the surrogate path's rate over a full run, exact steps
+(every 50 steps and when the residual test fires) included, and `roofline`
+is the MFMA roofline of the 64 -> 64 convolution.
 
 Prints ONE JSON line.  `value` is timed with events around K graph-replayed
 steps.  `roofline` covers the kernel family with the largest share of GPU
@@ -32,6 +37,11 @@ MEASURED_TRAFFIC = {
     ("cfg3", "prop_col"): dict(bytes_per_launch=17291173, source_sha256="473bfc94ccdeb072a69fd59b0ea1ec85b6a01dfb68370ac9eb365a3cbbd0c151"),
 }
 HBM_PEAK_GBS = 8000.0
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense
+WEIGHTS = os.path.join(ROOT, "paper_1804_02883_amd", "weights", "surrogate_q.npy")
+# useful flops per site of each network launch (multiply-add = 2 flops):
+# 9 taps x cin x cout x 2; conv0 has 5 real input channels, the output layer 2
+NN_FLOPS_PER_SITE = {"nn_conv0": 9 * 5 * 64 * 2, "nn_conv": 9 * 64 * 64 * 2, "nn_out": 9 * 64 * 2 * 2}
 
 # Algorithmic bytes per site per hybrid STEP of each kernel family, in units
 # of the element size P (forward and backward chains counted together):
@@ -84,10 +94,72 @@ def cpu_baseline(preset_name, steps):
                        f"(NumPy, single thread), {dt:.1f} s")
 
 
+def surrogate_summary(steps):
+    """Plain vs surrogate on the 512^2 quench (cfg5q), full runs from the seed."""
+    import numpy as np
+    from paper_1804_02883_amd.surrogate_eval import compare
+    from seeded_inputs import PRESETS
+    cfg = PRESETS["cfg5q"]
+    w = np.load(WEIGHTS)
+    r = compare(dict(cfg["params"]), cfg["seed"], cfg["sigma"], w, steps)
+    r["workload"] = f"cfg5q: {cfg['name']}, seed {cfg['seed']}, {r['steps']} steps from the seed"
+    return r
+
+
+def run_surrogate(args):
+    """--workload cfg5q: the surrogate path as the main line."""
+    import numpy as np
+    import torch
+    from paper_1804_02883_amd import Simulation
+    from seeded_inputs import PRESETS
+    cfg = PRESETS["cfg5q"]
+    p = dict(cfg["params"])
+    n = p["nx"] * p["ny"]
+    steps = args.steps if args.steps_given else cfg["steps"]
+    r = surrogate_summary(steps - 50)
+    # per-kernel durations of the surrogate path (100 steps: 2 exact)
+    sim = Simulation(dict(p, density_mode=1, fallback_every=50, check_every=10, resid_tol=1e-3))
+    sim.surrogate_set_weights(np.load(WEIGHTS))
+    sim.seed(cfg["seed"], cfg["sigma"])
+    sim.step(100)
+    sim.sync()
+    sim.profile_start(4000)
+    sim.step(100)
+    prof = sim.profile_read()
+    sim.close()
+    conv = prof["nn_conv"]
+    achieved = NN_FLOPS_PER_SITE["nn_conv"] * n / (conv["avg_ms"] / 1e3) / 1e12
+    roofline = dict(bound="mfma", kernel="nn_conv", achieved=round(achieved, 1), peak=BF16_MFMA_PEAK_TFLOPS,
+                    unit="TFLOP/s", frac=round(achieved / BF16_MFMA_PEAK_TFLOPS, 4), traffic=None,
+                    avg_launch_us=round(conv["avg_ms"] * 1e3, 3), launches_per_step=conv["launches"] / 100,
+                    alg_flops_per_launch=NN_FLOPS_PER_SITE["nn_conv"] * n)
+    tot = sum(x["total_ms"] for x in prof.values())
+    breakdown = {k: dict(launches_per_step=v["launches"] / 100, avg_us=round(v["avg_ms"] * 1e3, 3),
+                         share=round(v["total_ms"] / tot, 4),
+                         tflops=(round(NN_FLOPS_PER_SITE[k] * n / (v["avg_ms"] / 1e3) / 1e12, 1)
+                                 if k in NN_FLOPS_PER_SITE else None))
+                 for k, v in prof.items()}
+    sur = r["surrogate"]
+    out = dict(metric=METRIC, value=sur["value"], unit="site-updates/s", n_gpus=1, steps=r["steps"], warmup=50,
+               ms_per_step=sur["ms_per_step"], higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f32+bf16", data="synthetic",
+               config=dict(workload=r["workload"] + "; exact step every 50 steps and on the residual test",
+                           nx=p["nx"], ny=p["ny"], n_contour=p["n_contour"], path="surrogate"),
+               roofline=roofline, breakdown=breakdown,
+               plain=dict(value=r["plain"]["value"], ms_per_step=r["plain"]["ms_per_step"]),
+               speedup=r["speedup"],
+               density_err=dict(max_at_exact_steps=sur["max_density_err"], last=sur["last_density_err"],
+                                bar=1e-3, uniform_density_err_at_end=r["fluct_max"]),
+               n_exact=sur["n_exact"], n_triggered=sur["n_triggered"], sigma_delta=r["sigma_delta"])
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline("cfg5q", 1)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="cfg3")
     ap.add_argument("--profile-launches", type=int, default=8192)
@@ -96,7 +168,12 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1804_02883_amd", "tune", "gfx950.txt"),
                     help="autotuner results file (read first, new results appended)")
+    ap.add_argument("--surrogate-steps", type=int, default=20000,
+                    help="steps of the plain vs surrogate comparison added to the line (0: skip)")
     args = ap.parse_args()
+    args.steps_given = args.steps is not None
+    if args.steps is None:
+        args.steps = 2000
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU sharding is described in DESIGN.md, not built", file=sys.stderr)
@@ -107,6 +184,8 @@ def main():
     from seeded_inputs import PRESETS, replica_manifest
 
     torch.cuda.set_device(0)
+    if args.workload == "cfg5q":
+        return run_surrogate(args)
     if args.workload == "cfg4":
         man = replica_manifest()
         plist = [m["params"] for m in man]
@@ -183,6 +262,8 @@ def main():
                warmup=args.warmup, ms_per_step=ms_per_step, higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f32" if P == 4 else "f64", data="synthetic",
                config=cfgd, roofline=roofline, breakdown=breakdown, shapes=shapes, Q_P=d["Q_P"])
+    if args.surrogate_steps and args.workload != "cfg4":
+        out["surrogate"] = surrogate_summary(args.surrogate_steps)
     if not args.no_cpu_baseline and args.workload != "cfg4":
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_steps)
     print(json.dumps(out), flush=True)

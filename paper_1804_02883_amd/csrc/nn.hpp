@@ -10,7 +10,10 @@
 // its closed form, so the compressibility constraint on the means holds
 // exactly as for the chain propagators (Sec. II, Eqs. for Phi_P and Phi_S).
 //
-// Tensor storage (bf16, [sample][site][channel]):
+// Tensor storage (bf16, per sample): channel-blocked rows,
+//   [y][x / 32][chunk][x % 32][8 channels],  chunk = position / 8,
+// so that the 32 consecutive sites an MFMA operand covers read (and the
+// epilogue writes) 512 contiguous bytes per 16-byte chunk.  Positions:
 //   16-channel tensors (x, output gradient): channel c at position c.
 //   64-channel tensors (activations, pre-activations, their gradients): the
 //   logical channel c sits at position s(c) chosen so that every lane of the
@@ -70,6 +73,12 @@ __device__ __forceinline__ float softplus(float z) { return fmaxf(z, 0.0f) + log
 
 __device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
+// Element offset of 16-byte chunk c of site (x, y) in a C-channel tensor.
+template <int C>
+__device__ __forceinline__ long blk_off(int x, int y, int nx, int c) {
+  return ((long(y) * (nx >> 5) + (x >> 5)) * (C / 8) + c) * 256 + (x & 31) * 8;
+}
+
 __device__ __forceinline__ double nn_wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -109,6 +118,22 @@ __device__ __forceinline__ void nn_block_reduce(double (&v)[NV], double* red /*[
 // [tap][ks][nb][lane] of 8 bf16 each.  x: this lane's site column; y0: the
 // wave's first row.  nx, ny are powers of two (periodic wrap by masking).
 // ---------------------------------------------------------------------------
+// The activations of tap t+1 are loaded while tap t's MFMAs run.
+template <int CI>
+__device__ __forceinline__ void load_tap(const __bf16* __restrict__ in, int nx, int ny, int d, int x, int y0,
+                                         int t, int g, u32x4 (&v)[kSB][CI / 16]) {
+  constexpr int KS = CI / 16;
+  const int ty = t / 3 - 1, tx = t % 3 - 1;
+  const int xs = (x + d * tx) & (nx - 1);
+#pragma unroll
+  for (int sb = 0; sb < kSB; ++sb) {
+    const int ys = (y0 + sb + d * ty) & (ny - 1);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+      v[sb][ks] = *reinterpret_cast<const u32x4*>(in + blk_off<CI>(xs, ys, nx, KS * g + ks));
+  }
+}
+
 template <int CI, int NB>
 __device__ __forceinline__ void conv_mma(const __bf16* __restrict__ in, const bf16x8* w, int nx, int ny, int d,
                                          int x, int y0, f32x16 (&acc)[kSB][NB]) {
@@ -121,18 +146,27 @@ __device__ __forceinline__ void conv_mma(const __bf16* __restrict__ in, const bf
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[sb][nb][i] = 0.0f;
+  if constexpr (KS == 1) {
+    // few MFMAs per tap: issue every tap's loads first
+    u32x4 all[9][kSB][1];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) load_tap<CI>(in, nx, ny, d, x, y0, t, g, all[t]);
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const bf16x8 a = w[(t * NB + nb) * 64 + lane];
+#pragma unroll
+        for (int sb = 0; sb < kSB; ++sb)
+          acc[sb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, as_bf16x8(all[t][sb][0]), acc[sb][nb], 0, 0, 0);
+      }
+    return;
+  }
+  u32x4 cur[kSB][KS], nxt[kSB][KS];
+  load_tap<CI>(in, nx, ny, d, x, y0, 0, g, cur);
 #pragma unroll 1
   for (int t = 0; t < 9; ++t) {
-    const int ty = t / 3 - 1, tx = t % 3 - 1;
-    const int xs = (x + d * tx) & (nx - 1);
-    u32x4 v[kSB][KS];
-#pragma unroll
-    for (int sb = 0; sb < kSB; ++sb) {
-      const int ys = (y0 + sb + d * ty) & (ny - 1);
-      const u32x4* p = reinterpret_cast<const u32x4*>(in + (long(ys) * nx + xs) * CI + (CI / 2) * g);
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) v[sb][ks] = p[ks];
-    }
+    if (t < 8) load_tap<CI>(in, nx, ny, d, x, y0, t + 1, g, nxt);
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
@@ -140,8 +174,12 @@ __device__ __forceinline__ void conv_mma(const __bf16* __restrict__ in, const bf
         const bf16x8 a = w[((t * KS + ks) * NB + nb) * 64 + lane];
 #pragma unroll
         for (int sb = 0; sb < kSB; ++sb)
-          acc[sb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, as_bf16x8(v[sb][ks]), acc[sb][nb], 0, 0, 0);
+          acc[sb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, as_bf16x8(cur[sb][ks]), acc[sb][nb], 0, 0, 0);
       }
+#pragma unroll
+    for (int sb = 0; sb < kSB; ++sb)
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) cur[sb][ks] = nxt[sb][ks];
   }
 }
 
@@ -199,7 +237,8 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_hidden(ConvArgs P) {
   if (EPI != EPI_BWD && threadIdx.x < kHid) bias_s[threadIdx.x] = P.bias[threadIdx.x];
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, h = lane >> 5;
-  for (int tile = blockIdx.x; tile < P.ntiles; tile += gridDim.x) {
+  const int blk = xcd_tile(blockIdx.x, gridDim.x);
+  for (int tile = blk; tile < P.ntiles; tile += gridDim.x) {
     const TileInfo ti = tile_of(tile, P.nx, P.tiles_per_sample);
     const __bf16* in = P.in + long(P.slots ? P.slots[ti.z] : ti.z) * P.in_bs;
     const int x = ti.x0 + (lane & 31);
@@ -208,14 +247,13 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_hidden(ConvArgs P) {
     conv_mma<CI, NB>(in, w, P.nx, P.ny, P.d, x, y0, acc);
 #pragma unroll
     for (int sb = 0; sb < kSB; ++sb) {
-      const long site = long(y0 + sb) * P.nx + x;
-      const long base = long(ti.z) * P.bs + site * kHid + 32 * h;
+      // this lane's 32 positions are chunks 4h .. 4h+3 of its site
+      const long base = long(ti.z) * P.bs + blk_off<kHid>(x, y0 + sb, P.nx, 4 * h);
       float v[32];
       if (EPI == EPI_BWD) {
-        const u32x4* zp = reinterpret_cast<const u32x4*>(P.zin + base);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const bf16x8 zz = as_bf16x8(zp[q]);
+          const bf16x8 zz = as_bf16x8(*reinterpret_cast<const u32x4*>(P.zin + base + q * 256));
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
             const int s = 8 * q + j;  // position within this lane's 32
@@ -229,25 +267,23 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_hidden(ConvArgs P) {
           v[s] = acc[sb][nb][i] + bias_s[32 * nb + 8 * (i >> 2) + 4 * h + (i & 3)];
         }
         if (EPI == EPI_FWD_TRAIN) {
-          u32x4* zp = reinterpret_cast<u32x4*>(P.zout + base);
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             bf16x8 o;
 #pragma unroll
             for (int j = 0; j < 8; ++j) o[j] = __bf16(v[8 * q + j]);
-            zp[q] = __builtin_bit_cast(u32x4, o);
+            *reinterpret_cast<u32x4*>(P.zout + base + q * 256) = __builtin_bit_cast(u32x4, o);
           }
         }
 #pragma unroll
         for (int s = 0; s < 32; ++s) v[s] = silu(v[s]);
       }
-      u32x4* op = reinterpret_cast<u32x4*>(P.out + base);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         bf16x8 o;
 #pragma unroll
         for (int j = 0; j < 8; ++j) o[j] = __bf16(v[8 * q + j]);
-        op[q] = __builtin_bit_cast(u32x4, o);
+        *reinterpret_cast<u32x4*>(P.out + base + q * 256) = __builtin_bit_cast(u32x4, o);
       }
     }
   }
@@ -292,7 +328,8 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_out(OutArgs<T> P) {
   const float b0 = P.bias[0], b1 = P.bias[1];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   double r[2] = {0.0, 0.0};  // INFER: sums of Phi_hat_A, B; TRAIN: sum r^2, max |err|
-  for (int tile = blockIdx.x; tile < P.ntiles; tile += gridDim.x) {
+  const int blk = xcd_tile(blockIdx.x, gridDim.x);
+  for (int tile = blk; tile < P.ntiles; tile += gridDim.x) {
     const TileInfo ti = tile_of(tile, P.nx, P.tiles_per_sample);
     const __bf16* in = P.in + long(ti.z) * P.in_bs;
     const int x = ti.x0 + (lane & 31);
@@ -321,9 +358,9 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_out(OutArgs<T> P) {
           for (int j = 0; j < 8; ++j) gv[j] = zero[j] = __bf16(0.0f);
           gv[0] = __bf16(P.gscale * r0 * sigm(o0));
           gv[1] = __bf16(P.gscale * r1 * sigm(o1));
-          u32x4* gp = reinterpret_cast<u32x4*>(P.gout + (long(ti.z) * P.plane + site) * kXC);
-          gp[0] = __builtin_bit_cast(u32x4, gv);
-          gp[1] = __builtin_bit_cast(u32x4, zero);
+          __bf16* gp = P.gout + long(ti.z) * P.plane * kXC;
+          *reinterpret_cast<u32x4*>(gp + blk_off<kXC>(x, y0 + sb, P.nx, 0)) = __builtin_bit_cast(u32x4, gv);
+          *reinterpret_cast<u32x4*>(gp + blk_off<kXC>(x, y0 + sb, P.nx, 1)) = __builtin_bit_cast(u32x4, zero);
         }
       }
     }
@@ -366,12 +403,13 @@ __device__ __forceinline__ void stage_tile(const __bf16* __restrict__ src, __bf1
                                            int gy0, int hw, int hh) {
   constexpr int RS = C + 8;
   constexpr int CH = C / 8;  // 16-byte chunks per site
-  const int total = hw * hh * CH;
+  const int sites = hw * hh;
+  const int total = sites * CH;
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    const int ch = e % CH, s = e / CH;
+    const int ch = e / sites, s = e - ch * sites;  // consecutive threads: consecutive sites
     const int hx = s % hw, hy = s / hw;
     const int gx = (gx0 + hx) & (nx - 1), gy = (gy0 + hy) & (ny - 1);
-    const u32x4 v = *reinterpret_cast<const u32x4*>(src + (long(gy) * nx + gx) * C + 8 * ch);
+    const u32x4 v = *reinterpret_cast<const u32x4*>(src + blk_off<C>(gx, gy, nx, ch));
     *reinterpret_cast<u32x4*>(dst + long(s) * RS + 8 * ch) = v;
   }
 }
@@ -556,10 +594,11 @@ __global__ void __launch_bounds__(256) k_adam(float* w, const float* g, float* m
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256) k_nn_input(const T* __restrict__ w, const double* __restrict__ mean,
-                                                  long n, float fA, float invN, __bf16* __restrict__ x,
+                                                  long n, int nx, float fA, float invN, __bf16* __restrict__ x,
                                                   const T* __restrict__ phi, float* __restrict__ tgt) {
   const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const int sx = int(i % nx), sy = int(i / nx);
   bf16x8 v0, v1;
   v0[0] = __bf16(float(double(w[i]) - mean[0]));
   v0[1] = __bf16(float(double(w[n + i]) - mean[1]));
@@ -570,9 +609,8 @@ __global__ void __launch_bounds__(256) k_nn_input(const T* __restrict__ w, const
   for (int j = 5; j < 8; ++j) v0[j] = __bf16(0.0f);
 #pragma unroll
   for (int j = 0; j < 8; ++j) v1[j] = __bf16(0.0f);
-  u32x4* xp = reinterpret_cast<u32x4*>(x + i * kXC);
-  xp[0] = __builtin_bit_cast(u32x4, v0);
-  xp[1] = __builtin_bit_cast(u32x4, v1);
+  *reinterpret_cast<u32x4*>(x + blk_off<kXC>(sx, sy, nx, 0)) = __builtin_bit_cast(u32x4, v0);
+  *reinterpret_cast<u32x4*>(x + blk_off<kXC>(sx, sy, nx, 1)) = __builtin_bit_cast(u32x4, v1);
   if (tgt) {
     tgt[i] = float(phi[i]);
     tgt[n + i] = float(phi[n + i]);
@@ -582,8 +620,12 @@ __global__ void __launch_bounds__(256) k_nn_input(const T* __restrict__ w, const
 
 // Maximum of non-negative doubles: their bit patterns order like the values
 // (a NaN orders above every finite value and so stays visible).
+// Most workgroups find the running maximum already larger and skip the atomic.
 __device__ __forceinline__ void atomic_max_nonneg(double* p, double v) {
-  atomicMax(reinterpret_cast<unsigned long long*>(p), static_cast<unsigned long long>(__double_as_longlong(v)));
+  unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
+  const unsigned long long bits = static_cast<unsigned long long>(__double_as_longlong(v));
+  if (__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= bits) return;
+  atomicMax(q, bits);
 }
 
 // ---------------------------------------------------------------------------

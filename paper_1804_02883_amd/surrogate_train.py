@@ -1,9 +1,10 @@
 """Training driver of the density surrogate.
 
 Pairs (potentials -> exact densities) come from the library's exact GPU path:
-seeded quenches (chi reading Q) on 256 x 256 grids, sampled every `every`
-steps, with the two model parameter sets of the 256^2 and 1024x512 workloads
-(N = 32, f_A = 0.5, phibar_P = 0.1 and N = 64, f_A = 0.3, phibar_P = 0.15).
+seeded quenches (chi reading Q, initial noise amplitudes `sigmas`) on
+256 x 256 grids, sampled every `every` steps, with the two model parameter
+sets of the 256^2 and 1024x512 workloads (N = 32, f_A = 0.5,
+phibar_P = 0.1 and N = 64, f_A = 0.3, phibar_P = 0.15).
 Training runs entirely in the library's HIP kernels (forward, backward-data,
 weight-gradient, Adam); this script only schedules them.
 
@@ -42,27 +43,34 @@ def param_sets(grid):
     ]
 
 
-def generate(trainer, psets, seeds, steps, every, slot0, log):
-    """Runs each (parameter set, seed) quench and captures a pair every `every` steps."""
+def schedule(steps, every, early, early_every):
+    """Step counts between captures: every `early_every` steps up to step
+    `early` (the fast relaxation right after the quench), then every `every`."""
+    out = [early_every] * (early // early_every) if early_every else []
+    out += [every] * ((steps - sum(out)) // every)
+    return out
+
+
+def generate(trainer, psets, runs, sched, slot0, log):
+    """Runs each (parameter set, seed, sigma) quench and captures a pair after each schedule entry."""
     from paper_1804_02883_amd import Simulation
     slot = slot0
-    for pi, p in enumerate(psets):
-        for seed in seeds:
-            sim = Simulation(p)
-            sim.seed(int(seed), 1e-3)
-            t0 = time.perf_counter()
-            amp = []
-            for k in range(steps // every):
-                sim.step(every)
-                trainer.capture(slot, sim)
-                slot += 1
-                if (k + 1) % max(1, (steps // every) // 4) == 0:
-                    phi = sim.densities()
-                    amp.append(round(float(np.max(np.abs(phi[0] - phi[0].mean()))), 5))
-            sim.sync()
-            log(dict(event="generated", pset=pi, seed=int(seed), pairs=steps // every,
-                     seconds=round(time.perf_counter() - t0, 2), amp_phiA=amp))
-            sim.close()
+    for pi, seed, sigma in runs:
+        sim = Simulation(psets[pi])
+        sim.seed(int(seed), float(sigma))
+        t0 = time.perf_counter()
+        amp = []
+        for k, gap in enumerate(sched):
+            sim.step(gap)
+            trainer.capture(slot, sim)
+            slot += 1
+            if (k + 1) % max(1, len(sched) // 4) == 0:
+                phi = sim.densities()
+                amp.append(round(float(np.max(np.abs(phi[0] - phi[0].mean()))), 5))
+        sim.sync()
+        log(dict(event="generated", pset=pi, seed=int(seed), sigma=sigma, pairs=len(sched),
+                 seconds=round(time.perf_counter() - t0, 2), amp_phiA=amp))
+        sim.close()
     return slot
 
 
@@ -99,15 +107,21 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
     ap.add_argument("--grid", type=int, default=256)
-    ap.add_argument("--seeds", type=int, default=6, help="training quenches per parameter set")
+    ap.add_argument("--seeds", type=int, default=3, help="quenches per sigma, 256^2-workload parameters")
+    ap.add_argument("--seeds1", type=int, default=1, help="quenches per sigma, 1024x512-workload parameters")
+    ap.add_argument("--sigmas", default="0.03,0.05,0.08", help="initial noise amplitudes of the quenches")
     ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--every", type=int, default=50)
+    ap.add_argument("--every", type=int, default=25)
+    ap.add_argument("--early", type=int, default=500)
+    ap.add_argument("--early-every", type=int, default=5)
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--phi-scale", type=float, default=0.1)
     ap.add_argument("--init-seed", type=int, default=0)
     ap.add_argument("--init", default=None, help="start from these weights (.npy)")
+    ap.add_argument("--eval-steps", type=int, default=2000,
+                    help="steps of the 512x512 quench compared plain vs surrogate after training (0: skip)")
     args = ap.parse_args(argv)
 
     import torch
@@ -118,14 +132,18 @@ def main(argv=None):
         print(json.dumps(d), flush=True)
 
     psets = param_sets(args.grid)
-    per = args.steps // args.every
-    n_train = len(psets) * args.seeds * per
-    n_val = len(psets) * per
+    sigmas = [float(x) for x in args.sigmas.split(",")]
+    sched = schedule(args.steps, args.every, args.early, args.early_every)
+    per = len(sched)
+    train_runs = [(pi, 20000 + 1000 * pi + 100 * j + i, sg) for pi, ns in ((0, args.seeds), (1, args.seeds1))
+                  for j, sg in enumerate(sigmas) for i in range(ns)]
+    val_runs = [(0, 29999, sigmas[len(sigmas) // 2])]
+    n_train = len(train_runs) * per
+    n_val = len(val_runs) * per
     tr = Trainer(args.grid, args.grid, n_train + n_val, args.batch)
     t0 = time.perf_counter()
-    train_seeds = [20000 + i for i in range(args.seeds)]
-    end = generate(tr, psets, train_seeds, args.steps, args.every, 0, log)
-    generate(tr, psets, [29999], args.steps, args.every, end, log)
+    end = generate(tr, psets, train_runs, sched, 0, log)
+    generate(tr, psets, val_runs, sched, end, log)
     log(dict(event="data", train_pairs=n_train, val_pairs=n_val, seconds=round(time.perf_counter() - t0, 1)))
     w0 = np.load(args.init) if args.init else init_weights(args.init_seed)
     tr.set_weights(w0)
@@ -135,6 +153,14 @@ def main(argv=None):
     np.save(args.out, w)
     log(dict(event="saved", path=args.out, params=int(w.size), seconds=round(time.perf_counter() - t0, 1)))
     tr.close()
+    if args.eval_steps:
+        from paper_1804_02883_amd.surrogate_eval import compare, error_trace
+        from seeded_inputs import PRESETS
+        cfg = PRESETS["cfg5q"]
+        r = compare(dict(cfg["params"]), cfg["seed"], cfg["sigma"], w, args.eval_steps)
+        log(dict(event="eval", workload="cfg5q", **r))
+        tr_ = error_trace(dict(cfg["params"]), cfg["seed"], cfg["sigma"], w, args.eval_steps)
+        log(dict(event="error_trace", workload="cfg5q", **tr_))
 
 
 if __name__ == "__main__":

@@ -46,6 +46,11 @@ PRESETS = {
     "cfg5": dict(params=base_params(512, 512, 32, 0.5, 0.1, "L", 1e-5),
                  steps=20000, seed=1005, sigma=1e-3,
                  name="512x512 FP32 N=32 f_A=0.5 phi_P=0.1"),
+    # the surrogate comparison: a quench (reading Q) from a stronger seeded
+    # noise, so that the density fluctuations exceed the 1e-3 error bar
+    "cfg5q": dict(params=base_params(512, 512, 32, 0.5, 0.1, "Q", 1e-5),
+                  steps=20000, seed=1005, sigma=0.05,
+                  name="512x512 FP32 N=32 f_A=0.5 phi_P=0.1, chi reading Q, noise 0.05"),
 }
 
 
