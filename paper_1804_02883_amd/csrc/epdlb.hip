@@ -2051,7 +2051,7 @@ int epdlb_nn_set_pair(epdlb_nn* t, int32_t slot, const double* omega, const doub
   }
   HIPCHK(hipMemcpyAsync(t->stage, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, t->stream));
   hipLaunchKernelGGL(nn::k_nn_input<double>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, t->stream,
-                     (const double*)t->stage, (const double*)(t->stage + 5 * n), long(n), float(f_A),
+                     (const double*)t->stage, (const double*)(t->stage + 5 * n), long(n), t->nx, float(f_A),
                      float(1.0 / n_contour), t->x + size_t(slot) * n * nn::kXC, (const double*)(t->stage + 3 * n),
                      t->tgt + size_t(slot) * 2 * n);
   HIPCHK(hipGetLastError());
@@ -2075,11 +2075,11 @@ int epdlb_nn_capture(epdlb_nn* t, int32_t slot, epdlb_ctx* c) {
   float* tg = t->tgt + size_t(slot) * 2 * n;
   if (c->p.precision == 0)
     hipLaunchKernelGGL(nn::k_nn_input<double>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, t->stream,
-                       (const double*)c->ptr<double>(c->L.omega[c->cur]), mean, n, fA, invN, x,
+                       (const double*)c->ptr<double>(c->L.omega[c->cur]), mean, n, t->nx, fA, invN, x,
                        (const double*)c->ptr<double>(c->L.phi), tg);
   else
     hipLaunchKernelGGL(nn::k_nn_input<float>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, t->stream,
-                       (const float*)c->ptr<float>(c->L.omega[c->cur]), mean, n, fA, invN, x,
+                       (const float*)c->ptr<float>(c->L.omega[c->cur]), mean, n, t->nx, fA, invN, x,
                        (const float*)c->ptr<float>(c->L.phi), tg);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(t->stream));

@@ -147,7 +147,7 @@ int stage_nn(epdlb_ctx* c, int mode, int use_corr) {
   {
     ProfScope ps(c, K_NN_INPUT);
     launch_k(nn::k_nn_input<T>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, c->stream, (const T*)w,
-             (const double*)(scal + kMeanA), n, float(p.f_A), float(1.0 / p.n_contour), x, (const T*)nullptr,
+             (const double*)(scal + kMeanA), n, p.nx, float(p.f_A), float(1.0 / p.n_contour), x, (const T*)nullptr,
              (float*)nullptr);
   }
   HIPCHK(hipGetLastError());
