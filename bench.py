@@ -118,7 +118,7 @@ def run_surrogate(args):
     steps = args.steps if args.steps_given else cfg["steps"]
     r = surrogate_summary(steps - 50)
     # per-kernel durations of the surrogate path (100 steps: 2 exact)
-    sim = Simulation(dict(p, density_mode=1, fallback_every=50, check_every=10, resid_tol=1e-3))
+    sim = Simulation(dict(p, density_mode=1, fallback_every=50, check_every=10, resid_tol=1e-3, err_tol=0.0))
     sim.surrogate_set_weights(np.load(WEIGHTS))
     sim.seed(cfg["seed"], cfg["sigma"])
     sim.step(100)
@@ -143,13 +143,15 @@ def run_surrogate(args):
     out = dict(metric=METRIC, value=sur["value"], unit="site-updates/s", n_gpus=1, steps=r["steps"], warmup=50,
                ms_per_step=sur["ms_per_step"], higher_is_better=True, scaling="weak", vs_baseline=None,
                dtype="f32+bf16", data="synthetic",
-               config=dict(workload=r["workload"] + "; exact step every 50 steps and on the residual test",
+               config=dict(workload=r["workload"] + "; exact step every 50 steps, on the residual test, and "
+                           "while the last measured surrogate error exceeds 9e-4",
                            nx=p["nx"], ny=p["ny"], n_contour=p["n_contour"], path="surrogate"),
                roofline=roofline, breakdown=breakdown,
                plain=dict(value=r["plain"]["value"], ms_per_step=r["plain"]["ms_per_step"]),
                speedup=r["speedup"],
-               density_err=dict(max_at_exact_steps=sur["max_density_err"], last=sur["last_density_err"],
-                                bar=1e-3, uniform_density_err_at_end=r["fluct_max"]),
+               density_err=dict(in_use=sur["density_err_in_use"], bar=1e-3,
+                                max_at_exact_steps=sur["max_density_err"], last=sur["last_density_err"],
+                                uniform_density_err_at_end=r["fluct_max"]),
                n_exact=sur["n_exact"], n_triggered=sur["n_triggered"], sigma_delta=r["sigma_delta"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline("cfg5q", 1)

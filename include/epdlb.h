@@ -74,11 +74,16 @@ typedef struct {
    * surrogate's incompressibility residual max|sum_I Phi_I - 1| exceeds the
    * last exact step's by more than resid_tol.  The residual is read by the
    * host every check_every steps, one interval behind the device, so a
-   * triggered exact step comes at most 2*check_every steps late. */
+   * triggered exact step comes at most 2*check_every steps late.  With
+   * err_tol > 0 the surrogate is used only while the last exact step
+   * measured its density error (max over sites, A and B, of
+   * |Phi_NN - Phi_exact|) within err_tol; otherwise every step is exact (in
+   * particular from seeding until the first such measurement is read). */
   int32_t density_mode;
   int32_t fallback_every; /* default 50 */
   int32_t check_every;    /* default 10 */
   double resid_tol;       /* default 1e-3 */
+  double err_tol;         /* default 1e-3; 0 disables the requirement */
 } epdlb_params;
 
 /* Scalars maintained on the device (FP64). */
@@ -96,6 +101,7 @@ typedef struct {
   double nn_err_max;     /* maximum of nn_err_last over all exact steps (and the seed) */
   double resid_nn_max;   /* max |sum_I Phi_I - 1| over surrogate steps since seeding */
   double resid_exact;    /* the same for the last exact step */
+  double nn_err_in_use;  /* max of nn_err_last over exact steps that ended a run of surrogate steps */
 } epdlb_diag;
 
 /* Stage identifiers for epdlb_run_stage (one hybrid step = 1, 2, 3, 4). */

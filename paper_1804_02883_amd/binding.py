@@ -51,7 +51,7 @@ class epdlb_params(ctypes.Structure):
         ("g_units", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("init_flow", ctypes.c_int32), ("couple_lb", ctypes.c_int32),
         ("density_mode", ctypes.c_int32), ("fallback_every", ctypes.c_int32),
-        ("check_every", ctypes.c_int32), ("resid_tol", ctypes.c_double),
+        ("check_every", ctypes.c_int32), ("resid_tol", ctypes.c_double), ("err_tol", ctypes.c_double),
     ]
 
 
@@ -64,6 +64,7 @@ class epdlb_diag(ctypes.Structure):
         ("n_exact", ctypes.c_int64), ("n_triggered", ctypes.c_int64),
         ("nn_err_last", ctypes.c_double), ("nn_err_max", ctypes.c_double),
         ("resid_nn_max", ctypes.c_double), ("resid_exact", ctypes.c_double),
+        ("nn_err_in_use", ctypes.c_double),
     ]
 
 
@@ -306,7 +307,7 @@ def _diag_dict(d):
     return dict(step=d.step, Q_P=d.Q_P, Q_P_bwd=d.Q_P_bwd, Q_S=d.Q_S, gauge_S=d.gauge_S,
                 mean_omega=tuple(d.mean_omega), n_exact=d.n_exact, n_triggered=d.n_triggered,
                 nn_err_last=d.nn_err_last, nn_err_max=d.nn_err_max, resid_nn_max=d.resid_nn_max,
-                resid_exact=d.resid_exact)
+                resid_exact=d.resid_exact, nn_err_in_use=d.nn_err_in_use)
 
 
 def epdlb_autotune(ctx, reps=20, cache_path=None):

@@ -162,6 +162,7 @@ struct epdlb_ctx {
   bool force_exact = false;   // residual test asks for an exact step
   int64_t n_exact = 0, n_triggered = 0;
   double resid_nn_max = 0.0;
+  bool validated = false;     // the last measured surrogate error is within err_tol
   double* snap = nullptr;     // pinned: device maxima at the last check point
   hipEvent_t snap_ev = nullptr;
   bool snap_pending = false;
@@ -240,8 +241,10 @@ int validate(const epdlb_params* p) {
     return fail(EPDLB_EINVAL, "non-finite parameter");
   if (p->density_mode != 0 && p->density_mode != 1) return fail(EPDLB_EINVAL, "density_mode must be 0 or 1");
   if (p->density_mode == 1 &&
-      (p->fallback_every < 1 || p->check_every < 1 || !(p->resid_tol > 0.0) || !std::isfinite(p->resid_tol)))
-    return fail(EPDLB_EINVAL, "surrogate mode needs fallback_every >= 1, check_every >= 1, resid_tol > 0");
+      (p->fallback_every < 1 || p->check_every < 1 || !(p->resid_tol > 0.0) || !std::isfinite(p->resid_tol) ||
+       !(p->err_tol >= 0.0) || !std::isfinite(p->err_tol)))
+    return fail(EPDLB_EINVAL,
+                "surrogate mode needs fallback_every >= 1, check_every >= 1, resid_tol > 0, err_tol >= 0");
   return EPDLB_OK;
 }
 
@@ -1203,6 +1206,7 @@ int epdlb_params_default(epdlb_params* p) {
   p->fallback_every = 50;
   p->check_every = 10;
   p->resid_tol = 1e-3;
+  p->err_tol = 1e-3;
   return EPDLB_OK;
 }
 
@@ -1277,7 +1281,7 @@ int epdlb_create(const epdlb_params* p, int device, void* stream, void* workspac
   }
   default_shapes(c);
   if (p->density_mode == 1) {
-    if (hipHostMalloc(reinterpret_cast<void**>(&c->snap), 2 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->snap), 3 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&c->snap_ev, hipEventDisableTiming) != hipSuccess) {
       epdlb_destroy(c);
       return fail(EPDLB_ENOMEM, "pinned host buffer or event for the residual test failed");
@@ -1336,7 +1340,8 @@ int epdlb_step(epdlb_ctx* c, int64_t n) {
   if (c->p.density_mode == 1) {
     if (!c->nn_ready) return fail(EPDLB_ESTATE, "surrogate mode: weights not loaded (epdlb_surrogate_set_weights)");
     for (int64_t s = 0; s < n; ++s) {
-      const bool exact = c->force_exact || c->nstep % c->p.fallback_every == 0;
+      const bool exact = c->force_exact || c->nstep % c->p.fallback_every == 0 ||
+                         (c->p.err_tol > 0.0 && !c->validated);
       const int kind = (exact ? 3 : 1) + (c->last_exact ? 1 : 0);
       if (c->use_graph && !c->prof_on) {
         hipGraphExec_t g;
@@ -1470,6 +1475,7 @@ int epdlb_read_diag(epdlb_ctx* c, epdlb_diag* d) {
   d->nn_err_max = s[kNnErr];
   d->resid_nn_max = std::max(c->resid_nn_max, s[kNnResid]);
   d->resid_exact = s[kResidEx];
+  d->nn_err_in_use = s[kNnErrUse];
   return EPDLB_OK;
 }
 

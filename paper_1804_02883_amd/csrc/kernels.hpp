@@ -21,7 +21,8 @@ enum Scal : int {
   kResidEx = 9,                         // max |sum Phi - 1| of the last exact step
   kNnErrLast = 10,                      // max |Phi_NN - Phi_exact| (A, B) at the last exact step
   kNnErr = 11,                          // the same, maximum over all exact steps
-  kNumScal = 12
+  kNnErrUse = 12,                       // the same, over exact steps that ended surrogate steps
+  kNumScal = 13
 };
 
 // ---------------------------------------------------------------------------

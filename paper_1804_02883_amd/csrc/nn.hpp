@@ -194,13 +194,13 @@ __device__ __forceinline__ void stage_weights(const __bf16* __restrict__ src, bf
 struct TileInfo {
   int z, x0, y0;
 };
-__device__ __forceinline__ TileInfo tile_of(int tile, int nx, int tiles_per_sample) {
+__device__ __forceinline__ TileInfo tile_of(int tile, int nx, int tiles_per_sample, int th = kConvTH) {
   TileInfo ti;
   ti.z = tile / tiles_per_sample;
   const int r = tile - ti.z * tiles_per_sample;
   const int tx = nx / kTW;
   ti.x0 = (r % tx) * kTW;
-  ti.y0 = (r / tx) * kConvTH;
+  ti.y0 = (r / tx) * th;
   return ti;
 }
 
@@ -227,28 +227,17 @@ struct ConvArgs {
   int tiles_per_sample, ntiles;
 };
 
-template <int CI, int EPI>
-__global__ void __launch_bounds__(kConvThreads) k_conv_hidden(ConvArgs P) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char nn_lds[];
-  constexpr int KS = CI / 16, NB = 2;
-  bf16x8* w = reinterpret_cast<bf16x8*>(nn_lds);
-  __shared__ float bias_s[kHid];
-  stage_weights(P.wfrag, w, 9 * KS * NB * 64 * 16);
-  if (EPI != EPI_BWD && threadIdx.x < kHid) bias_s[threadIdx.x] = P.bias[threadIdx.x];
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, h = lane >> 5;
-  const int blk = xcd_tile(blockIdx.x, gridDim.x);
-  for (int tile = blk; tile < P.ntiles; tile += gridDim.x) {
-    const TileInfo ti = tile_of(tile, P.nx, P.tiles_per_sample);
-    const __bf16* in = P.in + long(P.slots ? P.slots[ti.z] : ti.z) * P.in_bs;
-    const int x = ti.x0 + (lane & 31);
-    const int y0 = ti.y0 + wid * kSB;
-    f32x16 acc[kSB][NB];
-    conv_mma<CI, NB>(in, w, P.nx, P.ny, P.d, x, y0, acc);
+// Bias + SiLU (forward) or SiLU'(z) (backward-data) and the stores of one
+// wave's kSB x 32 sites x 64 channels.
+template <int EPI>
+__device__ __forceinline__ void epilogue_hidden(const ConvArgs& P, f32x16 (&acc)[kSB][2], int z, int x, int y0,
+                                                const float* bias_s) {
+  const int h = (threadIdx.x & 63) >> 5;
+  {
 #pragma unroll
     for (int sb = 0; sb < kSB; ++sb) {
       // this lane's 32 positions are chunks 4h .. 4h+3 of its site
-      const long base = long(ti.z) * P.bs + blk_off<kHid>(x, y0 + sb, P.nx, 4 * h);
+      const long base = long(z) * P.bs + blk_off<kHid>(x, y0 + sb, P.nx, 4 * h);
       float v[32];
       if (EPI == EPI_BWD) {
 #pragma unroll
@@ -286,6 +275,28 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_hidden(ConvArgs P) {
         *reinterpret_cast<u32x4*>(P.out + base + q * 256) = __builtin_bit_cast(u32x4, o);
       }
     }
+  }
+}
+
+template <int CI, int EPI>
+__global__ void __launch_bounds__(kConvThreads) k_conv_hidden(ConvArgs P) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char nn_lds[];
+  constexpr int KS = CI / 16, NB = 2;
+  bf16x8* w = reinterpret_cast<bf16x8*>(nn_lds);
+  __shared__ float bias_s[kHid];
+  stage_weights(P.wfrag, w, 9 * KS * NB * 64 * 16);
+  if (EPI != EPI_BWD && threadIdx.x < kHid) bias_s[threadIdx.x] = P.bias[threadIdx.x];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, h = lane >> 5;
+  const int blk = xcd_tile(blockIdx.x, gridDim.x);
+  for (int tile = blk; tile < P.ntiles; tile += gridDim.x) {
+    const TileInfo ti = tile_of(tile, P.nx, P.tiles_per_sample);
+    const __bf16* in = P.in + long(P.slots ? P.slots[ti.z] : ti.z) * P.in_bs;
+    const int x = ti.x0 + (lane & 31);
+    const int y0 = ti.y0 + wid * kSB;
+    f32x16 acc[kSB][NB];
+    conv_mma<CI, NB>(in, w, P.nx, P.ny, P.d, x, y0, acc);
+    epilogue_hidden<EPI>(P, acc, ti.z, x, y0, bias_s);
   }
 }
 
@@ -705,6 +716,7 @@ __global__ void __launch_bounds__(256) k_nn_norm(NormArgs<T> P) {
     } else {
       atomic_max_nonneg(P.scal + kNnErrLast, m[1]);
       atomic_max_nonneg(P.scal + kNnErr, m[1]);
+      if (!P.use_corr) atomic_max_nonneg(P.scal + kNnErrUse, m[1]);  // surrogate steps came before
       atomic_max_nonneg(P.scal + kResidEx, m[2]);
     }
   }
@@ -713,7 +725,7 @@ __global__ void __launch_bounds__(256) k_nn_norm(NormArgs<T> P) {
 // Clears scal slots (bit i of mask: slot kNnResid + i).  One thread.
 __global__ void k_nn_reset(double* scal, int mask) {
   if (threadIdx.x == 0)
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 5; ++i)
       if (mask & (1 << i)) scal[kNnResid + i] = 0.0;
 }
 

@@ -256,8 +256,10 @@ int run_sur_step(epdlb_ctx* c, int kind) {
 int nn_check(epdlb_ctx* c) {
   if (c->snap_pending) {
     HIPCHK(hipEventSynchronize(c->snap_ev));
-    const double r_nn = c->snap[0], r_ex = c->snap[1];
+    const double r_nn = c->snap[0], r_ex = c->snap[1], err_last = c->snap[2];
     c->resid_nn_max = std::max(c->resid_nn_max, r_nn);
+    // the surrogate is trusted while the last exact step measured its error within err_tol
+    if (c->p.err_tol > 0.0) c->validated = err_last <= c->p.err_tol;
     // an exact step since the snapshot has already re-anchored the densities
     if (r_nn - r_ex > c->p.resid_tol && c->n_exact == c->snap_exact) {
       c->force_exact = true;
@@ -266,7 +268,7 @@ int nn_check(epdlb_ctx* c) {
     c->snap_pending = false;
   }
   double* scal = c->ptr<double>(c->L.scal);
-  HIPCHK(hipMemcpyAsync(c->snap, scal + kNnResid, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(c->snap, scal + kNnResid, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipEventRecord(c->snap_ev, c->stream));
   launch_k(nn::k_nn_reset, dim3(1), dim3(64), 0, c->stream, scal, 1);
   HIPCHK(hipGetLastError());
@@ -280,14 +282,19 @@ int nn_check(epdlb_ctx* c) {
 int nn_after_seed(epdlb_ctx* c) {
   c->last_exact = true;
   c->force_exact = false;
+  c->validated = false;
   c->n_exact = 0;
   c->n_triggered = 0;
   c->resid_nn_max = 0.0;
   c->snap_pending = false;
-  launch_k(nn::k_nn_reset, dim3(1), dim3(64), 0, c->stream, c->ptr<double>(c->L.scal), 15);
+  launch_k(nn::k_nn_reset, dim3(1), dim3(64), 0, c->stream, c->ptr<double>(c->L.scal), 31);
   HIPCHK(hipGetLastError());
   if (!c->nn_ready) return EPDLB_OK;
   CHK(stage_nn_any(c, 1, 0));
+  // the seed's comparison follows no surrogate step: not an in-use error
+  launch_k(nn::k_nn_reset, dim3(1), dim3(64), 0, c->stream, c->ptr<double>(c->L.scal),
+           1 << (kNnErrUse - kNnResid));
+  HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));
   return EPDLB_OK;
 }

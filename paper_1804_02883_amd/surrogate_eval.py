@@ -25,7 +25,7 @@ def _timed_steps(sim, steps, stream):
 
 
 def compare(params, seed, sigma, weights, steps, fallback_every=50, check_every=10, resid_tol=1e-3,
-            warmup=None):
+            err_tol=9e-4, warmup=None):
     """Returns a dict: plain and surrogate site-updates/s, speedup, errors."""
     from paper_1804_02883_amd import Simulation
     n = params["nx"] * params["ny"]
@@ -44,7 +44,7 @@ def compare(params, seed, sigma, weights, steps, fallback_every=50, check_every=
     sim.close()
     # surrogate
     ps = dict(params, density_mode=1, fallback_every=fallback_every, check_every=check_every,
-              resid_tol=resid_tol)
+              resid_tol=resid_tol, err_tol=err_tol)
     sim = Simulation(ps)
     sim.surrogate_set_weights(weights)
     sim.seed(seed, sigma)
@@ -56,7 +56,8 @@ def compare(params, seed, sigma, weights, steps, fallback_every=50, check_every=
     phi_sur = sim.densities()
     sim.close()
     out["surrogate"] = dict(value=n * steps / (ms_s / 1e3), ms_per_step=ms_s / steps, n_exact=d["n_exact"],
-                            n_triggered=d["n_triggered"], max_density_err=d["nn_err_max"],
+                            n_triggered=d["n_triggered"], density_err_in_use=d["nn_err_in_use"],
+                            max_density_err=d["nn_err_max"],
                             last_density_err=d["nn_err_last"], resid_max=d["resid_nn_max"],
                             resid_exact=d["resid_exact"])
     out["speedup"] = out["surrogate"]["value"] / out["plain"]["value"]
@@ -72,7 +73,7 @@ def compare(params, seed, sigma, weights, steps, fallback_every=50, check_every=
 def error_trace(params, seed, sigma, weights, steps, fallback_every=50):
     """Surrogate error at every exact step of one run (host reads after each interval; not timed)."""
     from paper_1804_02883_amd import Simulation
-    ps = dict(params, density_mode=1, fallback_every=fallback_every, check_every=10, resid_tol=1e-3)
+    ps = dict(params, density_mode=1, fallback_every=fallback_every, check_every=10, resid_tol=1e-3, err_tol=0.0)
     sim = Simulation(ps)
     sim.surrogate_set_weights(weights)
     sim.seed(seed, sigma)

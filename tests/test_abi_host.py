@@ -51,12 +51,13 @@ def test_defaults_and_validation():
     assert p.abi_version == 1 and p.nx == 32 and p.n_contour == 16
     assert abs(p.dx - 1 / 3) < 1e-16 and p.dt == 0.002 and p.D_A == 1 / 16
     assert B.epdlb_validate(p) == 0
-    assert (p.density_mode, p.fallback_every, p.check_every, p.resid_tol) == (0, 50, 10, 1e-3)
+    assert (p.density_mode, p.fallback_every, p.check_every, p.resid_tol, p.err_tol) == (0, 50, 10, 1e-3, 1e-3)
     assert B.epdlb_validate(B.make_params(density_mode=1)) == 0
     for bad in [dict(nx=48), dict(nx=16), dict(ny=8), dict(n_contour=1), dict(f_A=1.0),
                 dict(phi_P=0.0), dict(lb_tau=0.5), dict(precision=2), dict(abi_version=7),
                 dict(g=float("nan")), dict(density_mode=2), dict(density_mode=1, fallback_every=0),
-                dict(density_mode=1, check_every=0), dict(density_mode=1, resid_tol=0.0)]:
+                dict(density_mode=1, check_every=0), dict(density_mode=1, resid_tol=0.0),
+                dict(density_mode=1, err_tol=-1.0)]:
         q = B.make_params(**bad)
         assert B.epdlb_validate(q) == B.EPDLB_EINVAL, bad
         assert B.epdlb_last_error() != ""

@@ -168,7 +168,7 @@ def test_training_reduces_loss():
 
 
 def sim_params(**kw):
-    base = dict(preset("cfg1"), density_mode=1, fallback_every=3, check_every=1, resid_tol=1e9)
+    base = dict(preset("cfg1"), density_mode=1, fallback_every=3, check_every=1, resid_tol=1e9, err_tol=0.0)
     base.update(kw)
     return base
 
@@ -244,3 +244,23 @@ def test_surrogate_fp32_graph_and_stream_paths_agree():
     assert out[0][2]["n_exact"] == 3
     phi = out[0][0]
     assert abs(phi[0].mean() - p["f_A"] * p["phi_P"]) < 1e-6
+
+
+def test_error_gate_keeps_exact_steps_until_validated():
+    """err_tol: an untrained network (error far above the bar) is never trusted,
+    so every step is exact; with err_tol = 0 the schedule alone decides."""
+    from paper_1804_02883_amd import Simulation
+    w = flatten(init_params(8, out_scale=50.0))
+    counts = []
+    for tol in (1e-3, 0.0):
+        sim = Simulation(sim_params(fallback_every=10, check_every=2, err_tol=tol))
+        sim.surrogate_set_weights(w)
+        sim.seed(1001, 0.05)
+        sim.step(20)
+        sim.sync()
+        d = sim.diag()
+        counts.append(d["n_exact"])
+        if tol:
+            assert d["nn_err_last"] > tol and d["nn_err_in_use"] == 0.0
+        sim.close()
+    assert counts == [20, 2]
