@@ -29,12 +29,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "lattice site-updates/s per hybrid step, plain vs surrogate at <=1e-3 density err"
 
-# HBM traffic of the dominant kernel measured with rocprofv3 --pmc FETCH_SIZE and
-# WRITE_SIZE (one counter per run), scaled by the same counters' readings for a
-# plain 256 MiB copy (FETCH x2.0, WRITE x1.0); see profiles/prop_col_cfg3_traffic.md.
-# Valid only while the kernel sources hash to `source_sha256`.
+# HBM traffic per launch measured with rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
+# (one counter per run, averaged over the kernel's dispatches), scaled by the
+# same counters' readings for a plain 256 MiB copy (FETCH x2.0, WRITE x1.0);
+# the summary with its commands is profiles/prop_cfg3_traffic.md.  Valid only
+# while the kernel sources hash to `source_sha256`.
+_SRC = "2ca78da5792119dee5830cb3c7b6f33ec4f996cdf21c0613e2adf286bb82cfa5"
 MEASURED_TRAFFIC = {
-    ("cfg3", "prop_col"): dict(bytes_per_launch=17291173, source_sha256="473bfc94ccdeb072a69fd59b0ea1ec85b6a01dfb68370ac9eb365a3cbbd0c151"),
+    ("cfg3", "prop_col"): dict(bytes_per_launch=17280303, source_sha256=_SRC),
+    ("cfg3", "prop_row"): dict(bytes_per_launch=16033336, source_sha256=_SRC),
 }
 HBM_PEAK_GBS = 8000.0
 BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense
@@ -72,11 +75,12 @@ def step_bytes_per_site(kind, N, P):
 def kernel_source_sha256():
     import hashlib
     csrc = os.path.join(ROOT, "paper_1804_02883_amd", "csrc")
-    data = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("fft.hpp", "kernels.hpp"))
+    data = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("fft.hpp", "kernels.hpp", "nn.hpp"))
     return hashlib.sha256(data).hexdigest()
 
 
-def cpu_baseline(preset_name, steps):
+def cpu_baseline(preset_name, seconds):
+    """The oracle's plain hybrid step on the host: whole steps until `seconds` have passed."""
     import numpy as np  # noqa: F401
     from oracle import epdlb_oracle as O
     from seeded_inputs import PRESETS, initial_omega
@@ -85,8 +89,10 @@ def cpu_baseline(preset_name, steps):
     w0 = initial_omega(p["nx"], p["ny"], cfg["seed"], cfg["sigma"])
     s = O.init_state(p, w0)
     t0 = time.perf_counter()
-    for _ in range(steps):
+    steps = 0
+    while steps == 0 or time.perf_counter() - t0 < seconds:
         s = O.step(s, p)
+        steps += 1
     dt = time.perf_counter() - t0
     n = p["nx"] * p["ny"]
     return dict(value=n * steps / dt, unit="site-updates/s", cores=1, kind="oracle",
@@ -154,7 +160,7 @@ def run_surrogate(args):
                                 uniform_density_err_at_end=r["fluct_max"]),
                n_exact=sur["n_exact"], n_triggered=sur["n_triggered"], sigma_delta=r["sigma_delta"])
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline("cfg5q", 1)
+        out["cpu_baseline"] = cpu_baseline("cfg5q", args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
@@ -165,7 +171,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="cfg3")
     ap.add_argument("--profile-launches", type=int, default=8192)
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="host time budget of the oracle baseline (whole steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1804_02883_amd", "tune", "gfx950.txt"),
@@ -267,7 +274,7 @@ def main():
     if args.surrogate_steps and args.workload != "cfg4":
         out["surrogate"] = surrogate_summary(args.surrogate_steps)
     if not args.no_cpu_baseline and args.workload != "cfg4":
-        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
