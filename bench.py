@@ -44,7 +44,7 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense
 WEIGHTS = os.path.join(ROOT, "paper_1804_02883_amd", "weights", "surrogate_q.npy")
 # useful flops per site of each network launch (multiply-add = 2 flops):
 # 9 taps x cin x cout x 2; conv0 has 5 real input channels, the output layer 2
-NN_FLOPS_PER_SITE = {"nn_conv0": 9 * 5 * 64 * 2, "nn_conv": 9 * 64 * 64 * 2, "nn_out": 9 * 64 * 2 * 2}
+NN_FLOPS_PER_SITE = {"nn_conv0": 9 * 5 * 64 * 2, "nn_conv": 9 * 64 * 64 * 2}
 
 # Algorithmic bytes per site per hybrid STEP of each kernel family, in units
 # of the element size P (forward and backward chains counted together):

@@ -60,7 +60,7 @@ struct Layout {
   size_t omega[2], phi, stilde, S, q[2], tmp, spec, F, fstar[2], rho, u, boltz;
   size_t mult_x, mult_y, tw_x, tw_y, wnA, wnB, scal, partials, counters;
   // surrogate mode only (density_mode 1)
-  size_t nn_x, nn_act[2], nn_w, nn_frag, nn_phin, nn_corr;
+  size_t nn_act[2], nn_w, nn_frag, nn_phin, nn_corr, nn_proj;
   size_t total;
   size_t n_partials;
 };
@@ -105,11 +105,11 @@ Layout make_layout(const epdlb_params& p) {
   L.partials = take(L.n_partials * sizeof(double));
   L.counters = take(16 * sizeof(unsigned));
   if (p.density_mode == 1) {
-    L.nn_x = take(n * nn::kXC * 2);
     L.nn_act[0] = take(n * nn::kHid * 2);
     L.nn_act[1] = take(n * nn::kHid * 2);
     L.nn_w = take(size_t(nn::kNnParams) * sizeof(float));
-    L.nn_frag = take(size_t(nn::kFwdFragElems) * 2);
+    L.nn_frag = take(size_t(nn::kFwdFragElems + nn::kProjFragElems) * 2);
+    L.nn_proj = take(size_t(nn::kProjRows) * n * sizeof(float));
     L.nn_phin = take(2 * plane);
     L.nn_corr = take(plane);
   }
@@ -175,12 +175,11 @@ namespace {
 int nn_after_seed(epdlb_ctx* c);
 
 enum Kind { K_STATS, K_ADVECT, K_FINISH, K_BOLTZ, K_PROP_ROW, K_PROP_COL, K_DENSITY, K_FROW_FWD, K_FCOL,
-            K_FROW_INV, K_LB, K_NN_INPUT, K_NN_CONV0, K_NN_CONV, K_NN_OUT, K_NN_NORM, K_NN_RESET, K_NUM };
+            K_FROW_INV, K_LB, K_NN_CONV0, K_NN_CONV, K_NN_OUT, K_NN_NORM, K_NN_RESET, K_NUM };
 const char* const kKindName[K_NUM] = {"field_stats", "advect_update", "finish_stats",  "boltzmann",
                                       "prop_row",    "prop_col",      "density",       "force_row_fwd",
-                                      "force_col",   "force_row_inv", "lb",            "nn_input",
-                                      "nn_conv0",    "nn_conv",       "nn_out",        "nn_norm",
-                                      "nn_reset"};
+                                      "force_col",   "force_row_inv", "lb",            "nn_conv0",
+                                      "nn_conv",     "nn_out",        "nn_norm",       "nn_reset"};
 
 // Profiling: while the profiler has room, the next kernel launch records a
 // start/stop event pair at the kernel's own start and end (AMD's extended
@@ -1916,6 +1915,9 @@ int epdlb_surrogate_set_weights(epdlb_ctx* c, const float* w, int64_t count) {
   float* dw = c->ptr<float>(c->L.nn_w);
   HIPCHK(hipMemcpyAsync(dw, w, sizeof(float) * count, hipMemcpyHostToDevice, c->stream));
   HIPCHK(nn_pack(dw, c->ptr<__bf16>(c->L.nn_frag), nullptr, c->stream));
+  hipLaunchKernelGGL(nn::k_pack_proj, dim3(unsigned((nn::kProjFragElems + 255) / 256)), dim3(256), 0, c->stream,
+                     (const float*)(dw + nn_offsets().W[3]), c->ptr<__bf16>(c->L.nn_frag) + nn::kFwdFragElems);
+  HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));
   c->nn_ready = true;
   if (c->seeded) CHK(nn_after_seed(c));

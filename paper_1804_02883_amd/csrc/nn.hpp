@@ -50,6 +50,10 @@ constexpr int kConvTH = (kConvThreads / 64) * kSB;  // tile height: 8 rows
 constexpr int kNnParams = 9 * 5 * 64 + 64 + 2 * (9 * 64 * 64 + 64) + 9 * 64 * 2 + 2;  // 77954
 // Packed forward fragments of the four layers (bf16 elements).
 constexpr long kFwdFragElems = 9L * 1 * 2 * 512 + 2 * (9L * 4 * 2 * 512) + 9L * 4 * 1 * 512;
+// Inference projection of the last hidden layer onto the output taps:
+// p[2t + c](r) = sum_ci a3[r][ci] W4[t][ci][c], 18 rows of one 32-row block.
+constexpr int kProjRows = 18;
+constexpr long kProjFragElems = 4L * 64 * 8;
 
 // logical channel counts and dilations per layer
 __host__ __device__ constexpr int cin_of(int l) { return l == 0 ? 5 : kHid; }
@@ -62,8 +66,10 @@ __host__ __device__ inline int c_of_s64(int s) {
   return 32 * b + 8 * (i >> 2) + 4 * h + (i & 3);
 }
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
-__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + __expf(-z)); }
+// v_rcp_f32 (about 1 ulp) instead of an IEEE division: far below the BF16
+// rounding of the stored activations
+__device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu(float z) { return z * sigm(z); }
 __device__ __forceinline__ float silu_grad(float z) {
   const float s = sigm(z);
   return s * (1.0f + z * (1.0f - s));
@@ -211,7 +217,7 @@ __device__ __forceinline__ TileInfo tile_of(int tile, int nx, int tiles_per_samp
 //   EPI_BWD:       out = conv * SiLU'(zin)   (backward-data: conv of the
 //                  gradient with flipped taps and transposed weights)
 // ---------------------------------------------------------------------------
-enum { EPI_FWD = 0, EPI_FWD_TRAIN = 1, EPI_BWD = 2 };
+enum { EPI_FWD = 0, EPI_FWD_TRAIN = 1, EPI_BWD = 2, EPI_FWD_PROJ = 3 };
 
 struct ConvArgs {
   const __bf16* in;     // [sample][site][CI]
@@ -223,6 +229,9 @@ struct ConvArgs {
   __bf16* zout;         // EPI_FWD_TRAIN
   const __bf16* zin;    // EPI_BWD: pre-activation of the layer below
   long bs;              // elements per sample of out / zout / zin
+  const __bf16* pfrag;  // EPI_FWD_PROJ: projection fragments [4 k-steps][64 lanes][8]
+  float* proj;          // EPI_FWD_PROJ: 18 FP32 planes of `plane` sites
+  long plane;
   int nx, ny, d;
   int tiles_per_sample, ntiles;
 };
@@ -231,8 +240,36 @@ struct ConvArgs {
 // wave's kSB x 32 sites x 64 channels.
 template <int EPI>
 __device__ __forceinline__ void epilogue_hidden(const ConvArgs& P, f32x16 (&acc)[kSB][2], int z, int x, int y0,
-                                                const float* bias_s) {
-  const int h = (threadIdx.x & 63) >> 5;
+                                                const float* bias_s, const bf16x8* pw = nullptr) {
+  const int lane = threadIdx.x & 63;
+  const int h = lane >> 5;
+  if constexpr (EPI == EPI_FWD_PROJ) {
+    // the activations this lane holds (positions 32h..32h+31 of its site)
+    // are exactly its B operand for k-steps 0..3 of the next contraction
+#pragma unroll
+    for (int sb = 0; sb < kSB; ++sb) {
+      f32x16 pr;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) pr[i] = 0.0f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        bf16x8 b;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int s = 8 * q + j, nb = s >> 4, i = s & 15;
+          b[j] = __bf16(silu(acc[sb][nb][i] + bias_s[32 * nb + 8 * (i >> 2) + 4 * h + (i & 3)]));
+        }
+        pr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pw[q * 64 + lane], b, pr, 0, 0, 0);
+      }
+      const long site = long(y0 + sb) * P.nx + x;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int m = 8 * (i >> 2) + 4 * h + (i & 3);
+        if (m < kProjRows) P.proj[long(m) * P.plane + site] = pr[i];
+      }
+    }
+    return;
+  }
   {
 #pragma unroll
     for (int sb = 0; sb < kSB; ++sb) {
@@ -284,7 +321,9 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_hidden(ConvArgs P) {
   constexpr int KS = CI / 16, NB = 2;
   bf16x8* w = reinterpret_cast<bf16x8*>(nn_lds);
   __shared__ float bias_s[kHid];
+  __shared__ bf16x8 pw_s[EPI == EPI_FWD_PROJ ? 4 * 64 : 1];
   stage_weights(P.wfrag, w, 9 * KS * NB * 64 * 16);
+  if constexpr (EPI == EPI_FWD_PROJ) stage_weights(P.pfrag, pw_s, 4 * 64 * 16);
   if (EPI != EPI_BWD && threadIdx.x < kHid) bias_s[threadIdx.x] = P.bias[threadIdx.x];
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, h = lane >> 5;
@@ -296,8 +335,140 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_hidden(ConvArgs P) {
     const int y0 = ti.y0 + wid * kSB;
     f32x16 acc[kSB][NB];
     conv_mma<CI, NB>(in, w, P.nx, P.ny, P.d, x, y0, acc);
-    epilogue_hidden<EPI>(P, acc, ti.z, x, y0, bias_s);
+    epilogue_hidden<EPI>(P, acc, ti.z, x, y0, bias_s, pw_s);
   }
+}
+
+// ---------------------------------------------------------------------------
+// First layer for inference, reading the potentials directly: the B operand
+// of lane group 0 is (w_A - <w_A>, w_B - <w_B>, w_S - <w_S>, f_A, 1/N, 0, 0, 0)
+// in BF16 (the same values k_nn_input stores), group 1 carries the zero
+// channels 8..15.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct InArgs {
+  ConvArgs c;        // out, bs, nx, ny, d = 1, tiles, wfrag (16-channel layer), bias
+  const T* w;        // 3 planes
+  const double* mean;
+  long plane;
+  float fA, invN;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kConvThreads) k_conv_in(InArgs<T> P) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char nn_lds[];
+  constexpr int NB = 2;
+  bf16x8* w = reinterpret_cast<bf16x8*>(nn_lds);
+  __shared__ float bias_s[kHid];
+  stage_weights(P.c.wfrag, w, 9 * NB * 64 * 16);
+  if (threadIdx.x < kHid) bias_s[threadIdx.x] = P.c.bias[threadIdx.x];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, g = lane >> 5;
+  const int nx = P.c.nx, ny = P.c.ny;
+  const double dA = P.mean[0], dB = P.mean[1], dS = P.mean[2];
+  const int blk = xcd_tile(blockIdx.x, gridDim.x);
+  for (int tile = blk; tile < P.c.ntiles; tile += gridDim.x) {
+    const TileInfo ti = tile_of(tile, nx, P.c.tiles_per_sample);
+    const int x = ti.x0 + (lane & 31);
+    const int y0 = ti.y0 + wid * kSB;
+    // potentials of the next tap are loaded while the current tap's MFMAs run
+    auto load = [&](int t, T (&v)[kSB][3]) {
+      if (g != 0) return;
+      const int xs = (x + (t % 3 - 1)) & (nx - 1);
+#pragma unroll
+      for (int sb = 0; sb < kSB; ++sb) {
+        const long i = long((y0 + sb + (t / 3 - 1)) & (ny - 1)) * nx + xs;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[sb][c] = P.w[c * P.plane + i];
+      }
+    };
+    T cur[kSB][3] = {}, nxt[kSB][3] = {};
+    load(0, cur);
+    f32x16 acc[kSB][NB];
+#pragma unroll
+    for (int sb = 0; sb < kSB; ++sb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[sb][nb][i] = 0.0f;
+#pragma unroll 1
+    for (int t = 0; t < 9; ++t) {
+      if (t < 8) load(t + 1, nxt);
+      bf16x8 b[kSB];
+#pragma unroll
+      for (int sb = 0; sb < kSB; ++sb) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) b[sb][j] = __bf16(0.0f);
+        if (g == 0) {
+          b[sb][0] = __bf16(float(double(cur[sb][0]) - dA));
+          b[sb][1] = __bf16(float(double(cur[sb][1]) - dB));
+          b[sb][2] = __bf16(float(double(cur[sb][2]) - dS));
+          b[sb][3] = __bf16(P.fA);
+          b[sb][4] = __bf16(P.invN);
+        }
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const bf16x8 a = w[(t * NB + nb) * 64 + lane];
+#pragma unroll
+        for (int sb = 0; sb < kSB; ++sb)
+          acc[sb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[sb], acc[sb][nb], 0, 0, 0);
+      }
+#pragma unroll
+      for (int sb = 0; sb < kSB; ++sb)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) cur[sb][c] = nxt[sb][c];
+    }
+    epilogue_hidden<EPI_FWD>(P.c, acc, ti.z, x, y0, bias_s);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Output of the inference path: o_c(r) = b_c + sum_t p[2t + c](r + 8 (ty, tx)),
+// Phi_hat = softplus(o) into two planes of T, per-workgroup sums in
+// partials[2*block + c].
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_nn_out_stencil(const float* __restrict__ proj, const float* __restrict__ bias,
+                                                        T* __restrict__ phi, double* __restrict__ partials, int nx,
+                                                        int ny, int d) {
+  __shared__ double red[16 * 2];
+  const long n = long(nx) * ny;
+  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  double r[2] = {0.0, 0.0};
+  if (i < n) {
+    const int x = int(i % nx), y = int(i / nx);
+    float o0 = bias[0], o1 = bias[1];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const long j = long((y + d * (t / 3 - 1)) & (ny - 1)) * nx + ((x + d * (t % 3 - 1)) & (nx - 1));
+      o0 += proj[long(2 * t) * n + j];
+      o1 += proj[long(2 * t + 1) * n + j];
+    }
+    const float p0 = softplus(o0), p1 = softplus(o1);
+    phi[i] = T(p0);
+    phi[n + i] = T(p1);
+    r[0] = p0;
+    r[1] = p1;
+  }
+  nn_block_reduce<2, 2>(r, red);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = r[0];
+    partials[2 * blockIdx.x + 1] = r[1];
+  }
+}
+
+// Projection fragments: lane l, k-step q, element j: row m = l % 32 (tap m / 2,
+// output m % 2), stored input position 32 (l / 32) + 8 q + j.
+__global__ void __launch_bounds__(256) k_pack_proj(const float* __restrict__ W4, __bf16* __restrict__ frag) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= int(kProjFragElems)) return;
+  const int j = e & 7, lane = (e >> 3) & 63, q = e >> 9;
+  const int m = lane & 31, s = 32 * (lane >> 5) + 8 * q + j;
+  const int ci = c_of_s64(s);
+  float v = 0.0f;
+  if (m < kProjRows) v = W4[(long(m >> 1) * kHid + ci) * 2 + (m & 1)];
+  frag[e] = __bf16(v);
 }
 
 // ---------------------------------------------------------------------------

@@ -139,67 +139,72 @@ int stage_nn(epdlb_ctx* c, int mode, int use_corr) {
   T* w = c->ptr<T>(c->L.omega[c->cur]);
   T* phi = c->ptr<T>(c->L.phi);
   double* scal = c->ptr<double>(c->L.scal);
-  __bf16* x = c->ptr<__bf16>(c->L.nn_x);
   __bf16* act0 = c->ptr<__bf16>(c->L.nn_act[0]);
   __bf16* act1 = c->ptr<__bf16>(c->L.nn_act[1]);
   const float* wts = c->ptr<float>(c->L.nn_w);
   const __bf16* ff = c->ptr<__bf16>(c->L.nn_frag);
-  {
-    ProfScope ps(c, K_NN_INPUT);
-    launch_k(nn::k_nn_input<T>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, c->stream, (const T*)w,
-             (const double*)(scal + kMeanA), n, p.nx, float(p.f_A), float(1.0 / p.n_contour), x, (const T*)nullptr,
-             (float*)nullptr);
-  }
-  HIPCHK(hipGetLastError());
   const int tps = (p.nx / nn::kTW) * (p.ny / nn::kConvTH);
   nn::ConvArgs a{};
   a.nx = p.nx;
   a.ny = p.ny;
   a.tiles_per_sample = a.ntiles = tps;
   a.bs = n * nn::kHid;
-  a.in = x;
-  a.in_bs = n * nn::kXC;
-  a.wfrag = ff + fo.f[0];
-  a.bias = wts + o.b[0];
-  a.out = act0;
-  a.d = 1;
   {
+    // first layer straight from the potentials
+    nn::InArgs<T> ia{};
+    ia.c = a;
+    ia.c.wfrag = ff + fo.f[0];
+    ia.c.bias = wts + o.b[0];
+    ia.c.out = act0;
+    ia.c.d = 1;
+    ia.w = w;
+    ia.mean = scal + kMeanA;
+    ia.plane = n;
+    ia.fA = float(p.f_A);
+    ia.invN = float(1.0 / p.n_contour);
     ProfScope ps(c, K_NN_CONV0);
-    HIPCHK((conv_hidden<nn::kXC, nn::EPI_FWD>(a, c->stream)));
+    launch_k(nn::k_conv_in<T>, dim3(std::min(tps, kConvMaxBlocks)), dim3(nn::kConvThreads),
+             size_t(9) * 2 * 64 * 16, c->stream, ia);
   }
-  __bf16* bufs[2] = {act0, act1};
-  for (int l = 1; l < 3; ++l) {
-    a.in = bufs[(l - 1) & 1];
-    a.in_bs = n * nn::kHid;
-    a.wfrag = ff + fo.f[l];
-    a.bias = wts + o.b[l];
-    a.out = bufs[l & 1];
-    a.d = nn::dil_of(l);
+  HIPCHK(hipGetLastError());
+  // second hidden layer, then the third with the output taps' projection
+  // fused into its epilogue (its activations are never stored)
+  a.in = act0;
+  a.in_bs = n * nn::kHid;
+  a.wfrag = ff + fo.f[1];
+  a.bias = wts + o.b[1];
+  a.out = act1;
+  a.d = nn::dil_of(1);
+  {
     ProfScope ps(c, K_NN_CONV);
     HIPCHK((conv_hidden<nn::kHid, nn::EPI_FWD>(a, c->stream)));
   }
+  float* proj = c->ptr<float>(c->L.nn_proj);
+  a.in = act1;
+  a.wfrag = ff + fo.f[2];
+  a.bias = wts + o.b[2];
+  a.out = nullptr;
+  a.d = nn::dil_of(2);
+  a.pfrag = ff + nn::kFwdFragElems;
+  a.proj = proj;
+  a.plane = n;
+  {
+    ProfScope ps(c, K_NN_CONV);
+    HIPCHK((conv_hidden<nn::kHid, nn::EPI_FWD_PROJ>(a, c->stream)));
+  }
   T* dst = mode == 0 ? phi : c->ptr<T>(c->L.nn_phin);
-  nn::OutArgs<T> q{};
-  q.in = bufs[0];
-  q.in_bs = n * nn::kHid;
-  q.wfrag = ff + fo.f[3];
-  q.bias = wts + o.b[3];
-  q.phi = dst;
-  q.plane = n;
-  q.partials = c->ptr<double>(c->L.partials);
-  q.nx = p.nx;
-  q.ny = p.ny;
-  q.d = nn::dil_of(3);
-  q.tiles_per_sample = q.ntiles = tps;
-  int nslots = 0;
+  const int nslots = int((n + 255) / 256);
+  double* partials = c->ptr<double>(c->L.partials);
   {
     ProfScope ps(c, K_NN_OUT);
-    HIPCHK((conv_out<T, nn::EPO_INFER>(q, c->stream, &nslots)));
+    launch_k(nn::k_nn_out_stencil<T>, dim3(unsigned(nslots)), dim3(256), 0, c->stream, (const float*)proj,
+             wts + o.b[3], dst, partials, p.nx, p.ny, nn::dil_of(3));
   }
+  HIPCHK(hipGetLastError());
   nn::NormArgs<T> r{};
   r.src = dst;
   r.phi = phi;
-  r.part = q.partials;
+  r.part = partials;
   r.nslots = nslots;
   r.wS = w + 2 * n;
   r.stilde = c->ptr<T>(c->L.stilde);

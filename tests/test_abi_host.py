@@ -72,10 +72,10 @@ def test_workspace_bytes_scale():
     planes = 2 * N + 40  # omega 6, phi 3, S~ 1, S 1, q 2N, tmp 2, spec 2, F 2, f* 18, rho 1, u 2, E 2
     assert planes * n * 4 <= b32 < planes * n * 4 + (1 << 22)
     assert abs(b64 - 2 * b32) < (1 << 22)
-    # surrogate mode adds x (16 bf16), two 64-channel bf16 activations, the
-    # network's densities (2 planes) and the S correction (1 plane), weights
+    # surrogate mode adds two 64-channel bf16 activations, the network's
+    # densities (2 planes) and the S correction (1 plane), weights
     bs = B.epdlb_workspace_bytes(B.make_params(preset("cfg3"), density_mode=1))
-    extra = n * (16 * 2 + 2 * 64 * 2 + 3 * 4)
+    extra = n * (2 * 64 * 2 + 3 * 4)
     assert extra <= bs - b32 < extra + (1 << 20)
 
 
