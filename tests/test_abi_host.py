@@ -73,9 +73,10 @@ def test_workspace_bytes_scale():
     assert planes * n * 4 <= b32 < planes * n * 4 + (1 << 22)
     assert abs(b64 - 2 * b32) < (1 << 22)
     # surrogate mode adds two 64-channel bf16 activations, the network's
-    # densities (2 planes) and the S correction (1 plane), weights
+    # densities (2 planes), the S correction (1 plane), 18 FP32 output-tap
+    # planes, weights
     bs = B.epdlb_workspace_bytes(B.make_params(preset("cfg3"), density_mode=1))
-    extra = n * (2 * 64 * 2 + 3 * 4)
+    extra = n * (2 * 64 * 2 + 3 * 4 + 18 * 4)
     assert extra <= bs - b32 < extra + (1 << 20)
 
 
