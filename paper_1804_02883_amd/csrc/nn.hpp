@@ -42,8 +42,8 @@ constexpr int kLayers = 4;
 constexpr int kHid = 64;  // hidden channels
 constexpr int kXC = 16;   // stored channels of x and of dL/do
 constexpr int kTW = 32;   // tile width (x sites) of the conv kernels
-constexpr int kSB = 2;    // site rows per wave in the conv kernels
-constexpr int kConvThreads = 256;
+constexpr int kSB = 1;    // site rows per wave in the conv kernels
+constexpr int kConvThreads = 512;
 constexpr int kConvTH = (kConvThreads / 64) * kSB;  // tile height: 8 rows
 
 // Logical FP32 parameters: for l = 0..3, W_l [9][cin][cout] then b_l [cout].
@@ -125,14 +125,14 @@ __device__ __forceinline__ void nn_block_reduce(double (&v)[NV], double* red /*[
 // wave's first row.  nx, ny are powers of two (periodic wrap by masking).
 // ---------------------------------------------------------------------------
 // The activations of tap t+1 are loaded while tap t's MFMAs run.
-template <int CI>
+template <int CI, int SB>
 __device__ __forceinline__ void load_tap(const __bf16* __restrict__ in, int nx, int ny, int d, int x, int y0,
-                                         int t, int g, u32x4 (&v)[kSB][CI / 16]) {
+                                         int t, int g, u32x4 (&v)[SB][CI / 16]) {
   constexpr int KS = CI / 16;
   const int ty = t / 3 - 1, tx = t % 3 - 1;
   const int xs = (x + d * tx) & (nx - 1);
 #pragma unroll
-  for (int sb = 0; sb < kSB; ++sb) {
+  for (int sb = 0; sb < SB; ++sb) {
     const int ys = (y0 + sb + d * ty) & (ny - 1);
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
@@ -140,50 +140,50 @@ __device__ __forceinline__ void load_tap(const __bf16* __restrict__ in, int nx, 
   }
 }
 
-template <int CI, int NB>
+template <int CI, int NB, int SB = kSB>
 __device__ __forceinline__ void conv_mma(const __bf16* __restrict__ in, const bf16x8* w, int nx, int ny, int d,
-                                         int x, int y0, f32x16 (&acc)[kSB][NB]) {
+                                         int x, int y0, f32x16 (&acc)[SB][NB]) {
   constexpr int KS = CI / 16;
   const int lane = threadIdx.x & 63;
   const int g = lane >> 5;
 #pragma unroll
-  for (int sb = 0; sb < kSB; ++sb)
+  for (int sb = 0; sb < SB; ++sb)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[sb][nb][i] = 0.0f;
   if constexpr (KS == 1) {
     // few MFMAs per tap: issue every tap's loads first
-    u32x4 all[9][kSB][1];
+    u32x4 all[9][SB][1];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) load_tap<CI>(in, nx, ny, d, x, y0, t, g, all[t]);
+    for (int t = 0; t < 9; ++t) load_tap<CI, SB>(in, nx, ny, d, x, y0, t, g, all[t]);
 #pragma unroll
     for (int t = 0; t < 9; ++t)
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const bf16x8 a = w[(t * NB + nb) * 64 + lane];
 #pragma unroll
-        for (int sb = 0; sb < kSB; ++sb)
+        for (int sb = 0; sb < SB; ++sb)
           acc[sb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, as_bf16x8(all[t][sb][0]), acc[sb][nb], 0, 0, 0);
       }
     return;
   }
-  u32x4 cur[kSB][KS], nxt[kSB][KS];
-  load_tap<CI>(in, nx, ny, d, x, y0, 0, g, cur);
+  u32x4 cur[SB][KS], nxt[SB][KS];
+  load_tap<CI, SB>(in, nx, ny, d, x, y0, 0, g, cur);
 #pragma unroll 1
   for (int t = 0; t < 9; ++t) {
-    if (t < 8) load_tap<CI>(in, nx, ny, d, x, y0, t + 1, g, nxt);
+    if (t < 8) load_tap<CI, SB>(in, nx, ny, d, x, y0, t + 1, g, nxt);
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const bf16x8 a = w[((t * KS + ks) * NB + nb) * 64 + lane];
 #pragma unroll
-        for (int sb = 0; sb < kSB; ++sb)
+        for (int sb = 0; sb < SB; ++sb)
           acc[sb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, as_bf16x8(cur[sb][ks]), acc[sb][nb], 0, 0, 0);
       }
 #pragma unroll
-    for (int sb = 0; sb < kSB; ++sb)
+    for (int sb = 0; sb < SB; ++sb)
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) cur[sb][ks] = nxt[sb][ks];
   }
@@ -238,8 +238,8 @@ struct ConvArgs {
 
 // Bias + SiLU (forward) or SiLU'(z) (backward-data) and the stores of one
 // wave's kSB x 32 sites x 64 channels.
-template <int EPI>
-__device__ __forceinline__ void epilogue_hidden(const ConvArgs& P, f32x16 (&acc)[kSB][2], int z, int x, int y0,
+template <int EPI, int SB = kSB>
+__device__ __forceinline__ void epilogue_hidden(const ConvArgs& P, f32x16 (&acc)[SB][2], int z, int x, int y0,
                                                 const float* bias_s, const bf16x8* pw = nullptr) {
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
@@ -247,7 +247,7 @@ __device__ __forceinline__ void epilogue_hidden(const ConvArgs& P, f32x16 (&acc)
     // the activations this lane holds (positions 32h..32h+31 of its site)
     // are exactly its B operand for k-steps 0..3 of the next contraction
 #pragma unroll
-    for (int sb = 0; sb < kSB; ++sb) {
+    for (int sb = 0; sb < SB; ++sb) {
       f32x16 pr;
 #pragma unroll
       for (int i = 0; i < 16; ++i) pr[i] = 0.0f;
@@ -272,7 +272,7 @@ __device__ __forceinline__ void epilogue_hidden(const ConvArgs& P, f32x16 (&acc)
   }
   {
 #pragma unroll
-    for (int sb = 0; sb < kSB; ++sb) {
+    for (int sb = 0; sb < SB; ++sb) {
       // this lane's 32 positions are chunks 4h .. 4h+3 of its site
       const long base = long(z) * P.bs + blk_off<kHid>(x, y0 + sb, P.nx, 4 * h);
       float v[32];
@@ -315,8 +315,8 @@ __device__ __forceinline__ void epilogue_hidden(const ConvArgs& P, f32x16 (&acc)
   }
 }
 
-template <int CI, int EPI>
-__global__ void __launch_bounds__(kConvThreads) k_conv_hidden(ConvArgs P) {
+template <int CI, int EPI, int SB = kSB, int NW = kConvThreads / 64>
+__global__ void __launch_bounds__(NW * 64) k_conv_hidden(ConvArgs P) {
   extern __shared__ __attribute__((aligned(16))) unsigned char nn_lds[];
   constexpr int KS = CI / 16, NB = 2;
   bf16x8* w = reinterpret_cast<bf16x8*>(nn_lds);
@@ -329,13 +329,13 @@ __global__ void __launch_bounds__(kConvThreads) k_conv_hidden(ConvArgs P) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, h = lane >> 5;
   const int blk = xcd_tile(blockIdx.x, gridDim.x);
   for (int tile = blk; tile < P.ntiles; tile += gridDim.x) {
-    const TileInfo ti = tile_of(tile, P.nx, P.tiles_per_sample);
+    const TileInfo ti = tile_of(tile, P.nx, P.tiles_per_sample, NW * SB);
     const __bf16* in = P.in + long(P.slots ? P.slots[ti.z] : ti.z) * P.in_bs;
     const int x = ti.x0 + (lane & 31);
-    const int y0 = ti.y0 + wid * kSB;
-    f32x16 acc[kSB][NB];
-    conv_mma<CI, NB>(in, w, P.nx, P.ny, P.d, x, y0, acc);
-    epilogue_hidden<EPI>(P, acc, ti.z, x, y0, bias_s, pw_s);
+    const int y0 = ti.y0 + wid * SB;
+    f32x16 acc[SB][NB];
+    conv_mma<CI, NB, SB>(in, w, P.nx, P.ny, P.d, x, y0, acc);
+    epilogue_hidden<EPI, SB>(P, acc, ti.z, x, y0, bias_s, pw_s);
   }
 }
 
