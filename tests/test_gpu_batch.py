@@ -86,6 +86,9 @@ def test_batch_rejects_mismatched_models():
     c = base_params(32, 32, 32, 0.5, 0.1)
     with pytest.raises(EpdlbError):
         Batch([a, c])
+    # the batch runs the exact densities only
+    with pytest.raises(EpdlbError):
+        Batch([a, dict(a, density_mode=1)])
 
 
 def test_cfg4_manifest_two_steps():
