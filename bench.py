@@ -1,15 +1,20 @@
 """Benchmark: lattice site-updates/s of the hybrid LB/EPD step on one MI355X.
 
-Workload (default): 1024 x 512 periodic grid, FP32 fields with FP64
-partition-function reductions, N = 64 contour steps, f_A = 0.3, phi_P = 0.15,
-chi reading L, g = 1e-5 f*, seeded Gaussian noise sigma = 1e-3 (seed 1003).
-A "step" is one full hybrid step (advection + EPD update, both chain
-propagators, densities, force reconstruction, D2Q9 LB) on the resident state.
-The line also carries the plain-versus-surrogate comparison on the 512 x 512
-quench (`surrogate`), which `--workload cfg5q` reports as the main line:
-there `value` is the surrogate path's rate over a full run, exact steps
-(every 50 steps and when the residual test fires) included, and `roofline`
-is the MFMA roofline of the 64 -> 64 convolution.
+A "step" is one full hybrid step (advection + EPD update, densities, force
+reconstruction, D2Q9 LB) on the resident state.
+
+Default workload (cfg5q), plain versus surrogate: 512 x 512 periodic grid,
+FP32 fields with FP64 partition-function reductions, N = 32, f_A = 0.5,
+phi_P = 0.1, chi reading Q, g = 1e-5 f*, seeded Gaussian noise sigma = 0.05
+(seed 1005), 2e4 steps from the seed for each path.  `value` is the
+surrogate path's rate over its whole run: its exact steps (every 50 steps,
+on the residual test, and while the last measured network error exceeds
+9e-4) included; `density_err.in_use` is the largest network error measured
+at an exact step that ended surrogate steps.  `roofline` is the MFMA
+roofline of the 64 -> 64 convolution.  `plain_full_scale` adds the plain
+path on 1024 x 512, N = 64 with its HBM roofline.
+
+`--workload cfg3` (or cfg2, cfg5, cfg4) reports a plain line instead.
 
 Prints ONE JSON line.  `value` is timed with events around K graph-replayed
 steps.  `roofline` covers the kernel family with the largest share of GPU
@@ -34,10 +39,10 @@ METRIC = "lattice site-updates/s per hybrid step, plain vs surrogate at <=1e-3 d
 # same counters' readings for a plain 256 MiB copy (FETCH x2.0, WRITE x1.0);
 # the summary with its commands is profiles/prop_cfg3_traffic.md.  Valid only
 # while the kernel sources hash to `source_sha256`.
-_SRC = "2ca78da5792119dee5830cb3c7b6f33ec4f996cdf21c0613e2adf286bb82cfa5"
+_SRC = "009de11dd46a121ecd3c509293958627f4fb8d370289dca15e86a774ba0f297f"
 MEASURED_TRAFFIC = {
-    ("cfg3", "prop_col"): dict(bytes_per_launch=17280303, source_sha256=_SRC),
-    ("cfg3", "prop_row"): dict(bytes_per_launch=16033336, source_sha256=_SRC),
+    ("cfg3", "prop_col"): dict(bytes_per_launch=17276403, source_sha256=_SRC),
+    ("cfg3", "prop_row"): dict(bytes_per_launch=16033181, source_sha256=_SRC),
 }
 HBM_PEAK_GBS = 8000.0
 BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense
@@ -96,8 +101,8 @@ def cpu_baseline(preset_name, seconds):
     dt = time.perf_counter() - t0
     n = p["nx"] * p["ny"]
     return dict(value=n * steps / dt, unit="site-updates/s", cores=1, kind="oracle",
-                sample=f"{steps} hybrid steps of {p['nx']}x{p['ny']} N={p['n_contour']} FP64 "
-                       f"(NumPy, single thread), {dt:.1f} s")
+                sample=f"{steps} plain hybrid steps (exact propagator) of {preset_name}, {p['nx']}x{p['ny']} "
+                       f"N={p['n_contour']}, FP64 NumPy oracle, single thread, {dt:.1f} s")
 
 
 def surrogate_summary(steps):
@@ -112,10 +117,9 @@ def surrogate_summary(steps):
     return r
 
 
-def run_surrogate(args):
-    """--workload cfg5q: the surrogate path as the main line."""
+def surrogate_line(args):
+    """The surrogate path on the 512^2 quench (cfg5q) as a bench line."""
     import numpy as np
-    import torch
     from paper_1804_02883_amd import Simulation
     from seeded_inputs import PRESETS
     cfg = PRESETS["cfg5q"]
@@ -123,7 +127,7 @@ def run_surrogate(args):
     n = p["nx"] * p["ny"]
     steps = args.steps if args.steps_given else cfg["steps"]
     r = surrogate_summary(steps - 50)
-    # per-kernel durations of the surrogate path (100 steps: 2 exact)
+    # per-kernel durations of surrogate steps (100 steps, 2 of them exact)
     sim = Simulation(dict(p, density_mode=1, fallback_every=50, check_every=10, resid_tol=1e-3, err_tol=0.0))
     sim.surrogate_set_weights(np.load(WEIGHTS))
     sim.seed(cfg["seed"], cfg["sigma"])
@@ -145,57 +149,29 @@ def run_surrogate(args):
                          tflops=(round(NN_FLOPS_PER_SITE[k] * n / (v["avg_ms"] / 1e3) / 1e12, 1)
                                  if k in NN_FLOPS_PER_SITE else None))
                  for k, v in prof.items()}
+    breakdown["kernel_sum_us_per_step"] = round(1e3 * tot / 100, 2)
     sur = r["surrogate"]
-    out = dict(metric=METRIC, value=sur["value"], unit="site-updates/s", n_gpus=1, steps=r["steps"], warmup=50,
-               ms_per_step=sur["ms_per_step"], higher_is_better=True, scaling="weak", vs_baseline=None,
-               dtype="f32+bf16", data="synthetic",
-               config=dict(workload=r["workload"] + "; exact step every 50 steps, on the residual test, and "
-                           "while the last measured surrogate error exceeds 9e-4",
-                           nx=p["nx"], ny=p["ny"], n_contour=p["n_contour"], path="surrogate"),
-               roofline=roofline, breakdown=breakdown,
-               plain=dict(value=r["plain"]["value"], ms_per_step=r["plain"]["ms_per_step"]),
-               speedup=r["speedup"],
-               density_err=dict(in_use=sur["density_err_in_use"], bar=1e-3,
-                                max_at_exact_steps=sur["max_density_err"], last=sur["last_density_err"],
-                                uniform_density_err_at_end=r["fluct_max"]),
-               n_exact=sur["n_exact"], n_triggered=sur["n_triggered"], sigma_delta=r["sigma_delta"])
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline("cfg5q", args.cpu_seconds)
-    print(json.dumps(out), flush=True)
+    return dict(metric=METRIC, value=sur["value"], unit="site-updates/s", n_gpus=1, steps=r["steps"], warmup=50,
+                ms_per_step=sur["ms_per_step"], higher_is_better=True, scaling="weak", vs_baseline=None,
+                dtype="f32+bf16", data="synthetic",
+                config=dict(workload=r["workload"] + "; exact step every 50 steps, on the residual test, and "
+                            "while the last measured surrogate error exceeds 9e-4",
+                            nx=p["nx"], ny=p["ny"], n_contour=p["n_contour"], path="surrogate"),
+                roofline=roofline, breakdown=breakdown,
+                plain=dict(value=r["plain"]["value"], ms_per_step=r["plain"]["ms_per_step"]),
+                speedup=r["speedup"],
+                density_err=dict(in_use=sur["density_err_in_use"], bar=1e-3,
+                                 max_at_exact_steps=sur["max_density_err"], last=sur["last_density_err"],
+                                 uniform_density_err_at_end=r["fluct_max"]),
+                n_exact=sur["n_exact"], n_triggered=sur["n_triggered"], sigma_delta=r["sigma_delta"])
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="cfg3")
-    ap.add_argument("--profile-launches", type=int, default=8192)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="host time budget of the oracle baseline (whole steps)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1804_02883_amd", "tune", "gfx950.txt"),
-                    help="autotuner results file (read first, new results appended)")
-    ap.add_argument("--surrogate-steps", type=int, default=20000,
-                    help="steps of the plain vs surrogate comparison added to the line (0: skip)")
-    args = ap.parse_args()
-    args.steps_given = args.steps is not None
-    if args.steps is None:
-        args.steps = 2000
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is described in DESIGN.md, not built", file=sys.stderr)
-        sys.exit(2)
-
+def plain_line(args, workload):
+    """The plain (exact propagator) path on one workload as a bench line."""
     import torch
     from paper_1804_02883_amd import Batch, Simulation
     from seeded_inputs import PRESETS, replica_manifest
-
-    torch.cuda.set_device(0)
-    if args.workload == "cfg5q":
-        return run_surrogate(args)
-    if args.workload == "cfg4":
+    if workload == "cfg4":
         man = replica_manifest()
         plist = [m["params"] for m in man]
         p = dict(plist[0])
@@ -210,17 +186,18 @@ def main():
               f"{n} sites, plain (exact propagator)")
         cfgd = dict(workload=wl, replicas=len(plist), sites=n, n_contour=32, path="plain")
     else:
-        cfg = PRESETS[args.workload]
+        cfg = PRESETS[workload]
         p = dict(cfg["params"])
         n = p["nx"] * p["ny"]
         sim = Simulation(p)
         sim.seed(cfg["seed"], cfg["sigma"])
         shapes = sim.shapes() if args.no_tune else sim.autotune(20, args.tune_cache)
-        wl = (f"{args.workload}: {cfg['name']}, chi reading L, g={p['g']}, "
+        wl = (f"{workload}: {cfg['name']}, g={p['g']}, "
               f"seed {cfg['seed']} noise sigma {cfg['sigma']}, plain (exact propagator)")
         cfgd = dict(workload=wl, nx=p["nx"], ny=p["ny"], n_contour=p["n_contour"], path="plain")
     N = p["n_contour"]
     P = 8 if p["precision"] == 0 else 4
+    steps = args.steps if args.steps_given else 2000
     sim.step(args.warmup)
     sim.sync()
 
@@ -229,20 +206,20 @@ def main():
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record(stream)
-    sim.step(args.steps)
+    sim.step(steps)
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
     sim.sync()
     # per-kernel durations: HIP start/stop events recorded by each kernel launch
     # itself (stream launches of the same workload, right after the timed region)
-    per_step = (N + 9) * (1 if args.workload != "cfg4" else sim.info()[0])
+    per_step = (N + 9) * (1 if workload != "cfg4" else sim.info()[0])
     prof_steps = max(1, min(50, args.profile_launches // per_step))
     sim.profile_start(prof_steps * per_step + 16)
     sim.step(prof_steps)
     prof = sim.profile_read()
-    ms_per_step = ms / args.steps
-    value = n * args.steps / (ms / 1e3)
+    ms_per_step = ms / steps
+    value = n * steps / (ms / 1e3)
 
     # dominant kernel family by GPU time; achieved = its algorithmic bytes over
     # the profiled steps / its summed kernel durations
@@ -250,7 +227,7 @@ def main():
     fam = max(fams, key=lambda k: prof[k]["total_ms"])
     alg_bytes = step_bytes_per_site(fam, N, P) * n * prof_steps
     achieved = alg_bytes / (prof[fam]["total_ms"] / 1e3) / 1e9
-    tr = MEASURED_TRAFFIC.get((args.workload, fam))
+    tr = MEASURED_TRAFFIC.get((workload, fam))
     traffic = tr["bytes_per_launch"] if tr and tr["source_sha256"] == kernel_source_sha256() else None
     roofline = dict(bound="hbm", kernel=fam, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
@@ -264,15 +241,52 @@ def main():
                               if step_bytes_per_site(k, N, P) else None))
                  for k, v in prof.items()}
     breakdown["kernel_sum_us_per_step"] = round(1e3 * tot / prof_steps, 2)
-    d = sim.diag() if args.workload != "cfg4" else sim.diag(0)
+    d = sim.diag() if workload != "cfg4" else sim.diag(0)
     sim.close()
+    return dict(metric=METRIC, value=value, unit="site-updates/s", n_gpus=1, steps=steps,
+                warmup=args.warmup, ms_per_step=ms_per_step, higher_is_better=True, scaling="weak",
+                vs_baseline=None, dtype="f32" if P == 4 else "f64", data="synthetic",
+                config=cfgd, roofline=roofline, breakdown=breakdown, shapes=shapes, Q_P=d["Q_P"])
 
-    out = dict(metric=METRIC, value=value, unit="site-updates/s", n_gpus=1, steps=args.steps,
-               warmup=args.warmup, ms_per_step=ms_per_step, higher_is_better=True, scaling="weak",
-               vs_baseline=None, dtype="f32" if P == 4 else "f64", data="synthetic",
-               config=cfgd, roofline=roofline, breakdown=breakdown, shapes=shapes, Q_P=d["Q_P"])
-    if args.surrogate_steps and args.workload != "cfg4":
-        out["surrogate"] = surrogate_summary(args.surrogate_steps)
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 20000 for cfg5q, the run from the seed; 2000 otherwise)")
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="cfg5q", choices=["cfg5q", "cfg3", "cfg2", "cfg4", "cfg5"])
+    ap.add_argument("--profile-launches", type=int, default=8192)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="host time budget of the oracle baseline (whole steps)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1804_02883_amd", "tune", "gfx950.txt"),
+                    help="autotuner results file (read first, new results appended)")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the secondary comparison on the line (the 1024x512 plain run for cfg5q, "
+                         "the cfg5q plain vs surrogate run otherwise)")
+    args = ap.parse_args()
+    args.steps_given = args.steps is not None
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding is described in DESIGN.md, not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    torch.cuda.set_device(0)
+    if args.workload == "cfg5q":
+        out = surrogate_line(args)
+        if not args.no_secondary:
+            a3 = argparse.Namespace(**vars(args))
+            a3.steps_given = False
+            pl = plain_line(a3, "cfg3")
+            out["plain_full_scale"] = dict(workload=pl["config"]["workload"], value=pl["value"],
+                                           ms_per_step=pl["ms_per_step"], roofline=pl["roofline"])
+    else:
+        out = plain_line(args, args.workload)
+        if not args.no_secondary and args.workload != "cfg4":
+            out["surrogate"] = surrogate_summary(20000 - 50)
     if not args.no_cpu_baseline and args.workload != "cfg4":
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
     print(json.dumps(out), flush=True)
