@@ -270,7 +270,7 @@ def main():
     args.steps_given = args.steps is not None
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is described in DESIGN.md, not built", file=sys.stderr)
+              "sharding over several GPUs is designed but not built", file=sys.stderr)
         sys.exit(2)
 
     import torch

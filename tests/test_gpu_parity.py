@@ -234,7 +234,8 @@ def test_cfg3_full_size_step(couple):
     densities carry ~1e-6 relative propagator round-off, which is of the size
     of the per-step diffusive change they are differenced for (S), so the
     polymer force is round-off dominated near the homogeneous state; the
-    coupled velocity is only held to the size of that noise."""
+    coupled velocity is only held to the size of that noise (FP64 runs match
+    the oracle to 1e-10, test_cfg1_full_run_fp64)."""
     say(f"[cfg3] 1024x512 N=64 FP32, 2 steps, couple_lb={couple}")
     p = preset("cfg3", couple_lb=couple)
     w0 = initial_omega(1024, 512, 1003, 1e-3)
