@@ -264,3 +264,27 @@ def test_error_gate_keeps_exact_steps_until_validated():
             assert d["nn_err_last"] > tol and d["nn_err_in_use"] == 0.0
         sim.close()
     assert counts == [20, 2]
+
+
+@pytest.mark.parametrize("nx,ny,prec,tol", [(32, 16, 0, 1e-6), (64, 32, 1, 1e-4)])
+def test_surrogate_steps_match_oracle_shapes(nx, ny, prec, tol):
+    """The smallest grid (32x16, FP64) and an FP32 run (64x32) of the surrogate
+    path against the oracle trajectory; FP32 is held to the FP32 density bar."""
+    from paper_1804_02883_amd import Simulation
+    from seeded_inputs import initial_omega
+    p = sim_params(nx=nx, ny=ny, precision=prec, fallback_every=2)
+    w32 = flatten(init_params(9, phibar=0.05, out_scale=0.2))
+    w0 = initial_omega(nx, ny, 78, 0.05)
+    sim = Simulation(p)
+    sim.surrogate_set_weights(w32)
+    sim.set_fields(w0)
+    sim.step(5)
+    sim.sync()
+    phi = sim.densities()
+    d = sim.diag()
+    sim.close()
+    ref = NN.surrogate_run(p, NN.round_params(unflatten(w32), NN.bf16_round), w0, 5, 2, rnd=NN.bf16_round)
+    err = np.max(np.abs(phi - ref["phi"]))
+    print(f"{nx}x{ny} precision {prec}: max dPhi {err:.3e}, n_exact {d['n_exact']}")
+    assert d["n_exact"] == 3
+    assert err <= tol
