@@ -153,6 +153,27 @@ int epdlb_set_fields(epdlb_ctx* ctx, const double* omega);
 int epdlb_set_state(epdlb_ctx* ctx, const double* omega, const double* phi,
                     const double* fstar, const double* u);
 
+/* Download the state in the layout epdlb_set_state takes (checkpoint): a
+ * context given it continues the run (to rounding: the restore recomputes
+ * the FP64 field means with another summation order).  Synchronises. */
+int epdlb_get_state(epdlb_ctx* ctx, double* omega, double* phi, double* fstar, double* u);
+
+/* Device addresses of the current state planes, row-major [y][x], plane
+ * stride nx*ny elements of FP64 (precision 0) or FP32 (precision 1), inside
+ * the context's workspace.  Valid until the next call that steps or resets
+ * the context (omega and the populations alternate between two buffers).
+ * Reading them races with queued steps unless ordered on the context's
+ * stream; writing them is undefined. */
+typedef struct {
+  int32_t precision;
+  int64_t plane;        /* elements per plane */
+  const void* omega;    /* 3 planes: A, B, S */
+  const void* phi;      /* 3 planes */
+  const void* rho;      /* 1 plane */
+  const void* u;        /* 2 planes, lattice units */
+} epdlb_dev_views;
+int epdlb_device_views(epdlb_ctx* ctx, epdlb_dev_views* out);
+
 /* Queue n hybrid steps on the context stream. */
 int epdlb_step(epdlb_ctx* ctx, int64_t n);
 

@@ -81,6 +81,12 @@ class epdlb_shape(ctypes.Structure):
                 ("us", ctypes.c_double)]
 
 
+class epdlb_dev_views(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("plane", ctypes.c_int64),
+                ("omega", ctypes.c_void_p), ("phi", ctypes.c_void_p),
+                ("rho", ctypes.c_void_p), ("u", ctypes.c_void_p)]
+
+
 class EpdlbError(RuntimeError):
     def __init__(self, code, fn, msg):
         super().__init__(f"{fn} failed ({code}): {msg}")
@@ -106,6 +112,8 @@ SIGNATURES = {
     "epdlb_seed": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_double]),
     "epdlb_set_fields": (ctypes.c_int, [_vp, _dp]),
     "epdlb_set_state": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp]),
+    "epdlb_get_state": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp]),
+    "epdlb_device_views": (ctypes.c_int, [_vp, _P(epdlb_dev_views)]),
     "epdlb_step": (ctypes.c_int, [_vp, ctypes.c_int64]),
     "epdlb_run_stage": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "epdlb_sync": (ctypes.c_int, [_vp]),
@@ -243,6 +251,20 @@ def epdlb_set_fields(ctx, omega, n):
 def epdlb_set_state(ctx, omega, phi, fstar, u, n):
     a, b, c, d = _f64(omega, 3 * n), _f64(phi, 3 * n), _f64(fstar, 9 * n), _f64(u, 2 * n)
     _check(load_library().epdlb_set_state(ctx, _ptr(a), _ptr(b), _ptr(c), _ptr(d)), "epdlb_set_state")
+
+
+def epdlb_get_state(ctx, shape):
+    n = shape[0] * shape[1]
+    om, ph, fs, u = np.empty(3 * n), np.empty(3 * n), np.empty(9 * n), np.empty(2 * n)
+    _check(load_library().epdlb_get_state(ctx, _ptr(om), _ptr(ph), _ptr(fs), _ptr(u)), "epdlb_get_state")
+    return om.reshape((3,) + tuple(shape)), ph.reshape((3,) + tuple(shape)), \
+        fs.reshape((9,) + tuple(shape)), u.reshape((2,) + tuple(shape))
+
+
+def epdlb_device_views(ctx):
+    v = epdlb_dev_views()
+    _check(load_library().epdlb_device_views(ctx, ctypes.byref(v)), "epdlb_device_views")
+    return v
 
 
 def epdlb_step(ctx, n):
@@ -448,6 +470,27 @@ class Simulation:
 
     def surrogate_set_weights(self, w):
         epdlb_surrogate_set_weights(self.ctx, w)
+
+    def get_state(self):
+        """(omega, phi, fstar, u) on the host, the layout set_state takes."""
+        return epdlb_get_state(self.ctx, self.shape)
+
+    def device_views(self):
+        """Zero-copy torch views of the current state (valid until the next step):
+        dict of omega [3, ny, nx], phi [3, ny, nx], rho [ny, nx], u [2, ny, nx]."""
+        import torch
+        if self._ws is None:
+            raise RuntimeError("device views need the torch workspace (use_torch=True)")
+        v = epdlb_device_views(self.ctx)
+        dt = torch.float64 if v.precision == 0 else torch.float32
+        es = 8 if v.precision == 0 else 4
+        base = self._ws.data_ptr()
+        out = {}
+        for name, planes in (("omega", 3), ("phi", 3), ("rho", 1), ("u", 2)):
+            off = getattr(v, name) - base
+            t = self._ws[off:off + planes * v.plane * es].view(dt)
+            out[name] = t.view((planes,) + self.shape) if planes > 1 else t.view(self.shape)
+        return out
 
 
 # ---- density surrogate ---------------------------------------------------------------------

@@ -1331,6 +1331,28 @@ int epdlb_set_state(epdlb_ctx* c, const double* omega, const double* phi, const 
   return EPDLB_OK;
 }
 
+int epdlb_get_state(epdlb_ctx* c, double* omega, double* phi, double* fstar, double* u) {
+  if (!c || !omega || !phi || !fstar || !u) return fail(EPDLB_EINVAL, "NULL argument");
+  if (!c->seeded) return fail(EPDLB_ESTATE, "no state before seed/set_fields/set_state");
+  const size_t n = size_t(c->p.nx) * c->p.ny;
+  CHK(download(c, c->L.omega[c->cur], omega, 3 * n));
+  CHK(download(c, c->L.phi, phi, 3 * n));
+  CHK(epdlb_read_populations(c, fstar));
+  CHK(download(c, c->L.u, u, 2 * n));
+  return EPDLB_OK;
+}
+
+int epdlb_device_views(epdlb_ctx* c, epdlb_dev_views* v) {
+  if (!c || !v) return fail(EPDLB_EINVAL, "NULL argument");
+  v->precision = c->p.precision;
+  v->plane = int64_t(c->p.nx) * c->p.ny;
+  v->omega = c->base + c->L.omega[c->cur];
+  v->phi = c->base + c->L.phi;
+  v->rho = c->base + c->L.rho;
+  v->u = c->base + c->L.u;
+  return EPDLB_OK;
+}
+
 int epdlb_step(epdlb_ctx* c, int64_t n) {
   if (!c) return fail(EPDLB_EINVAL, "ctx is NULL");
   if (!c->seeded) return fail(EPDLB_ESTATE, "step before seed/set_fields/set_state");

@@ -273,3 +273,37 @@ def test_determinism_bitwise():
         outs.append((sim.densities(), sim.populations()))
         sim.close()
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_checkpoint_resume_and_device_views():
+    """get_state -> set_state continues the run (FP64, to rounding of the
+    recomputed field means); device views alias the state planes."""
+    import torch
+    from paper_1804_02883_amd import Simulation
+    say("[resume] cfg1 10 + 5 steps")
+    p = preset("cfg1")
+    a = Simulation(p)
+    a.seed(1001, 1e-3)
+    a.step(10)
+    a.sync()
+    state = a.get_state()
+    views = a.device_views()
+    torch.cuda.synchronize()
+    assert np.array_equal(views["phi"].cpu().numpy(), a.densities())
+    assert np.array_equal(views["omega"].cpu().numpy(), a.fields())
+    rho, u = a.velocity()
+    assert np.array_equal(views["u"].cpu().numpy(), u)
+    assert np.array_equal(views["rho"].cpu().numpy(), rho)
+    b = Simulation(p)
+    b.set_state(*state)
+    a.step(5)
+    b.step(5)
+    a.sync()
+    b.sync()
+    for get in ("densities", "fields"):
+        x, y = getattr(a, get)(), getattr(b, get)()
+        assert np.max(np.abs(x - y)) <= 1e-12 * np.max(np.abs(x)), get
+    (ra, ua), (rb, ub) = a.velocity(), b.velocity()
+    assert np.max(np.abs(ua - ub)) <= 1e-14 + 1e-10 * np.max(np.abs(ua))
+    a.close()
+    b.close()
