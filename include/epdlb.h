@@ -288,7 +288,7 @@ void epdlb_batch_destroy(epdlb_batch* b);
 int epdlb_surrogate_set_weights(epdlb_ctx* ctx, const float* w, int64_t count);
 
 /* Trainer: a device dataset of `capacity` (potentials -> densities) pairs on
- * an nx x ny grid, mini-batches of up to max_batch pairs, mean squared error
+ * an nx x ny grid, mini-batches of up to max_batch (<= 64) pairs, mean squared error
  * of (Phi_hat - Phi)/phi_scale over sites and species A, B, Adam
  * (b1 = 0.9, b2 = 0.999, eps = 1e-8) on FP32 master weights.  The trainer
  * allocates its device memory; `stream` as in epdlb_create. */

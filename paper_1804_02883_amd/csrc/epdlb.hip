@@ -1952,7 +1952,8 @@ int epdlb_nn_create(int32_t nx, int32_t ny, int32_t capacity, int32_t max_batch,
   *out = nullptr;
   if (!is_pow2(nx) || nx < 32 || nx > 1024 || !is_pow2(ny) || ny < 16 || ny > 1024)
     return fail(EPDLB_EINVAL, "nx, ny must be powers of two, 32 <= nx <= 1024, 16 <= ny <= 1024");
-  if (capacity < 1 || max_batch < 1 || max_batch > capacity) return fail(EPDLB_EINVAL, "bad capacity or batch");
+  if (capacity < 1 || max_batch < 1 || max_batch > capacity || max_batch > nn::kMaxBatch)
+    return fail(EPDLB_EINVAL, "bad capacity or batch (1 <= max_batch <= min(capacity, 64))");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= device || device < 0)
     return fail(EPDLB_ENODEV, "no HIP device with that index");

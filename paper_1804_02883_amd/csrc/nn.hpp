@@ -756,6 +756,17 @@ __global__ void __launch_bounds__(256) k_pack(PackArgs P) {
   P.frag[e] = __bf16(v);
 }
 
+// Mini-batch slot list passed by value (kernel arguments are copied at
+// launch), written to device memory in stream order.
+constexpr int kMaxBatch = 64;
+struct SlotList {
+  int n;
+  int s[kMaxBatch];
+};
+__global__ void k_set_slots(SlotList L, int* dst) {
+  if (threadIdx.x < L.n) dst[threadIdx.x] = L.s[threadIdx.x];
+}
+
 // Adam (Kingma & Ba 2015) on FP32 master weights; c1 = lr / (1 - b1^t),
 // c2 = 1 / (1 - b2^t) are the bias corrections of step t.
 __global__ void __launch_bounds__(256) k_adam(float* w, const float* g, float* m, float* v, int n, float b1,

@@ -454,9 +454,14 @@ int nn_backward(epdlb_nn* t, int count) {
 
 int nn_upload_slots(epdlb_nn* t, const int32_t* slots, int count) {
   if (!slots || count < 1 || count > t->max_batch) return fail(EPDLB_EINVAL, "slot list size out of range");
-  for (int i = 0; i < count; ++i)
+  nn::SlotList L{};
+  L.n = count;
+  for (int i = 0; i < count; ++i) {
     if (slots[i] < 0 || slots[i] >= t->capacity) return fail(EPDLB_EINVAL, "slot index out of range");
-  HIPCHK(hipMemcpyAsync(t->slots, slots, sizeof(int) * count, hipMemcpyHostToDevice, t->stream));
+    L.s[i] = slots[i];
+  }
+  hipLaunchKernelGGL(nn::k_set_slots, dim3(1), dim3(nn::kMaxBatch), 0, t->stream, L, t->slots);
+  HIPCHK(hipGetLastError());
   return EPDLB_OK;
 }
 

@@ -95,3 +95,11 @@ def test_create_without_gpu_fails_cleanly():
     with pytest.raises(B.EpdlbError) as e:
         B.epdlb_create(p)
     assert e.value.code in (B.EPDLB_ENODEV, B.EPDLB_EHIP)
+
+
+def test_trainer_create_rejects_bad_sizes_before_device_calls():
+    # argument checks come before any HIP call, so they hold without a GPU
+    for nx, ny, cap, mb in [(48, 32, 8, 4), (32, 8, 8, 4), (32, 32, 8, 9), (32, 32, 100, 65), (32, 32, 8, 0)]:
+        with pytest.raises(B.EpdlbError) as e:
+            B.epdlb_nn_create(nx, ny, cap, mb)
+        assert e.value.code == B.EPDLB_EINVAL, (nx, ny, cap, mb)
