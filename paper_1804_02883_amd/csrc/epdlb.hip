@@ -1245,6 +1245,7 @@ int epdlb_create(const epdlb_params* p, int device, void* stream, void* workspac
   HIPCHK(hipGetDeviceProperties(&prop, device));
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(EPDLB_ENODEV, std::string("library built for gfx950, device is ") + prop.gcnArchName);
+  device_cus();
   epdlb_ctx* c = new (std::nothrow) epdlb_ctx();
   if (!c) return fail(EPDLB_ENOMEM, "host allocation failed");
   c->p = *p;
@@ -1962,6 +1963,7 @@ int epdlb_nn_create(int32_t nx, int32_t ny, int32_t capacity, int32_t max_batch,
   HIPCHK(hipGetDeviceProperties(&prop, device));
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(EPDLB_ENODEV, std::string("library built for gfx950, device is ") + prop.gcnArchName);
+  device_cus();
   epdlb_nn* t = new (std::nothrow) epdlb_nn();
   if (!t) return fail(EPDLB_ENOMEM, "host allocation failed");
   t->device = device;

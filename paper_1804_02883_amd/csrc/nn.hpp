@@ -237,8 +237,9 @@ struct ConvArgs {
 };
 
 // Bias + SiLU (forward) or SiLU'(z) (backward-data) and the stores of one
-// wave's kSB x 32 sites x 64 channels.
-template <int EPI, int SB = kSB>
+// wave's kSB x 32 sites x 64 channels.  ACC_BIAS: the accumulators started
+// at the bias.
+template <int EPI, int SB = kSB, bool ACC_BIAS = false>
 __device__ __forceinline__ void epilogue_hidden(const ConvArgs& P, f32x16 (&acc)[SB][2], int z, int x, int y0,
                                                 const float* bias_s, const bf16x8* pw = nullptr) {
   const int lane = threadIdx.x & 63;
@@ -257,7 +258,7 @@ __device__ __forceinline__ void epilogue_hidden(const ConvArgs& P, f32x16 (&acc)
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const int s = 8 * q + j, nb = s >> 4, i = s & 15;
-          b[j] = __bf16(silu(acc[sb][nb][i] + bias_s[32 * nb + 8 * (i >> 2) + 4 * h + (i & 3)]));
+          b[j] = __bf16(silu(ACC_BIAS ? acc[sb][nb][i] : acc[sb][nb][i] + bias_s[32 * nb + 8 * (i >> 2) + 4 * h + (i & 3)]));
         }
         pr = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pw[q * 64 + lane], b, pr, 0, 0, 0);
       }
@@ -290,7 +291,7 @@ __device__ __forceinline__ void epilogue_hidden(const ConvArgs& P, f32x16 (&acc)
 #pragma unroll
         for (int s = 0; s < 32; ++s) {
           const int nb = s >> 4, i = s & 15;
-          v[s] = acc[sb][nb][i] + bias_s[32 * nb + 8 * (i >> 2) + 4 * h + (i & 3)];
+          v[s] = ACC_BIAS ? acc[sb][nb][i] : acc[sb][nb][i] + bias_s[32 * nb + 8 * (i >> 2) + 4 * h + (i & 3)];
         }
         if (EPI == EPI_FWD_TRAIN) {
 #pragma unroll
@@ -340,6 +341,116 @@ __global__ void __launch_bounds__(NW * 64) k_conv_hidden(ConvArgs P) {
 }
 
 // ---------------------------------------------------------------------------
+// 64-channel hidden convolutions on row tiles (all epilogue kinds).
+// One workgroup per CU keeps the layer's packed weights in LDS; each wave
+// walks 32-site row tiles of one contiguous band of the tile range (one band
+// per XCD, so the halo rows a band re-reads stay in that XCD's L2).
+// The tensor offset of (x, y, chunk) separates into a row term, uniform over
+// the wave, and a per-lane column term, so the activations come in through
+// buffer loads with the row term as the scalar offset and the chunk step as
+// the immediate: no per-tap address arithmetic.  The next tap's activations
+// and weight fragments are issued before the current tap's MFMAs (scheduling
+// fences keep that order); forward kinds start the accumulators at the bias.
+// ---------------------------------------------------------------------------
+constexpr unsigned kBufWord3 = 0x00020000u;  // raw buffer, 32-bit elements
+
+__device__ __forceinline__ void load_tap_buf(__amdgpu_buffer_rsrc_t r, int row_off, int col_off, u32x4 (&b)[4]) {
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks)
+    b[ks] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, col_off + ks * 512, row_off, 0));
+}
+__device__ __forceinline__ void load_frags(const bf16x8* w, int t, bf16x8 (&a)[8]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) a[j] = w[(t * 8 + j) * 64 + lane];
+}
+__device__ __forceinline__ void mma_tap(const bf16x8 (&a)[8], const u32x4 (&b)[4], f32x16 (&acc)[1][2]) {
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+      acc[0][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks * 2 + nb], as_bf16x8(b[ks]), acc[0][nb], 0, 0, 0);
+}
+
+template <int EPI>
+__global__ void __launch_bounds__(kConvThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) k_conv64(ConvArgs P) {
+  constexpr int NW = kConvThreads / 64;
+  extern __shared__ __attribute__((aligned(16))) unsigned char nn_lds[];
+  bf16x8* w = reinterpret_cast<bf16x8*>(nn_lds);
+  __shared__ __attribute__((aligned(16))) float bias_s[kHid];
+  __shared__ bf16x8 pw_s[EPI == EPI_FWD_PROJ ? 4 * 64 : 1];
+  stage_weights(P.wfrag, w, 9 * 4 * 2 * 64 * 16);
+  if constexpr (EPI == EPI_FWD_PROJ) stage_weights(P.pfrag, pw_s, 4 * 64 * 16);
+  if (EPI != EPI_BWD && threadIdx.x < kHid) bias_s[threadIdx.x] = P.bias[threadIdx.x];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, g = lane >> 5;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nx = P.nx, ny = P.ny, d = P.d;
+  const int rpr = nx >> 5, lg = __builtin_ctz(rpr);  // row tiles per grid row
+  const int row_bytes = rpr * 4096;                  // 32 sites x 64 channels x 2 bytes per row tile
+  // tiles [start, start + band) for this workgroup's XCD
+  int start = 0, band = P.ntiles, loc = blockIdx.x, per = gridDim.x;
+  if ((gridDim.x % kNumXcd) == 0 && (P.ntiles % kNumXcd) == 0) {
+    band = P.ntiles / kNumXcd;
+    start = (blockIdx.x % kNumXcd) * band;
+    loc = blockIdx.x / kNumXcd;
+    per = gridDim.x / kNumXcd;
+  }
+  for (int m = loc * NW + wid; m < band; m += per * NW) {
+    const int rt = start + m;
+    const int z = rt / P.tiles_per_sample;
+    const int r = rt - z * P.tiles_per_sample;
+    const int y = r >> lg;
+    const int x = ((r & (rpr - 1)) << 5) + (lane & 31);
+    const __bf16* in = P.in + long(P.slots ? P.slots[z] : z) * P.in_bs;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<__bf16*>(in), 0, int(P.in_bs * 2), kBufWord3);
+    int ro[3], co[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ro[k] = ((y + (k - 1) * d) & (ny - 1)) * row_bytes;
+      const int xs = (x + (k - 1) * d) & (nx - 1);
+      co[k] = (xs >> 5) * 4096 + (xs & 31) * 16 + g * 2048;  // lane group g holds chunks 4g .. 4g+3
+    }
+    f32x16 acc[1][2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        // output rows of register group q: 32 nb + 8 q + 4 g + [0, 4)
+        float4 bv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (EPI != EPI_BWD) bv = *reinterpret_cast<const float4*>(&bias_s[32 * nb + 8 * q + 4 * g]);
+        acc[0][nb][4 * q + 0] = bv.x;
+        acc[0][nb][4 * q + 1] = bv.y;
+        acc[0][nb][4 * q + 2] = bv.z;
+        acc[0][nb][4 * q + 3] = bv.w;
+      }
+    u32x4 b0[4], b1[4];
+    bf16x8 a0[8], a1[8];
+    load_tap_buf(rs, ro[0], co[0], b0);
+    load_frags(w, 0, a0);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      if (t < 8) {
+        const int tn = t + 1;  // taps in (ty, tx) row-major order
+        if (t & 1) {
+          load_tap_buf(rs, ro[tn / 3], co[tn % 3], b0);
+          load_frags(w, tn, a0);
+        } else {
+          load_tap_buf(rs, ro[tn / 3], co[tn % 3], b1);
+          load_frags(w, tn, a1);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (t & 1) mma_tap(a1, b1, acc);
+      else mma_tap(a0, b0, acc);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    epilogue_hidden<EPI, 1, EPI != EPI_BWD>(P, acc, z, x, y, bias_s, pw_s);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // First layer for inference, reading the potentials directly: the B operand
 // of lane group 0 is (w_A - <w_A>, w_B - <w_B>, w_S - <w_S>, f_A, 1/N, 0, 0, 0)
 // in BF16 (the same values k_nn_input stores), group 1 carries the zero
@@ -354,72 +465,70 @@ struct InArgs {
   float fA, invN;
 };
 
+// Row tiles in XCD bands as in k_conv64 (c.ntiles counts 32-site rows); all
+// nine taps' potentials are loaded at the start of a tile.
 template <typename T>
-__global__ void __launch_bounds__(kConvThreads) k_conv_in(InArgs<T> P) {
+__global__ void __launch_bounds__(kConvThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) k_conv_in(InArgs<T> P) {
+  constexpr int NW = kConvThreads / 64;
   extern __shared__ __attribute__((aligned(16))) unsigned char nn_lds[];
-  constexpr int NB = 2;
   bf16x8* w = reinterpret_cast<bf16x8*>(nn_lds);
-  __shared__ float bias_s[kHid];
-  stage_weights(P.c.wfrag, w, 9 * NB * 64 * 16);
+  __shared__ __attribute__((aligned(16))) float bias_s[kHid];
+  stage_weights(P.c.wfrag, w, 9 * 2 * 64 * 16);
   if (threadIdx.x < kHid) bias_s[threadIdx.x] = P.c.bias[threadIdx.x];
   __syncthreads();
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, g = lane >> 5;
+  const int lane = threadIdx.x & 63, g = lane >> 5;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nx = P.c.nx, ny = P.c.ny;
+  const int rpr = nx >> 5, lg = __builtin_ctz(rpr);
   const double dA = P.mean[0], dB = P.mean[1], dS = P.mean[2];
-  const int blk = xcd_tile(blockIdx.x, gridDim.x);
-  for (int tile = blk; tile < P.c.ntiles; tile += gridDim.x) {
-    const TileInfo ti = tile_of(tile, nx, P.c.tiles_per_sample);
-    const int x = ti.x0 + (lane & 31);
-    const int y0 = ti.y0 + wid * kSB;
-    // potentials of the next tap are loaded while the current tap's MFMAs run
-    auto load = [&](int t, T (&v)[kSB][3]) {
-      if (g != 0) return;
-      const int xs = (x + (t % 3 - 1)) & (nx - 1);
+  int start = 0, band = P.c.ntiles, loc = blockIdx.x, per = gridDim.x;
+  if ((gridDim.x % kNumXcd) == 0 && (P.c.ntiles % kNumXcd) == 0) {
+    band = P.c.ntiles / kNumXcd;
+    start = (blockIdx.x % kNumXcd) * band;
+    loc = blockIdx.x / kNumXcd;
+    per = gridDim.x / kNumXcd;
+  }
+  for (int m = loc * NW + wid; m < band; m += per * NW) {
+    const int r = start + m;  // one sample
+    const int y = r >> lg;
+    const int x = ((r & (rpr - 1)) << 5) + (lane & 31);
+    // both lane groups load lane group 0's sites (same cache lines); group 1's
+    // operand is zeroed below
+    T v[9][3];
 #pragma unroll
-      for (int sb = 0; sb < kSB; ++sb) {
-        const long i = long((y0 + sb + (t / 3 - 1)) & (ny - 1)) * nx + xs;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) v[sb][c] = P.w[c * P.plane + i];
-      }
-    };
-    T cur[kSB][3] = {}, nxt[kSB][3] = {};
-    load(0, cur);
-    f32x16 acc[kSB][NB];
-#pragma unroll
-    for (int sb = 0; sb < kSB; ++sb)
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-        for (int i = 0; i < 16; ++i) acc[sb][nb][i] = 0.0f;
-#pragma unroll 1
     for (int t = 0; t < 9; ++t) {
-      if (t < 8) load(t + 1, nxt);
-      bf16x8 b[kSB];
+      const long i = long((y + (t / 3 - 1)) & (ny - 1)) * nx + ((x + (t % 3 - 1)) & (nx - 1));
 #pragma unroll
-      for (int sb = 0; sb < kSB; ++sb) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) b[sb][j] = __bf16(0.0f);
-        if (g == 0) {
-          b[sb][0] = __bf16(float(double(cur[sb][0]) - dA));
-          b[sb][1] = __bf16(float(double(cur[sb][1]) - dB));
-          b[sb][2] = __bf16(float(double(cur[sb][2]) - dS));
-          b[sb][3] = __bf16(P.fA);
-          b[sb][4] = __bf16(P.invN);
-        }
-      }
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const bf16x8 a = w[(t * NB + nb) * 64 + lane];
-#pragma unroll
-        for (int sb = 0; sb < kSB; ++sb)
-          acc[sb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[sb], acc[sb][nb], 0, 0, 0);
-      }
-#pragma unroll
-      for (int sb = 0; sb < kSB; ++sb)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) cur[sb][c] = nxt[sb][c];
+      for (int c = 0; c < 3; ++c) v[t][c] = P.w[c * P.plane + i];
     }
-    epilogue_hidden<EPI_FWD>(P.c, acc, ti.z, x, y0, bias_s);
+    f32x16 acc[1][2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 bv = *reinterpret_cast<const float4*>(&bias_s[32 * nb + 8 * q + 4 * g]);
+        acc[0][nb][4 * q + 0] = bv.x;
+        acc[0][nb][4 * q + 1] = bv.y;
+        acc[0][nb][4 * q + 2] = bv.z;
+        acc[0][nb][4 * q + 3] = bv.w;
+      }
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      bf16x8 b;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) b[j] = __bf16(0.0f);
+      if (g == 0) {
+        b[0] = __bf16(float(double(v[t][0]) - dA));
+        b[1] = __bf16(float(double(v[t][1]) - dB));
+        b[2] = __bf16(float(double(v[t][2]) - dS));
+        b[3] = __bf16(P.fA);
+        b[4] = __bf16(P.invN);
+      }
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+        acc[0][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[(t * 2 + nb) * 64 + lane], b, acc[0][nb], 0, 0, 0);
+    }
+    epilogue_hidden<EPI_FWD, 1, true>(P.c, acc, 0, x, y, bias_s);
   }
 }
 

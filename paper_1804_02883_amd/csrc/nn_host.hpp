@@ -76,13 +76,42 @@ hipError_t nn_pack(const float* w, __bf16* ffrag, __bf16* bfrag, hipStream_t s) 
 constexpr int kConvMaxBlocks = 512;
 constexpr int kWgradMaxBlocks = 256;
 
+// Compute units of the current device, cached per device (the first call
+// happens at create time, outside any stream capture).
+int device_cus() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cache[dev]) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cache[dev] = n;
+  }
+  return cache[dev];
+}
+
+// `a` carries tiles of kTW x kConvTH sites (ntiles over all samples); the
+// 64-channel kernel re-tiles into 32-site rows, one workgroup per CU.
 template <int CI, int EPI>
 hipError_t conv_hidden(const nn::ConvArgs& a, hipStream_t s) {
   const size_t lds = size_t(9) * (CI / 16) * 2 * 64 * 16;
-  auto k = nn::k_conv_hidden<CI, EPI>;
-  hipError_t e = prep_lds(k, lds);
-  if (e != hipSuccess) return e;
-  launch_k(k, dim3(std::min(a.ntiles, kConvMaxBlocks)), dim3(nn::kConvThreads), lds, s, a);
+  if constexpr (CI == nn::kHid) {
+    nn::ConvArgs b = a;
+    const int nsamples = a.ntiles / a.tiles_per_sample;
+    b.tiles_per_sample = (a.nx / nn::kTW) * a.ny;
+    b.ntiles = b.tiles_per_sample * nsamples;
+    constexpr int nw = nn::kConvThreads / 64;
+    const int grid = std::min(device_cus(), (b.ntiles + nw - 1) / nw);
+    auto k = nn::k_conv64<EPI>;
+    hipError_t e = prep_lds(k, lds);
+    if (e != hipSuccess) return e;
+    launch_k(k, dim3(grid), dim3(nn::kConvThreads), lds, s, b);
+  } else {
+    auto k = nn::k_conv_hidden<CI, EPI>;
+    hipError_t e = prep_lds(k, lds);
+    if (e != hipSuccess) return e;
+    launch_k(k, dim3(std::min(a.ntiles, kConvMaxBlocks)), dim3(nn::kConvThreads), lds, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -162,9 +191,12 @@ int stage_nn(epdlb_ctx* c, int mode, int use_corr) {
     ia.plane = n;
     ia.fA = float(p.f_A);
     ia.invN = float(1.0 / p.n_contour);
+    // 32-site row tiles; one workgroup per CU
+    ia.c.tiles_per_sample = ia.c.ntiles = (p.nx / nn::kTW) * p.ny;
+    constexpr int nw = nn::kConvThreads / 64;
+    const int grid = std::min(device_cus(), (ia.c.ntiles + nw - 1) / nw);
     ProfScope ps(c, K_NN_CONV0);
-    launch_k(nn::k_conv_in<T>, dim3(std::min(tps, kConvMaxBlocks)), dim3(nn::kConvThreads),
-             size_t(9) * 2 * 64 * 16, c->stream, ia);
+    launch_k(nn::k_conv_in<T>, dim3(grid), dim3(nn::kConvThreads), size_t(9) * 2 * 64 * 16, c->stream, ia);
   }
   HIPCHK(hipGetLastError());
   // second hidden layer, then the third with the output taps' projection
