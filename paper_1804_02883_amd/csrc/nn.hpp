@@ -465,22 +465,35 @@ struct InArgs {
   float fA, invN;
 };
 
-// Row tiles in XCD bands as in k_conv64 (c.ntiles counts 32-site rows); all
-// nine taps' potentials are loaded at the start of a tile.
+// Row tiles in XCD bands as in k_conv64 (c.ntiles counts 32-site rows).  A
+// wave converts the 3 x 34 sites its row tile reads (halo included) once into
+// B operands in its own LDS slots; each tap then reads its operand with one
+// 16-byte LDS load (lane group 1 reads the zero slot).
+constexpr int kInStage = 3 * 34 + 1;  // B operands per wave: 3 rows x 34 sites, then zero
+
 template <typename T>
-__global__ void __launch_bounds__(kConvThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) k_conv_in(InArgs<T> P) {
+__global__ void __launch_bounds__(kConvThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) k_conv_in(InArgs<T> P) {
   constexpr int NW = kConvThreads / 64;
   extern __shared__ __attribute__((aligned(16))) unsigned char nn_lds[];
   bf16x8* w = reinterpret_cast<bf16x8*>(nn_lds);
   __shared__ __attribute__((aligned(16))) float bias_s[kHid];
+  __shared__ bf16x8 stage_s[NW * kInStage];
   stage_weights(P.c.wfrag, w, 9 * 2 * 64 * 16);
   if (threadIdx.x < kHid) bias_s[threadIdx.x] = P.c.bias[threadIdx.x];
-  __syncthreads();
   const int lane = threadIdx.x & 63, g = lane >> 5;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  bf16x8* st = stage_s + wid * kInStage;
+  if (lane == 0) {
+    bf16x8 zero;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) zero[j] = __bf16(0.0f);
+    st[kInStage - 1] = zero;
+  }
+  __syncthreads();
   const int nx = P.c.nx, ny = P.c.ny;
   const int rpr = nx >> 5, lg = __builtin_ctz(rpr);
   const double dA = P.mean[0], dB = P.mean[1], dS = P.mean[2];
+  const __bf16 bfA = __bf16(P.fA), binvN = __bf16(P.invN);
   int start = 0, band = P.c.ntiles, loc = blockIdx.x, per = gridDim.x;
   if ((gridDim.x % kNumXcd) == 0 && (P.c.ntiles % kNumXcd) == 0) {
     band = P.c.ntiles / kNumXcd;
@@ -491,15 +504,27 @@ __global__ void __launch_bounds__(kConvThreads) __attribute__((amdgpu_waves_per_
   for (int m = loc * NW + wid; m < band; m += per * NW) {
     const int r = start + m;  // one sample
     const int y = r >> lg;
-    const int x = ((r & (rpr - 1)) << 5) + (lane & 31);
-    // both lane groups load lane group 0's sites (same cache lines); group 1's
-    // operand is zeroed below
-    T v[9][3];
+    const int x0 = (r & (rpr - 1)) << 5;
+    // the previous tile's reads of this wave's slots come before the rewrite
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // stage: slot e = row * 34 + col holds site (x0 - 1 + col, y - 1 + row)
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const long i = long((y + (t / 3 - 1)) & (ny - 1)) * nx + ((x + (t % 3 - 1)) & (nx - 1));
-#pragma unroll
-      for (int c = 0; c < 3; ++c) v[t][c] = P.w[c * P.plane + i];
+    for (int k = 0; k < 2; ++k) {
+      const int e = lane + 64 * k;
+      if (e < 3 * 34) {
+        const int row = e / 34, col = e - row * 34;
+        const long i = long((y - 1 + row) & (ny - 1)) * nx + ((x0 - 1 + col) & (nx - 1));
+        bf16x8 b;
+        b[0] = __bf16(float(double(P.w[i]) - dA));
+        b[1] = __bf16(float(double(P.w[P.plane + i]) - dB));
+        b[2] = __bf16(float(double(P.w[2 * P.plane + i]) - dS));
+        b[3] = bfA;
+        b[4] = binvN;
+        b[5] = b[6] = b[7] = __bf16(0.0f);
+        st[e] = b;
+      }
     }
     f32x16 acc[1][2];
 #pragma unroll
@@ -512,23 +537,19 @@ __global__ void __launch_bounds__(kConvThreads) __attribute__((amdgpu_waves_per_
         acc[0][nb][4 * q + 2] = bv.z;
         acc[0][nb][4 * q + 3] = bv.w;
       }
+    // the slots written above by other lanes of this wave are visible here
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int xl = lane & 31;
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-      bf16x8 b;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) b[j] = __bf16(0.0f);
-      if (g == 0) {
-        b[0] = __bf16(float(double(v[t][0]) - dA));
-        b[1] = __bf16(float(double(v[t][1]) - dB));
-        b[2] = __bf16(float(double(v[t][2]) - dS));
-        b[3] = __bf16(P.fA);
-        b[4] = __bf16(P.invN);
-      }
+      const bf16x8 b = st[g ? kInStage - 1 : (t / 3) * 34 + xl + (t % 3)];
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb)
         acc[0][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[(t * 2 + nb) * 64 + lane], b, acc[0][nb], 0, 0, 0);
     }
-    epilogue_hidden<EPI_FWD, 1, true>(P.c, acc, 0, x, y, bias_s);
+    epilogue_hidden<EPI_FWD, 1, true>(P.c, acc, 0, x0 + xl, y, bias_s);
   }
 }
 

@@ -191,10 +191,10 @@ int stage_nn(epdlb_ctx* c, int mode, int use_corr) {
     ia.plane = n;
     ia.fA = float(p.f_A);
     ia.invN = float(1.0 / p.n_contour);
-    // 32-site row tiles; one workgroup per CU
+    // 32-site row tiles; two workgroups per CU
     ia.c.tiles_per_sample = ia.c.ntiles = (p.nx / nn::kTW) * p.ny;
     constexpr int nw = nn::kConvThreads / 64;
-    const int grid = std::min(device_cus(), (ia.c.ntiles + nw - 1) / nw);
+    const int grid = std::min(2 * device_cus(), (ia.c.ntiles + nw - 1) / nw);
     ProfScope ps(c, K_NN_CONV0);
     launch_k(nn::k_conv_in<T>, dim3(grid), dim3(nn::kConvThreads), size_t(9) * 2 * 64 * 16, c->stream, ia);
   }
