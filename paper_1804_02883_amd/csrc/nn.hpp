@@ -342,17 +342,20 @@ __global__ void __launch_bounds__(NW * 64) k_conv_hidden(ConvArgs P) {
 
 // ---------------------------------------------------------------------------
 // 64-channel hidden convolutions on row tiles (all epilogue kinds).
-// One workgroup per CU keeps the layer's packed weights in LDS; each wave
-// walks 32-site row tiles of one contiguous band of the tile range (one band
-// per XCD, so the halo rows a band re-reads stay in that XCD's L2).
+// One workgroup of kConv64Threads per CU (4 waves per SIMD) keeps the layer's
+// packed weights in LDS; each wave walks 32-site row tiles of one contiguous
+// band of the tile range (one band per XCD, so the halo rows a band re-reads
+// stay in that XCD's L2).
 // The tensor offset of (x, y, chunk) separates into a row term, uniform over
 // the wave, and a per-lane column term, so the activations come in through
 // buffer loads with the row term as the scalar offset and the chunk step as
 // the immediate: no per-tap address arithmetic.  The next tap's activations
-// and weight fragments are issued before the current tap's MFMAs (scheduling
-// fences keep that order); forward kinds start the accumulators at the bias.
+// are issued before the current tap's weight fragments and MFMAs (scheduling
+// fences keep that order; the other waves of the SIMD cover the LDS latency);
+// forward kinds start the accumulators at the bias.
 // ---------------------------------------------------------------------------
 constexpr unsigned kBufWord3 = 0x00020000u;  // raw buffer, 32-bit elements
+constexpr int kConv64Threads = 1024;
 
 __device__ __forceinline__ void load_tap_buf(__amdgpu_buffer_rsrc_t r, int row_off, int col_off, u32x4 (&b)[4]) {
 #pragma unroll
@@ -373,8 +376,8 @@ __device__ __forceinline__ void mma_tap(const bf16x8 (&a)[8], const u32x4 (&b)[4
 }
 
 template <int EPI>
-__global__ void __launch_bounds__(kConvThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) k_conv64(ConvArgs P) {
-  constexpr int NW = kConvThreads / 64;
+__global__ void __launch_bounds__(kConv64Threads) __attribute__((amdgpu_waves_per_eu(4, 4))) k_conv64(ConvArgs P) {
+  constexpr int NW = kConv64Threads / 64;
   extern __shared__ __attribute__((aligned(16))) unsigned char nn_lds[];
   bf16x8* w = reinterpret_cast<bf16x8*>(nn_lds);
   __shared__ __attribute__((aligned(16))) float bias_s[kHid];
@@ -426,24 +429,19 @@ __global__ void __launch_bounds__(kConvThreads) __attribute__((amdgpu_waves_per_
         acc[0][nb][4 * q + 3] = bv.w;
       }
     u32x4 b0[4], b1[4];
-    bf16x8 a0[8], a1[8];
     load_tap_buf(rs, ro[0], co[0], b0);
-    load_frags(w, 0, a0);
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       if (t < 8) {
         const int tn = t + 1;  // taps in (ty, tx) row-major order
-        if (t & 1) {
-          load_tap_buf(rs, ro[tn / 3], co[tn % 3], b0);
-          load_frags(w, tn, a0);
-        } else {
-          load_tap_buf(rs, ro[tn / 3], co[tn % 3], b1);
-          load_frags(w, tn, a1);
-        }
+        if (t & 1) load_tap_buf(rs, ro[tn / 3], co[tn % 3], b0);
+        else load_tap_buf(rs, ro[tn / 3], co[tn % 3], b1);
       }
       __builtin_amdgcn_sched_barrier(0);
-      if (t & 1) mma_tap(a1, b1, acc);
-      else mma_tap(a0, b0, acc);
+      bf16x8 a[8];
+      load_frags(w, t, a);
+      if (t & 1) mma_tap(a, b1, acc);
+      else mma_tap(a, b0, acc);
       __builtin_amdgcn_sched_barrier(0);
     }
     epilogue_hidden<EPI, 1, EPI != EPI_BWD>(P, acc, z, x, y, bias_s, pw_s);
@@ -986,6 +984,24 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_nn_norm(NormArgs<T> P) {
   __shared__ double red[16 * 3];
   __shared__ double scale_s[2];
+  const long n = P.n;
+  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  const bool in = i < n;
+  // this site's inputs are issued first, so their latency overlaps that of
+  // the partial sums below
+  T hA = T(0), hB = T(0), wS = T(0), st = T(0), cr = T(0), eA = T(0), eB = T(0), eS = T(0);
+  if (in) {
+    hA = P.src[i];
+    hB = P.src[n + i];
+    wS = P.wS[i];
+    st = P.stilde[i];
+    if (P.use_corr) cr = P.corr[i];
+    if (P.mode != 0) {
+      eA = P.phi[i];
+      eB = P.phi[n + i];
+      eS = P.phi[2 * n + i];
+    }
+  }
   {
     double acc[2] = {0.0, 0.0};
     for (int s = threadIdx.x; s < P.nslots; s += blockDim.x) {
@@ -999,25 +1015,22 @@ __global__ void __launch_bounds__(256) k_nn_norm(NormArgs<T> P) {
     }
     __syncthreads();
   }
-  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
   double m[3] = {0.0, 0.0, 0.0};  // surrogate residual, surrogate error, exact residual
-  if (i < P.n) {
-    const long n = P.n;
-    const T pA = T(scale_s[0]) * P.src[i], pB = T(scale_s[1]) * P.src[n + i];
+  if (in) {
+    const T pA = T(scale_s[0]) * hA, pB = T(scale_s[1]) * hB;
     const T cS = T(P.V * P.phiSbar / P.scal[kQS]);
-    const T pS = cS * exp(-(P.wS[i] - T(P.scal[kGaugeS])));
-    T Sv = pA * T(P.invDA) + pB * T(P.invDB) + pS * T(P.invDS) - P.stilde[i];
-    if (P.use_corr) Sv -= P.corr[i];
+    const T pS = cS * exp(-(wS - T(P.scal[kGaugeS])));
+    T Sv = pA * T(P.invDA) + pB * T(P.invDB) + pS * T(P.invDS) - st;
+    if (P.use_corr) Sv -= cr;
     if (P.mode == 0) {
       P.phi[i] = pA;
       P.phi[n + i] = pB;
       P.phi[2 * n + i] = pS;
       m[0] = fabs(double(pA) + double(pB) + double(pS) - 1.0);
     } else {
-      const T eA = P.phi[i], eB = P.phi[n + i];
       P.corr[i] = (pA - eA) * T(P.invDA) + (pB - eB) * T(P.invDB);
       m[1] = fmax(fabs(double(pA) - double(eA)), fabs(double(pB) - double(eB)));
-      m[2] = fabs(double(eA) + double(eB) + double(P.phi[2 * n + i]) - 1.0);
+      m[2] = fabs(double(eA) + double(eB) + double(eS) - 1.0);
     }
     P.S[i] = Sv;
   }

@@ -100,12 +100,12 @@ hipError_t conv_hidden(const nn::ConvArgs& a, hipStream_t s) {
     const int nsamples = a.ntiles / a.tiles_per_sample;
     b.tiles_per_sample = (a.nx / nn::kTW) * a.ny;
     b.ntiles = b.tiles_per_sample * nsamples;
-    constexpr int nw = nn::kConvThreads / 64;
+    constexpr int nw = nn::kConv64Threads / 64;
     const int grid = std::min(device_cus(), (b.ntiles + nw - 1) / nw);
     auto k = nn::k_conv64<EPI>;
     hipError_t e = prep_lds(k, lds);
     if (e != hipSuccess) return e;
-    launch_k(k, dim3(grid), dim3(nn::kConvThreads), lds, s, b);
+    launch_k(k, dim3(grid), dim3(nn::kConv64Threads), lds, s, b);
   } else {
     auto k = nn::k_conv_hidden<CI, EPI>;
     hipError_t e = prep_lds(k, lds);
