@@ -37,51 +37,33 @@ METRIC = "lattice site-updates/s per hybrid step, plain vs surrogate at <=1e-3 d
 # HBM traffic per launch measured with rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
 # (one counter per run, averaged over the kernel's dispatches), scaled by the
 # same counters' readings for a plain 256 MiB copy (FETCH x2.0, WRITE x1.0);
-# the summary with its commands is profiles/prop_cfg3_traffic.md.  Valid only
-# while the kernel sources hash to `source_sha256`.
-_SRC = "10ae0a2d916a3544bcd02bdfeda6f9c63cbe834a83619ba725a494246dc16193"
+# the summaries with their commands are profiles/prop_cfg3_traffic.md and
+# profiles/nn_conv_cfg5q_traffic.md.  An entry is valid only while the sources
+# its kernels are built from hash to `source_sha256`.
+_PROP_FILES = ("fft.hpp", "kernels.hpp")
+_NN_FILES = ("kernels.hpp", "nn.hpp")
 MEASURED_TRAFFIC = {
-    ("cfg3", "prop_col"): dict(bytes_per_launch=17276403, source_sha256=_SRC),
-    ("cfg3", "prop_row"): dict(bytes_per_launch=16033181, source_sha256=_SRC),
+    ("cfg3", "prop_col"): dict(bytes_per_launch=17276403, files=_PROP_FILES,
+                               source_sha256="10ae0a2d916a3544bcd02bdfeda6f9c63cbe834a83619ba725a494246dc16193"),
+    ("cfg3", "prop_row"): dict(bytes_per_launch=16033181, files=_PROP_FILES,
+                               source_sha256="10ae0a2d916a3544bcd02bdfeda6f9c63cbe834a83619ba725a494246dc16193"),
+    # mean over the two 64 -> 64 launches of a surrogate step
+    ("cfg5q", "nn_conv"): dict(bytes_per_launch=63954944, files=_NN_FILES, source_sha256="57fdad948ceeb4b2c773626518c7436a1a2c9ec88920e8fdd0199dae65745846"),
 }
-HBM_PEAK_GBS = 8000.0
-BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense
-WEIGHTS = os.path.join(ROOT, "paper_1804_02883_amd", "weights", "surrogate_q.npy")
-# useful flops per site of each network launch (multiply-add = 2 flops):
-# 9 taps x cin x cout x 2; conv0 has 5 real input channels, the output layer 2
-NN_FLOPS_PER_SITE = {"nn_conv0": 9 * 5 * 64 * 2, "nn_conv": 9 * 64 * 64 * 2}
-
-# Algorithmic bytes per site per hybrid STEP of each kernel family, in units
-# of the element size P (forward and backward chains counted together):
-#   advect_update : read Phi 3, omega 3, u 2; write omega 3, S~ 1        = 12P
-#   boltzmann     : read omega_A, omega_B; write their half-step factors =  4P
-#   prop_row/col  : per chain, the first launch reads a factor plane and
-#                   writes the scratch plane (2P); a fused boundary launch
-#                   reads scratch + factor and writes q_{a+1} + scratch (4P);
-#                   the last reads scratch + factor and writes q_N (3P)
-#   density       : read 2N chain planes + omega_S + S~, write Phi 3 + S = (2N + 6)P
-#   force_*       : 3P + 4P + 4P (row FFT of S, column pass, row inverse)
-#   lb            : read 9 populations + F 2; write 9 + rho + u 2        = 23P
-def step_bytes_per_site(kind, N, P):
-    last_row = (N - 1) % 2 == 1           # the final propagator launch is x-oriented
-    n_fused_row = sum(1 for s in range(N - 1) if s % 2 == 1)
-    n_fused_col = sum(1 for s in range(N - 1) if s % 2 == 0)
-    per_chain_row = 2 + 4 * n_fused_row + (3 if last_row else 0)
-    per_chain_col = 4 * n_fused_col + (0 if last_row else 3)
-    return {
-        "advect_update": 12 * P, "boltzmann": 4 * P,
-        "prop_row": 2 * per_chain_row * P, "prop_col": 2 * per_chain_col * P,
-        "density": (2 * N + 6) * P,
-        "force_row_fwd": 3 * P, "force_col": 4 * P, "force_row_inv": 4 * P,
-        "lb": 23 * P,
-    }.get(kind)
 
 
-def kernel_source_sha256():
+def kernel_source_sha256(files=_PROP_FILES):
     import hashlib
     csrc = os.path.join(ROOT, "paper_1804_02883_amd", "csrc")
-    data = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("fft.hpp", "kernels.hpp"))
+    data = b"".join(open(os.path.join(csrc, f), "rb").read() for f in files)
     return hashlib.sha256(data).hexdigest()
+
+
+def measured_traffic(workload, fam):
+    tr = MEASURED_TRAFFIC.get((workload, fam))
+    if tr and tr["source_sha256"] == kernel_source_sha256(tr["files"]):
+        return tr["bytes_per_launch"]
+    return None
 
 
 def cpu_baseline(preset_name, seconds):
@@ -140,7 +122,8 @@ def surrogate_line(args):
     conv = prof["nn_conv"]
     achieved = NN_FLOPS_PER_SITE["nn_conv"] * n / (conv["avg_ms"] / 1e3) / 1e12
     roofline = dict(bound="mfma", kernel="nn_conv", achieved=round(achieved, 1), peak=BF16_MFMA_PEAK_TFLOPS,
-                    unit="TFLOP/s", frac=round(achieved / BF16_MFMA_PEAK_TFLOPS, 4), traffic=None,
+                    unit="TFLOP/s", frac=round(achieved / BF16_MFMA_PEAK_TFLOPS, 4),
+                    traffic=measured_traffic("cfg5q", "nn_conv"),
                     avg_launch_us=round(conv["avg_ms"] * 1e3, 3), launches_per_step=conv["launches"] / 100,
                     alg_flops_per_launch=NN_FLOPS_PER_SITE["nn_conv"] * n)
     tot = sum(x["total_ms"] for x in prof.values())
@@ -227,8 +210,7 @@ def plain_line(args, workload):
     fam = max(fams, key=lambda k: prof[k]["total_ms"])
     alg_bytes = step_bytes_per_site(fam, N, P) * n * prof_steps
     achieved = alg_bytes / (prof[fam]["total_ms"] / 1e3) / 1e9
-    tr = MEASURED_TRAFFIC.get((workload, fam))
-    traffic = tr["bytes_per_launch"] if tr and tr["source_sha256"] == kernel_source_sha256() else None
+    traffic = measured_traffic(workload, fam)
     roofline = dict(bound="hbm", kernel=fam, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                     avg_launch_us=round(prof[fam]["avg_ms"] * 1e3, 3),
