@@ -40,6 +40,12 @@ READINGS = {
     "R13": "Lattice force F = f dt^2/dx with rho_0 = 1; g in units f* = rho R_G tau^-2.",
     "R14": "Gauge: omega_I shifted by constants c_I inside the propagator "
            "(densities are invariant under such shifts).",
+    "R15": "Multi-relaxation LB (lb_mrt = 1): collision in moment space; the traceless "
+           "non-equilibrium stress is scaled by gamma_s, its trace by gamma_b, the three "
+           "non-hydrodynamic modes by gamma_g (not stated in the paper; default 0). The "
+           "forcing stress Sigma of Eq. force_col uses the trace split of d = 2 "
+           "(the printed 2/3 and 1/3 are the d = 3 values; the bulk-viscosity relation of "
+           "the same passage carries d). u includes F/2; the momentum gains F.",
 }
 
 PARITY_UNPINNED = ()
@@ -313,6 +319,14 @@ def lb_equilibrium(rho, u):
     return feq
 
 
+def lb_stream(fstar):
+    """Streaming of Eq. LB_prop as a pull: f_i(x) = f*_i(x - c_i), periodic."""
+    f = np.empty_like(fstar)
+    for i in range(9):
+        f[i] = np.roll(fstar[i], shift=(C9[i, 1], C9[i, 0]), axis=(0, 1))
+    return f
+
+
 def lb_step(fstar, F, tau):
     """Stream then collide with body force (reading R12).
 
@@ -321,9 +335,7 @@ def lb_step(fstar, F, tau):
     f*_i = f_i - (f_i - feq_i)/tau + (1 - 1/(2 tau)) w_i [3 (c_i - u).F + 9 (c_i.u)(c_i.F)].
     Returns (f*_new, rho, u).
     """
-    f = np.empty_like(fstar)
-    for i in range(9):
-        f[i] = np.roll(fstar[i], shift=(C9[i, 1], C9[i, 0]), axis=(0, 1))
+    f = lb_stream(fstar)
     rho = f.sum(axis=0)
     jx = sum(C9[i, 0] * f[i] for i in range(9))
     jy = sum(C9[i, 1] * f[i] for i in range(9))
@@ -341,9 +353,89 @@ def lb_step(fstar, F, tau):
     return out, rho, u
 
 
-def poiseuille_profile(ny, F0, tau):
-    """Eq. flow_field in lattice units at cell centres y + 1/2, nu = (tau - 1/2)/3, rho = 1."""
-    nu = (tau - 0.5) / 3.0
+def lb_moments(f):
+    """rho = sum f_i, j = sum f_i c_i, Pi = sum f_i c_i c_i (shapes (), (2,), (2, 2))."""
+    c = C9.astype(np.float64)
+    rho = f.sum(axis=0)
+    j = np.einsum("ia,i...->a...", c, f)
+    Pi = np.einsum("ia,ib,i...->ab...", c, c, f)
+    return rho, j, Pi
+
+
+def lb_hermite(rho, j, Pi):
+    """Populations carrying the moments (rho, j, Pi) and nothing else: the
+    second-order Hermite expansion in the D2Q9 weights,
+    n_i = w_i [rho + j.c_i/c_s^2 + (Pi - rho c_s^2 I):(c_i c_i - c_s^2 I)/(2 c_s^4)]."""
+    out = np.empty((9,) + np.shape(rho))
+    for i in range(9):
+        cx, cy = float(C9[i, 0]), float(C9[i, 1])
+        h = ((Pi[0, 0] - rho * CS2) * (cx * cx - CS2) + (Pi[1, 1] - rho * CS2) * (cy * cy - CS2)
+             + 2.0 * Pi[0, 1] * cx * cy)
+        out[i] = W9[i] * (rho + (j[0] * cx + j[1] * cy) / CS2 + h / (2.0 * CS2 * CS2))
+    return out
+
+
+def lb_collide_mrt(f, F, gamma_s, gamma_b, gamma_g):
+    """Multi-relaxation collision with the force term of Eq. force_col (reading R15).
+
+    u = (j + F/2)/rho; Pi_eq = rho c_s^2 I + rho u u; the non-equilibrium stress
+    Pi - Pi_eq keeps gamma_s of its traceless part and gamma_b of its trace;
+    Sigma = (1 + gamma_s)/2 [u F + F u - (u.F) I] + (1 + gamma_b)/2 (u.F) I;
+    post-collision moments (rho, j + F, Pi_eq + relaxed + Sigma); the
+    non-hydrodynamic remainder f - hermite(moments of f) is scaled by gamma_g.
+    Returns (f*, rho, u)."""
+    rho, j, Pi = lb_moments(f)
+    u = (j + 0.5 * F) / rho
+    eye = np.eye(2)[:, :, None, None]
+    uu = np.einsum("a...,b...->ab...", u, u)
+    Pi_eq = rho * CS2 * eye + rho * uu
+    neq = Pi - Pi_eq
+    tr = neq[0, 0] + neq[1, 1]
+    relaxed = gamma_s * (neq - 0.5 * tr * eye) + gamma_b * 0.5 * tr * eye
+    uF = u[0] * F[0] + u[1] * F[1]
+    sym = np.einsum("a...,b...->ab...", u, F) + np.einsum("a...,b...->ab...", F, u)
+    Sigma = 0.5 * (1.0 + gamma_s) * (sym - uF * eye) + 0.5 * (1.0 + gamma_b) * uF * eye
+    post = lb_hermite(rho, j + F, Pi_eq + relaxed + Sigma)
+    ghost = f - lb_hermite(rho, j, Pi)
+    return post + gamma_g * ghost, rho, u
+
+
+def lb_step_mrt(fstar, F, gamma_s, gamma_b, gamma_g):
+    """Stream (Eq. LB_prop) then the multi-relaxation collision.  Returns (f*, rho, u)."""
+    return lb_collide_mrt(lb_stream(fstar), F, gamma_s, gamma_b, gamma_g)
+
+
+def mrt_gammas(eta, eta_B, rho, dx, dt, d=2):
+    """gamma_s, gamma_b from the viscosity relations of Sec. II:
+    eta = (dt rho c_s^2/2)(1 + gamma_s)/(1 - gamma_s),
+    eta_B = (dt rho c_s^2/d)(1 + gamma_b)/(1 - gamma_b), c_s^2 = dx^2/(3 dt^2)."""
+    cs2 = dx * dx / (3.0 * dt * dt)
+    a = 2.0 * eta / (dt * rho * cs2)
+    b = d * eta_B / (dt * rho * cs2)
+    return (a - 1.0) / (a + 1.0), (b - 1.0) / (b + 1.0)
+
+
+def lb_viscosity(p):
+    """Lattice kinematic shear viscosity of the configured collision (rho = 1):
+    BGK (tau - 1/2)/3; multi-relaxation (c_s^2/2)(1 + gamma_s)/(1 - gamma_s)."""
+    if p.get("lb_mrt", 0):
+        gs = p["lb_gamma_s"]
+        return 0.5 * CS2 * (1.0 + gs) / (1.0 - gs)
+    return (p["lb_tau"] - 0.5) / 3.0
+
+
+def lb_advance(fstar, F, p):
+    """The configured LB step: BGK (lb_mrt = 0) or multi-relaxation (lb_mrt = 1)."""
+    if p.get("lb_mrt", 0):
+        return lb_step_mrt(fstar, F, p["lb_gamma_s"], p["lb_gamma_b"], p.get("lb_gamma_g", 0.0))
+    return lb_step(fstar, F, p["lb_tau"])
+
+
+def poiseuille_profile(ny, F0, tau, nu=None):
+    """Eq. flow_field in lattice units at cell centres y + 1/2, rho = 1, with
+    nu = (tau - 1/2)/3 unless the viscosity nu is given."""
+    if nu is None:
+        nu = (tau - 0.5) / 3.0
     Y = np.arange(ny) + 0.5
     Ly = float(ny)
     return -(F0 / (2.0 * nu)) * (Y - Ly / 2) * (np.abs(Y - Ly / 2) - Ly / 2)
@@ -369,7 +461,7 @@ def init_state(p, omega0):
     d = densities(omega, p)
     u = np.zeros((2, ny, nx))
     if p.get("init_flow", 1):
-        prof = poiseuille_profile(ny, external_force_lattice_amplitude(p), p["lb_tau"])
+        prof = poiseuille_profile(ny, external_force_lattice_amplitude(p), p["lb_tau"], nu=lb_viscosity(p))
         u[0] = prof[:, None]
     rho = np.ones((ny, nx))
     fstar = lb_equilibrium(rho, u)
@@ -394,7 +486,7 @@ def step(state, p):
     D = diffusivities(p)
     S = sum((d["phi"][I] - phi_t[I]) / D[I] for I in range(3))
     F = lattice_force(S, p)
-    fstar, rho, u = lb_step(state["fstar"], F, p["lb_tau"])
+    fstar, rho, u = lb_advance(state["fstar"], F, p)
     return dict(omega=omega_new, phi=d["phi"], fstar=fstar, u=u, rho=rho, n=state["n"] + 1,
                 Q_P=d["Q_P"], Q_S=d["Q_S"], S=S, F=F, phi_t=phi_t)
 
