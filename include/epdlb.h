@@ -84,6 +84,19 @@ typedef struct {
   int32_t check_every;    /* default 10 */
   double resid_tol;       /* default 1e-3 */
   double err_tol;         /* default 1e-3; 0 disables the requirement */
+  /* LB collision (Sec. II).  0: BGK with relaxation time lb_tau and the
+   * second-order force term.  1: multi-relaxation D2Q9 in moment space: the
+   * traceless non-equilibrium stress keeps lb_gamma_s of itself, its trace
+   * lb_gamma_b, the three non-hydrodynamic modes lb_gamma_g; the force term
+   * of Eq. force_col adds to the stress, in the two-dimensional trace split,
+   *   Sigma = (1 + gamma_s)/2 [u F + F u - (u.F) I] + (1 + gamma_b)/2 (u.F) I,
+   * and F to the momentum.  Lattice viscosities (rho = 1):
+   *   nu = (1/6)(1 + gamma_s)/(1 - gamma_s), nu_B = (1/6)(1 + gamma_b)/(1 - gamma_b);
+   * lb_tau is then unused.  Each gamma must lie in (-1, 1).  The paper's
+   * eta = eta_B = 1 R_G^2/tau rho at dx = R_G/3, dt = 0.002 tau gives
+   * gamma_s = gamma_b = -0.8050541516245486 (lattice nu = 0.018). */
+  int32_t lb_mrt;         /* default 0 */
+  double lb_gamma_s, lb_gamma_b, lb_gamma_g; /* defaults 0 */
 } epdlb_params;
 
 /* Scalars maintained on the device (FP64). */

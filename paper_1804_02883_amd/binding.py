@@ -52,6 +52,8 @@ class epdlb_params(ctypes.Structure):
         ("init_flow", ctypes.c_int32), ("couple_lb", ctypes.c_int32),
         ("density_mode", ctypes.c_int32), ("fallback_every", ctypes.c_int32),
         ("check_every", ctypes.c_int32), ("resid_tol", ctypes.c_double), ("err_tol", ctypes.c_double),
+        ("lb_mrt", ctypes.c_int32),
+        ("lb_gamma_s", ctypes.c_double), ("lb_gamma_b", ctypes.c_double), ("lb_gamma_g", ctypes.c_double),
     ]
 
 
@@ -208,6 +210,17 @@ def make_params(d=None, **kw):
             raise KeyError(f"unknown parameter {k}")
         setattr(p, k, v)
     return p
+
+
+def mrt_gammas(eta, eta_B, rho=1.0, dx=1.0 / 3.0, dt=0.002, d=2):
+    """(gamma_s, gamma_b) of the multi-relaxation LB from the shear and bulk
+    viscosities (Sec. II): eta = (dt rho c_s^2/2)(1 + gamma_s)/(1 - gamma_s),
+    eta_B = (dt rho c_s^2/d)(1 + gamma_b)/(1 - gamma_b), c_s^2 = dx^2/(3 dt^2).
+    Host arithmetic only."""
+    cs2 = dx * dx / (3.0 * dt * dt)
+    a = 2.0 * eta / (dt * rho * cs2)
+    b = d * eta_B / (dt * rho * cs2)
+    return (a - 1.0) / (a + 1.0), (b - 1.0) / (b + 1.0)
 
 
 # ---- functions with the C ABI's names --------------------------------------------------

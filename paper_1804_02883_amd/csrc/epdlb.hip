@@ -233,6 +233,10 @@ int validate(const epdlb_params* p) {
   if (!(p->D_S > 0 && p->D_A > 0 && p->D_B > 0)) return fail(EPDLB_EINVAL, "diffusion constants must be > 0");
   if (!(p->R_G > 0 && p->dx > 0 && p->dt > 0)) return fail(EPDLB_EINVAL, "R_G, dx, dt must be > 0");
   if (!(p->lb_tau > 0.5)) return fail(EPDLB_EINVAL, "lb_tau must be > 1/2");
+  if (p->lb_mrt != 0 && p->lb_mrt != 1) return fail(EPDLB_EINVAL, "lb_mrt must be 0 or 1");
+  if (p->lb_mrt == 1 && !(std::fabs(p->lb_gamma_s) < 1.0 && std::fabs(p->lb_gamma_b) < 1.0 &&
+                          std::fabs(p->lb_gamma_g) < 1.0))
+    return fail(EPDLB_EINVAL, "lb_gamma_s, lb_gamma_b, lb_gamma_g must lie in (-1, 1)");
   if (p->precision != 0 && p->precision != 1) return fail(EPDLB_EINVAL, "precision must be 0 or 1");
   if (p->g_units != 0 && p->g_units != 1) return fail(EPDLB_EINVAL, "g_units must be 0 or 1");
   if (!std::isfinite(p->g) || !std::isfinite(p->kT_over_v) || !std::isfinite(p->kappa_H) ||
@@ -259,6 +263,11 @@ std::vector<double> segment_fractions(const epdlb_params& p) {
 }
 
 double g_lattice(const epdlb_params& p) { return p.g_units ? p.g : p.g * p.dt * p.dt / p.dx; }
+
+// Lattice kinematic shear viscosity of the configured collision (rho = 1).
+double lb_nu(const epdlb_params& p) {
+  return p.lb_mrt ? (1.0 / 6.0) * (1.0 + p.lb_gamma_s) / (1.0 - p.lb_gamma_s) : (p.lb_tau - 0.5) / 3.0;
+}
 
 int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
@@ -673,11 +682,17 @@ int stage_lb(epdlb_ctx* c) {
   a.n = n;
   a.omega = T(1.0 / p.lb_tau);
   a.fpre = T(1.0 - 0.5 / p.lb_tau);
+  a.gs = T(p.lb_gamma_s);
+  a.gb = T(p.lb_gamma_b);
+  a.gg = T(p.lb_gamma_g);
   a.nrep = c->nrep;
   a.rs = long(c->rstride);
   {
     ProfScope ps(c, K_LB);
-    launch_k((k_lb<T>), dim3((n + 255) / 256, 1, c->nrep), dim3(256), 0, c->stream, a);
+    if (p.lb_mrt)
+      launch_k((k_lb<T, true>), dim3((n + 255) / 256, 1, c->nrep), dim3(256), 0, c->stream, a);
+    else
+      launch_k((k_lb<T, false>), dim3((n + 255) / 256, 1, c->nrep), dim3(256), 0, c->stream, a);
   }
   HIPCHK(hipGetLastError());
   c->fcur = 1 - c->fcur;
@@ -906,7 +921,7 @@ int init_lb(epdlb_ctx* c, int r) {
   std::vector<double> ux(p.ny, 0.0);
   if (p.init_flow) {
     const double F0 = g_lattice(p);
-    const double nu = (p.lb_tau - 0.5) / 3.0;
+    const double nu = lb_nu(p);
     const double Ly = p.ny;
     for (int y = 0; y < p.ny; ++y) {
       const double Y = y + 0.5 - Ly / 2;
@@ -1060,7 +1075,8 @@ bool same_model(const epdlb_params& a, const epdlb_params& b) {
          a.chi_BS == b.chi_BS && a.kappa_H == b.kappa_H && a.D_S == b.D_S && a.D_A == b.D_A &&
          a.D_B == b.D_B && a.R_G == b.R_G && a.dx == b.dx && a.dt == b.dt && a.kT_over_v == b.kT_over_v &&
          a.lb_tau == b.lb_tau && a.g_units == b.g_units && a.precision == b.precision &&
-         a.init_flow == b.init_flow && a.couple_lb == b.couple_lb;
+         a.init_flow == b.init_flow && a.couple_lb == b.couple_lb && a.lb_mrt == b.lb_mrt &&
+         a.lb_gamma_s == b.lb_gamma_s && a.lb_gamma_b == b.lb_gamma_b && a.lb_gamma_g == b.lb_gamma_g;
 }
 
 // A group context over `rp` (same grid shape), arena allocated here.
@@ -1206,6 +1222,8 @@ int epdlb_params_default(epdlb_params* p) {
   p->check_every = 10;
   p->resid_tol = 1e-3;
   p->err_tol = 1e-3;
+  p->lb_mrt = 0;
+  p->lb_gamma_s = p->lb_gamma_b = p->lb_gamma_g = 0.0;
   return EPDLB_OK;
 }
 

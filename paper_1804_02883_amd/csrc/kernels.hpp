@@ -785,8 +785,9 @@ template <typename T> struct LbArgs {
   T* u;            // 2 planes
   int nx, ny;
   long n;
-  T omega;         // 1/tau
-  T fpre;          // 1 - 1/(2 tau)
+  T omega;         // BGK: 1/tau
+  T fpre;          // BGK: 1 - 1/(2 tau)
+  T gs, gb, gg;    // multi-relaxation: shear, bulk and non-hydrodynamic factors
   int nrep;
   long rs;
   __device__ void shift(long o) {
@@ -794,7 +795,17 @@ template <typename T> struct LbArgs {
   }
 };
 
-template <typename T>
+// MRT = false: BGK collision with relaxation time tau and the second-order
+// force term.  MRT = true: the multi-relaxation collision in moment space
+// (moments of the deviations g = f - w, so rho - 1 and the stress minus its
+// rest value keep full precision):
+//   u = (j + F/2)/rho,  Pi_eq = rho/3 I + rho u u,  N = Pi - Pi_eq,
+//   Pi* = Pi_eq + gs (N - tr(N)/2 I) + gb tr(N)/2 I
+//         + (1 + gs)/2 [u F + F u - (u.F) I] + (1 + gb)/2 (u.F) I,
+//   f*_i = H_i(rho, j + F, Pi*) + gg (f_i - H_i(rho, j, Pi)),
+// H_i(rho, j, Pi) = w_i [rho + 3 j.c_i + 4.5 (Pi - rho/3 I):(c_i c_i - I/3)],
+// the populations that carry exactly (rho, j, Pi).
+template <typename T, bool MRT>
 __global__ void __launch_bounds__(256) k_lb(LbArgs<T> P) {
   P.shift(long(blockIdx.z) * P.rs);
   const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -827,6 +838,37 @@ __global__ void __launch_bounds__(256) k_lb(LbArgs<T> P) {
   const T usq = ux * ux + uy * uy;
   constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
   constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  if constexpr (MRT) {
+    // second moments of g: sum_i w_i c_i c_i = I/3, so Pi - rho/3 I = Sg - drho/3 I
+    const T sxx = (g[1] + g[3]) + ((g[5] + g[6]) + (g[7] + g[8]));
+    const T syy = (g[2] + g[4]) + ((g[5] + g[6]) + (g[7] + g[8]));
+    const T sxy = (g[5] - g[6]) + (g[7] - g[8]);
+    const T third = T(1.0 / 3.0);
+    // A = Pi - rho/3 I (pre-collision), B = Pi* - rho/3 I (post-collision)
+    const T axx = sxx - third * drho, ayy = syy - third * drho, axy = sxy;
+    const T nxx = axx - rho * ux * ux, nyy = ayy - rho * uy * uy, nxy = axy - rho * ux * uy;
+    const T htr = T(0.5) * (nxx + nyy);
+    const T uF = ux * Fx + uy * Fy;
+    const T cs_ = T(0.5) * (T(1) + P.gs), cb_ = T(0.5) * (T(1) + P.gb);
+    const T bxx = rho * ux * ux + P.gs * (nxx - htr) + P.gb * htr + cs_ * (T(2) * ux * Fx - uF) + cb_ * uF;
+    const T byy = rho * uy * uy + P.gs * (nyy - htr) + P.gb * htr + cs_ * (T(2) * uy * Fy - uF) + cb_ * uF;
+    const T bxy = rho * ux * uy + P.gs * nxy + cs_ * (ux * Fy + uy * Fx);
+    const T jxs = jx + Fx, jys = jy + Fy;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const T w = k == 0 ? T(4.0 / 9.0) : (k < 5 ? T(1.0 / 9.0) : T(1.0 / 36.0));
+      const T qx = T(cx[k] * cx[k]) - third, qy = T(cy[k] * cy[k]) - third, qxy = T(2 * cx[k] * cy[k]);
+      const T hpost = w * (drho + T(3) * (T(cx[k]) * jxs + T(cy[k]) * jys) +
+                           T(4.5) * (bxx * qx + byy * qy + bxy * qxy));
+      const T hpre = w * (drho + T(3) * (T(cx[k]) * jx + T(cy[k]) * jy) +
+                          T(4.5) * (axx * qx + ayy * qy + axy * qxy));
+      P.fout[k * P.n + i] = hpost + P.gg * (g[k] - hpre);
+    }
+    P.rho[i] = rho;
+    P.u[i] = ux;
+    P.u[P.n + i] = uy;
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
     const T w = k == 0 ? T(4.0 / 9.0) : (k < 5 ? T(1.0 / 9.0) : T(1.0 / 36.0));

@@ -53,11 +53,16 @@ def test_defaults_and_validation():
     assert B.epdlb_validate(p) == 0
     assert (p.density_mode, p.fallback_every, p.check_every, p.resid_tol, p.err_tol) == (0, 50, 10, 1e-3, 1e-3)
     assert B.epdlb_validate(B.make_params(density_mode=1)) == 0
+    assert (p.lb_mrt, p.lb_gamma_s, p.lb_gamma_b, p.lb_gamma_g) == (0, 0.0, 0.0, 0.0)
+    gs, gb = B.mrt_gammas(1.0, 1.0)  # the paper's eta = eta_B at its dx, dt
+    assert abs(gs + 0.8050541516245486) < 1e-15 and gs == gb
+    assert B.epdlb_validate(B.make_params(lb_mrt=1, lb_gamma_s=gs, lb_gamma_b=gb, lb_gamma_g=0.5)) == 0
     for bad in [dict(nx=48), dict(nx=16), dict(ny=8), dict(n_contour=1), dict(f_A=1.0),
                 dict(phi_P=0.0), dict(lb_tau=0.5), dict(precision=2), dict(abi_version=7),
                 dict(g=float("nan")), dict(density_mode=2), dict(density_mode=1, fallback_every=0),
                 dict(density_mode=1, check_every=0), dict(density_mode=1, resid_tol=0.0),
-                dict(density_mode=1, err_tol=-1.0)]:
+                dict(density_mode=1, err_tol=-1.0), dict(lb_mrt=2), dict(lb_mrt=1, lb_gamma_s=1.0),
+                dict(lb_mrt=1, lb_gamma_b=-1.0), dict(lb_mrt=1, lb_gamma_g=float("nan"))]:
         q = B.make_params(**bad)
         assert B.epdlb_validate(q) == B.EPDLB_EINVAL, bad
         assert B.epdlb_last_error() != ""
@@ -103,3 +108,15 @@ def test_trainer_create_rejects_bad_sizes_before_device_calls():
         with pytest.raises(B.EpdlbError) as e:
             B.epdlb_nn_create(nx, ny, cap, mb)
         assert e.value.code == B.EPDLB_EINVAL, (nx, ny, cap, mb)
+
+
+def test_batch_rejects_mixed_collision_models_before_device_calls():
+    # replicas of one batch share the model: a BGK and a multi-relaxation replica
+    # (or two different gamma sets) are refused before any HIP call
+    a = B.make_params(nx=64, ny=64)
+    m = B.make_params(nx=64, ny=64, lb_mrt=1, lb_gamma_s=-0.5, lb_gamma_b=-0.5)
+    m2 = B.make_params(nx=64, ny=64, lb_mrt=1, lb_gamma_s=-0.5, lb_gamma_b=0.1)
+    for pair in ([a, m], [m, m2]):
+        with pytest.raises(B.EpdlbError) as e:
+            B.epdlb_batch_create(pair)
+        assert e.value.code == B.EPDLB_EINVAL

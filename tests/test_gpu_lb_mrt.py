@@ -1,0 +1,158 @@
+"""GPU parity of the multi-relaxation LB collision (Sec. II; reading R15)
+through the C ABI, against the FP64 oracle.
+
+Bars as for the BGK collision: one collision on a random state FP64 <= 1e-13,
+FP32 <= 1e-6 (relative to the largest population); full FP64 hybrid steps
+<= 1e-10; FP32 densities <= 1e-4.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import epdlb_oracle as O
+from seeded_inputs import initial_omega, preset
+from seeded_inputs.presets import base_params
+
+pytestmark = pytest.mark.gpu
+
+# the paper's eta = eta_B = 1 R_G^2/tau rho at dx = R_G/3, dt = 0.002 tau
+PAPER = dict(lb_mrt=1, lb_gamma_s=-0.8050541516245486, lb_gamma_b=-0.8050541516245486, lb_gamma_g=0.0)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _sim(p):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1804_02883_amd import Simulation
+    return Simulation(p)
+
+
+def rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _random_state(p, seed):
+    rng = np.random.default_rng(seed)
+    ny, nx = p["ny"], p["nx"]
+    phi = np.stack([np.full((ny, nx), v) for v in (0.05, 0.05, 0.9)]) + 0.01 * rng.standard_normal((3, ny, nx))
+    w = 0.2 * rng.standard_normal((3, ny, nx))
+    u = 0.05 * rng.standard_normal((2, ny, nx))
+    rho = 1 + 0.01 * rng.standard_normal((ny, nx))
+    f = O.lb_equilibrium(rho, u) * (1 + 0.01 * rng.standard_normal((9, ny, nx)))
+    return phi, w, u, f
+
+
+@pytest.mark.parametrize("nx,ny,prec,gs,gb,gg", [
+    (32, 16, 0, -0.8050541516245486, -0.8050541516245486, 0.0),
+    (64, 64, 0, -0.5, 0.3, 0.4),
+    (32, 32, 0, 0.2, -0.6, -0.3),
+    (256, 128, 1, -0.8050541516245486, 0.2, 0.0),
+    (1024, 16, 1, -0.3, -0.3, 0.5),
+])
+def test_stage_lb_mrt(nx, ny, prec, gs, gb, gg):
+    say(f"[lb mrt] {nx}x{ny} prec={prec} gammas=({gs}, {gb}, {gg})")
+    from paper_1804_02883_amd import EPDLB_STAGE_LB, EPDLB_AUX_FORCE
+    p = preset("cfg1", nx=nx, ny=ny, precision=prec, lb_mrt=1, lb_gamma_s=gs, lb_gamma_b=gb, lb_gamma_g=gg)
+    phi, w, u, f = _random_state(p, nx + 3 * ny)
+    rng = np.random.default_rng(7)
+    F = 1e-4 * rng.standard_normal((2, ny, nx))
+    sim = _sim(p)
+    sim.set_state(w, phi, f, u)
+    sim.write_aux(EPDLB_AUX_FORCE, F)
+    sim.run_stage(EPDLB_STAGE_LB)
+    fo = sim.populations()
+    rho, ug = sim.velocity()
+    ref, rho_r, u_r = O.lb_step_mrt(f, F, gs, gb, gg)
+    bar = 1e-13 if prec == 0 else 1e-6
+    assert rel(fo, ref) < bar
+    assert rel(rho, rho_r) < bar
+    assert np.max(np.abs(ug - u_r)) < (1e-15 if prec == 0 else 1e-7)
+    sim.close()
+
+
+def test_full_run_fp64_paper_viscosity():
+    """32x32, FP64, N = 16 with the paper's eta = eta_B (gamma = -0.805): 100 hybrid steps
+    from the seeded noise and the analytic start-up flow at the matching viscosity."""
+    say("[cfg1 mrt] 100 steps FP64")
+    p = preset("cfg1", **PAPER)
+    w0 = initial_omega(32, 32, 1001, 1e-3)
+    sim = _sim(p)
+    sim.set_fields(w0)
+    s = O.init_state(p, w0)
+    rho, u = sim.velocity()
+    assert np.max(np.abs(u - s["u"])) < 1e-14 * max(np.max(np.abs(s["u"])), 1e-30) + 1e-18
+    for chunk in (1, 9, 90):
+        sim.step(chunk)
+        for _ in range(chunk):
+            s = O.step(s, p)
+        sim.sync()
+        phi = sim.densities()
+        rho, u = sim.velocity()
+        for I in range(3):
+            assert rel(phi[I], s["phi"][I]) < 1e-10, (chunk, I)
+        for k in range(2):
+            assert np.max(np.abs(u[k] - s["u"][k])) < 1e-10 * np.max(np.abs(s["u"][0])) + 1e-14, (chunk, k)
+        assert rel(sim.populations(), s["fstar"]) < 1e-12
+    sim.close()
+
+
+def test_fp32_256_steps_vs_oracle_mrt():
+    """256x256, FP32, N = 32, reading Q, unequal gammas: densities after 1 and 10 steps <= 1e-4."""
+    say("[cfg2-shape mrt] FP32")
+    p = dict(base_params(256, 256, 32, 0.5, 0.1, "Q", 1e-5, precision=1),
+             lb_mrt=1, lb_gamma_s=-0.8050541516245486, lb_gamma_b=0.3, lb_gamma_g=0.0)
+    w0 = initial_omega(256, 256, 1002, 1e-3)
+    sim = _sim(p)
+    sim.set_fields(w0)
+    s = O.init_state(p, w0)
+    done = 0
+    for target in (1, 10):
+        sim.step(target - done)
+        for _ in range(target - done):
+            s = O.step(s, p)
+        done = target
+        sim.sync()
+        phi = sim.densities()
+        rho, u = sim.velocity()
+        for I in range(3):
+            assert rel(phi[I], s["phi"][I]) < 1e-4, (target, I)
+        # u follows the force, built from S: the diffusive change of a step (~1e-6 here)
+        # taken as a difference of O(0.1) densities, which FP32 carries to about
+        # 6e-8 * 0.1 / 1e-6 = 6e-3 relative; the FP64 run above checks u to 1e-10
+        assert np.max(np.abs(u - s["u"])) < 2e-2 * np.max(np.abs(s["u"])), target
+    sim.close()
+
+
+def test_batch_mrt_equals_single_runs_bitwise():
+    """A batch of multi-relaxation replicas with different grids, drives and A
+    fractions (two groups): each replica equals the same replica run alone, bit for bit."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1804_02883_amd import Batch, Simulation
+    params = [dict(base_params(64, 64, 32, 0.5, 0.1, "L", 2e-5), **PAPER),
+              dict(base_params(64, 64, 32, 0.5, 0.1, "L", 4e-5), **PAPER),
+              dict(base_params(128, 64, 32, 0.3, 0.1, "L", 3e-5), **PAPER)]
+    seeds = [21, 22, 23]
+    say("[batch mrt] 3 replicas")
+    b = Batch(params)
+    b.seed(seeds, 1e-3)
+    b.step(6)
+    b.sync()
+    for r, p in enumerate(params):
+        sim = Simulation(p)
+        sim.seed(seeds[r], 1e-3)
+        sim.step(6)
+        sim.sync()
+        assert np.array_equal(b.densities(r), sim.densities()), r
+        rb, ub = b.velocity(r)
+        rs, us = sim.velocity()
+        assert np.array_equal(ub, us), r
+        sim.close()
+    b.close()
