@@ -171,13 +171,20 @@ def plain_line(args, workload):
     else:
         cfg = PRESETS[workload]
         p = dict(cfg["params"])
+        lb_note = "BGK tau=%g" % p["lb_tau"]
+        if getattr(args, "lb", "bgk") == "mrt":
+            # the paper's fluid: eta = eta_B = 1 R_G^2/tau rho (Sec. III) at this dx, dt
+            from paper_1804_02883_amd import mrt_gammas
+            gs, gb = mrt_gammas(1.0, 1.0, 1.0, p["dx"], p["dt"])
+            p.update(lb_mrt=1, lb_gamma_s=gs, lb_gamma_b=gb, lb_gamma_g=0.0)
+            lb_note = "multi-relaxation, eta = eta_B = 1 (gamma_s = gamma_b = %.4f, gamma_g = 0)" % gs
         n = p["nx"] * p["ny"]
         sim = Simulation(p)
         sim.seed(cfg["seed"], cfg["sigma"])
         shapes = sim.shapes() if args.no_tune else sim.autotune(20, args.tune_cache)
         wl = (f"{workload}: {cfg['name']}, g={p['g']}, "
               f"seed {cfg['seed']} noise sigma {cfg['sigma']}, plain (exact propagator)")
-        cfgd = dict(workload=wl, nx=p["nx"], ny=p["ny"], n_contour=p["n_contour"], path="plain")
+        cfgd = dict(workload=wl, nx=p["nx"], ny=p["ny"], n_contour=p["n_contour"], path="plain", lb=lb_note)
     N = p["n_contour"]
     P = 8 if p["precision"] == 0 else 4
     steps = args.steps if args.steps_given else 2000
@@ -245,6 +252,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1804_02883_amd", "tune", "gfx950.txt"),
                     help="autotuner results file (read first, new results appended)")
+    ap.add_argument("--lb", default="bgk", choices=["bgk", "mrt"],
+                    help="LB collision of the plain single-grid workloads: BGK at the preset's tau, or "
+                         "the multi-relaxation collision at the paper's eta = eta_B")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the secondary comparison on the line (the 1024x512 plain run for cfg5q, "
                          "the cfg5q plain vs surrogate run otherwise)")

@@ -40,7 +40,7 @@ READINGS = {
     "R13": "Lattice force F = f dt^2/dx with rho_0 = 1; g in units f* = rho R_G tau^-2.",
     "R14": "Gauge: omega_I shifted by constants c_I inside the propagator "
            "(densities are invariant under such shifts).",
-    "R15": "Multi-relaxation LB (lb_mrt = 1): collision in moment space; the traceless "
+    "R17": "Multi-relaxation LB (lb_mrt = 1): collision in moment space; the traceless "
            "non-equilibrium stress is scaled by gamma_s, its trace by gamma_b, the three "
            "non-hydrodynamic modes by gamma_g (not stated in the paper; default 0). The "
            "forcing stress Sigma of Eq. force_col uses the trace split of d = 2 "
@@ -376,7 +376,7 @@ def lb_hermite(rho, j, Pi):
 
 
 def lb_collide_mrt(f, F, gamma_s, gamma_b, gamma_g):
-    """Multi-relaxation collision with the force term of Eq. force_col (reading R15).
+    """Multi-relaxation collision with the force term of Eq. force_col (reading R17).
 
     u = (j + F/2)/rho; Pi_eq = rho c_s^2 I + rho u u; the non-equilibrium stress
     Pi - Pi_eq keeps gamma_s of its traceless part and gamma_b of its trace;

@@ -1,4 +1,4 @@
-"""GPU parity of the multi-relaxation LB collision (Sec. II; reading R15)
+"""GPU parity of the multi-relaxation LB collision (Sec. II; reading R17)
 through the C ABI, against the FP64 oracle.
 
 Bars as for the BGK collision: one collision on a random state FP64 <= 1e-13,

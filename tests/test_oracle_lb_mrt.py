@@ -1,6 +1,6 @@
 """Pins of the oracle's multi-relaxation LB (Sec. II: the collision with
 relaxation parameters gamma_s, gamma_b, the force term of Eq. force_col and
-the viscosity relations; reading R15)."""
+the viscosity relations; reading R17)."""
 import numpy as np
 import pytest
 
@@ -70,7 +70,7 @@ def test_uniform_acceleration_stress_first_order_in_F():
     """A uniform fluid under a uniform force: after a collision the stress equals the
     equilibrium stress of the new momentum up to O(F^2), for unequal gamma_s and
     gamma_b.  This is what the force's stress term is for; it holds with the d = 2
-    trace split of reading R15 (the d = 3 factors leave a term linear in F)."""
+    trace split of reading R17 (the d = 3 factors leave a term linear in F)."""
     shape = (1, 1)
     j0 = np.array([0.02, -0.01]).reshape(2, 1, 1)
     rho = np.ones(shape)
