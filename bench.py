@@ -66,6 +66,39 @@ def measured_traffic(workload, fam):
     return None
 
 
+HBM_PEAK_GBS = 8000.0
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense
+WEIGHTS = os.path.join(ROOT, "paper_1804_02883_amd", "weights", "surrogate_q.npy")
+# useful flops per site of each network launch (multiply-add = 2 flops):
+# 9 taps x cin x cout x 2; conv0 has 5 real input channels, the output layer 2
+NN_FLOPS_PER_SITE = {"nn_conv0": 9 * 5 * 64 * 2, "nn_conv": 9 * 64 * 64 * 2}
+
+# Algorithmic bytes per site per hybrid STEP of each kernel family, in units
+# of the element size P (forward and backward chains counted together):
+#   advect_update : read Phi 3, omega 3, u 2; write omega 3, S~ 1        = 12P
+#   boltzmann     : read omega_A, omega_B; write their half-step factors =  4P
+#   prop_row/col  : per chain, the first launch reads a factor plane and
+#                   writes the scratch plane (2P); a fused boundary launch
+#                   reads scratch + factor and writes q_{a+1} + scratch (4P);
+#                   the last reads scratch + factor and writes q_N (3P)
+#   density       : read 2N chain planes + omega_S + S~, write Phi 3 + S = (2N + 6)P
+#   force_*       : 3P + 4P + 4P (row FFT of S, column pass, row inverse)
+#   lb            : read 9 populations + F 2; write 9 + rho + u 2        = 23P
+def step_bytes_per_site(kind, N, P):
+    last_row = (N - 1) % 2 == 1           # the final propagator launch is x-oriented
+    n_fused_row = sum(1 for s in range(N - 1) if s % 2 == 1)
+    n_fused_col = sum(1 for s in range(N - 1) if s % 2 == 0)
+    per_chain_row = 2 + 4 * n_fused_row + (3 if last_row else 0)
+    per_chain_col = 4 * n_fused_col + (0 if last_row else 3)
+    return {
+        "advect_update": 12 * P, "boltzmann": 4 * P,
+        "prop_row": 2 * per_chain_row * P, "prop_col": 2 * per_chain_col * P,
+        "density": (2 * N + 6) * P,
+        "force_row_fwd": 3 * P, "force_col": 4 * P, "force_row_inv": 4 * P,
+        "lb": 23 * P,
+    }.get(kind)
+
+
 def cpu_baseline(preset_name, seconds):
     """The oracle's plain hybrid step on the host: whole steps until `seconds` have passed."""
     import numpy as np  # noqa: F401
