@@ -43,12 +43,13 @@ METRIC = "lattice site-updates/s per hybrid step, plain vs surrogate at <=1e-3 d
 _PROP_FILES = ("fft.hpp", "kernels.hpp")
 _NN_FILES = ("kernels.hpp", "nn.hpp")
 MEASURED_TRAFFIC = {
-    ("cfg3", "prop_col"): dict(bytes_per_launch=17276403, files=_PROP_FILES,
-                               source_sha256="10ae0a2d916a3544bcd02bdfeda6f9c63cbe834a83619ba725a494246dc16193"),
-    ("cfg3", "prop_row"): dict(bytes_per_launch=16033181, files=_PROP_FILES,
-                               source_sha256="10ae0a2d916a3544bcd02bdfeda6f9c63cbe834a83619ba725a494246dc16193"),
+    ("cfg3", "prop_col"): dict(bytes_per_launch=17277052, files=_PROP_FILES,
+                               source_sha256="ee0abf9a2afb06b4113b1e020cbd83ef37b0b422a17353386528cb244d97770a"),
+    ("cfg3", "prop_row"): dict(bytes_per_launch=16033716, files=_PROP_FILES,
+                               source_sha256="ee0abf9a2afb06b4113b1e020cbd83ef37b0b422a17353386528cb244d97770a"),
     # mean over the two 64 -> 64 launches of a surrogate step
-    ("cfg5q", "nn_conv"): dict(bytes_per_launch=63954944, files=_NN_FILES, source_sha256="57fdad948ceeb4b2c773626518c7436a1a2c9ec88920e8fdd0199dae65745846"),
+    ("cfg5q", "nn_conv"): dict(bytes_per_launch=63956971, files=_NN_FILES,
+                               source_sha256="e824ea993e56df05c99da17f3d8a591609a20d013459db82cb6df84c3a511944"),
 }
 
 

@@ -1,0 +1,43 @@
+"""Host-side checks of bench.py (no GPU): the byte model, the traffic table and
+the refusal of several GPUs."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_step_byte_model_totals():
+    """Per-family algorithmic bytes per site and step add up to (10N + 58)P."""
+    fams = ["advect_update", "boltzmann", "prop_row", "prop_col", "density",
+            "force_row_fwd", "force_col", "force_row_inv", "lb"]
+    for N in (16, 32, 64):
+        for P in (4, 8):
+            total = sum(bench.step_bytes_per_site(k, N, P) for k in fams)
+            assert total == (10 * N + 58) * P, (N, P)
+    assert bench.step_bytes_per_site("lb", 32, 4) == 92
+    assert bench.step_bytes_per_site("nn_conv", 32, 4) is None
+
+
+def test_measured_traffic_entries_match_sources():
+    """Every traffic entry names existing kernel sources; the current sources hash to
+    the recorded value (a kernel change must re-measure or drop the entry)."""
+    for key, tr in bench.MEASURED_TRAFFIC.items():
+        assert tr["bytes_per_launch"] > 0
+        assert bench.kernel_source_sha256(tr["files"]) == tr["source_sha256"], key
+        assert bench.measured_traffic(*key) == tr["bytes_per_launch"]
+    assert bench.measured_traffic("cfg3", "lb") is None
+
+
+def test_peaks_and_flop_model():
+    assert bench.HBM_PEAK_GBS == 8000.0 and bench.BF16_MFMA_PEAK_TFLOPS == 2500.0
+    assert bench.NN_FLOPS_PER_SITE["nn_conv"] == 73728
+    assert os.path.exists(bench.WEIGHTS)
+
+
+def test_several_gpus_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
