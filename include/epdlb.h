@@ -99,6 +99,28 @@ typedef struct {
   double lb_gamma_s, lb_gamma_b, lb_gamma_g; /* defaults 0 */
 } epdlb_params;
 
+/* Observables of the current densities (Sec. III and IV).  Phi_P = Phi_A +
+ * Phi_B is formed in the storage precision; sums are FP64. */
+typedef struct {
+  double sigma;          /* (1/V) sum |Phi_P - phi_P| (Sec. III, mixing measure sigma(t)) */
+  double y2p;            /* Eq. width: sqrt(sum_y y^2 <Phi_P>_x / (phi_P sum_y y^2)), y = row + 1/2 - ny/2 */
+  int32_t n_particles;   /* connected clusters of sites with Phi_P >= threshold (Sec. IV) */
+  int32_t n_wrapping;    /* of which reach half the box in x or y */
+} epdlb_obs;
+
+/* One particle: sites with Phi_P >= threshold connected through nearest
+ * neighbours on the periodic grid. */
+typedef struct {
+  int32_t label;         /* lowest flat site index y * nx + x of the particle */
+  int32_t area;          /* number of sites */
+  int32_t wraps;         /* 1: offsets from the label site reach half the box (tensor not meaningful) */
+  int32_t pad;
+  double content;        /* N = sum of Phi_P over the sites */
+  double cx, cy;         /* Phi_P-weighted centroid, in site units inside the box */
+  double gxx, gxy, gyy;  /* Eq. gyration_tensor, positions as minimum-image offsets from the label site */
+  double R, c_rel;       /* Eq. asph R = sqrt(lambda_+ + lambda_-), Eq. rel_asph c_rel = c^2 / R^4 (0 if R = 0) */
+} epdlb_particle;
+
 /* Scalars maintained on the device (FP64). */
 typedef struct {
   int64_t step;          /* hybrid steps taken since seeding */
@@ -204,6 +226,23 @@ int epdlb_read_populations(epdlb_ctx* ctx, double* fstar /* 9*nx*ny */);
 int epdlb_read_aux(epdlb_ctx* ctx, int32_t which, double* out);
 int epdlb_write_aux(epdlb_ctx* ctx, int32_t which, const double* in);
 int epdlb_read_diag(epdlb_ctx* ctx, epdlb_diag* d);
+
+/* Observables of the current densities (after seed/set_fields/set_state and
+ * any steps; stream-ordered, synchronises the context's stream).
+ * threshold: particle threshold on Phi_P (the paper's 0.5).  particles: host
+ * array of max_particles entries (may be NULL when max_particles = 0); the
+ * first min(n_particles, max_particles) particles in increasing label order
+ * are written.  labels: NULL or a host int32 array of nx * ny ([y][x]): the
+ * particle label of each site, -1 off the particles.  The first call
+ * allocates device scratch of about 100 bytes per site, held until destroy.
+ * EINVAL on a bad argument, ESTATE before any state. */
+int epdlb_observables(epdlb_ctx* c, double threshold, epdlb_obs* out, epdlb_particle* particles,
+                      int32_t max_particles, int32_t* labels);
+
+/* sigma_Delta (Sec. III): (1/V) sum |Phi_P^a - Phi_P^b| over two contexts on
+ * the same device with the same grid and precision (e.g. runs with and
+ * without LB coupling from the same start).  Synchronises both streams. */
+int epdlb_sigma_delta(epdlb_ctx* a, epdlb_ctx* b, double* out);
 
 /* Launch shape of one FFT pass family: R values per lane, nf transforms per
  * block, and the time per launch the autotuner measured (0 if not tuned). */

@@ -89,6 +89,18 @@ class epdlb_dev_views(ctypes.Structure):
                 ("rho", ctypes.c_void_p), ("u", ctypes.c_void_p)]
 
 
+class epdlb_obs(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_double), ("y2p", ctypes.c_double),
+                ("n_particles", ctypes.c_int32), ("n_wrapping", ctypes.c_int32)]
+
+
+class epdlb_particle(ctypes.Structure):
+    _fields_ = [("label", ctypes.c_int32), ("area", ctypes.c_int32), ("wraps", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("content", ctypes.c_double), ("cx", ctypes.c_double),
+                ("cy", ctypes.c_double), ("gxx", ctypes.c_double), ("gxy", ctypes.c_double),
+                ("gyy", ctypes.c_double), ("R", ctypes.c_double), ("c_rel", ctypes.c_double)]
+
+
 class EpdlbError(RuntimeError):
     def __init__(self, code, fn, msg):
         super().__init__(f"{fn} failed ({code}): {msg}")
@@ -160,6 +172,9 @@ SIGNATURES = {
     "epdlb_nn_last_loss": (ctypes.c_int, [_vp, _dp, _dp]),
     "epdlb_nn_predict": (ctypes.c_int, [_vp, ctypes.c_int32, _dp]),
     "epdlb_nn_destroy": (None, [_vp]),
+    "epdlb_observables": (ctypes.c_int, [_vp, ctypes.c_double, _P(epdlb_obs), _P(epdlb_particle), ctypes.c_int32,
+                                         _P(ctypes.c_int32)]),
+    "epdlb_sigma_delta": (ctypes.c_int, [_vp, _vp, _dp]),
     "epdlb_last_error": (ctypes.c_char_p, []),
 }
 
@@ -338,6 +353,33 @@ def epdlb_read_diag(ctx):
     return _diag_dict(d)
 
 
+def epdlb_observables(ctx, threshold, max_particles, shape=None):
+    """(dict of sigma, y2p, n_particles, n_wrapping; list of particle dicts in label
+    order; labels [ny, nx] int32 or None).  Labels are returned when `shape` is given."""
+    import numpy as np
+    o = epdlb_obs()
+    arr = (epdlb_particle * max_particles)() if max_particles > 0 else None
+    lab = None
+    lab_ptr = None
+    if shape is not None:
+        lab = np.empty(shape, dtype=np.int32)
+        lab_ptr = lab.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    _check(load_library().epdlb_observables(ctx, threshold, ctypes.byref(o), arr, max_particles, lab_ptr),
+           "epdlb_observables")
+    parts = []
+    for k in range(min(o.n_particles, max_particles)):
+        q = arr[k]
+        parts.append(dict(label=q.label, area=q.area, wraps=bool(q.wraps), content=q.content,
+                          centroid=(q.cx, q.cy), G=(q.gxx, q.gxy, q.gyy), R=q.R, c_rel=q.c_rel))
+    return dict(sigma=o.sigma, y2p=o.y2p, n_particles=o.n_particles, n_wrapping=o.n_wrapping), parts, lab
+
+
+def epdlb_sigma_delta(ctx_a, ctx_b):
+    v = ctypes.c_double(0.0)
+    _check(load_library().epdlb_sigma_delta(ctx_a, ctx_b, ctypes.byref(v)), "epdlb_sigma_delta")
+    return v.value
+
+
 def _diag_dict(d):
     return dict(step=d.step, Q_P=d.Q_P, Q_P_bwd=d.Q_P_bwd, Q_S=d.Q_S, gauge_S=d.gauge_S,
                 mean_omega=tuple(d.mean_omega), n_exact=d.n_exact, n_triggered=d.n_triggered,
@@ -464,6 +506,14 @@ class Simulation:
 
     def diag(self):
         return epdlb_read_diag(self.ctx)
+
+    def observables(self, threshold=0.5, max_particles=4096, labels=False):
+        """sigma, Y_2^P and the particles of the current densities (Sec. III, IV)."""
+        return epdlb_observables(self.ctx, threshold, max_particles, self.shape if labels else None)
+
+    def sigma_delta(self, other):
+        """sigma_Delta between this run's and another run's polymer densities (Sec. III)."""
+        return epdlb_sigma_delta(self.ctx, other.ctx)
 
     def autotune(self, reps=20, cache_path=None):
         epdlb_autotune(self.ctx, reps, cache_path)

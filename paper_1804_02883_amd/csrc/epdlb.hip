@@ -15,6 +15,7 @@
 #include "epdlb.h"
 #include "kernels.hpp"
 #include "nn.hpp"
+#include "obs.hpp"
 
 using namespace epdlb;
 
@@ -167,6 +168,8 @@ struct epdlb_ctx {
   hipEvent_t snap_ev = nullptr;
   bool snap_pending = false;
   int64_t snap_exact = 0;     // exact steps taken when the snapshot was queued
+  // observables scratch, allocated at the first epdlb_observables call
+  unsigned char* obs = nullptr;
   template <typename T> T* ptr(size_t off) const { return reinterpret_cast<T*>(base + off); }
 };
 
@@ -1496,6 +1499,162 @@ int epdlb_write_aux(epdlb_ctx* c, int32_t which, const double* in) {
   return upload(c, off, in, planes * size_t(c->p.nx) * c->p.ny);
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Observables (Sec. III, IV)
+// ---------------------------------------------------------------------------
+namespace {
+
+// Scratch layout: labels, areas, wrap flags, counter (int32), per-site sums
+// (6 doubles), particle list (n/2 + 1 entries), block partials.
+struct ObsLayout {
+  size_t labels, area, wrap, count, sums, list, part, total;
+  int cap, nblocks;
+};
+ObsLayout obs_layout(long n) {
+  auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
+  ObsLayout o{};
+  o.nblocks = int((n + 255) / 256);
+  o.cap = int(n / 2 + 1);
+  size_t off = 0;
+  o.labels = off; off = up(off + 4 * size_t(n));
+  o.area = off; off = up(off + 4 * size_t(n));
+  o.wrap = off; off = up(off + 4 * size_t(n));
+  o.count = off; off = up(off + 4);
+  o.sums = off; off = up(off + 48 * size_t(n));
+  o.list = off; off = up(off + sizeof(obs::Particle) * size_t(o.cap));
+  o.part = off; off = up(off + 16 * size_t(o.nblocks));
+  o.total = off;
+  return o;
+}
+
+template <typename T>
+int observables_t(epdlb_ctx* c, double thr, epdlb_obs* out, epdlb_particle* particles, int max_particles,
+                  int32_t* labels) {
+  const epdlb_params& p = c->p;
+  const long n = long(p.nx) * p.ny;
+  const ObsLayout o = obs_layout(n);
+  if (!c->obs) {
+    void* m = nullptr;
+    if (hipMalloc(&m, o.total) != hipSuccess) return fail(EPDLB_ENOMEM, "observables scratch allocation failed");
+    c->obs = static_cast<unsigned char*>(m);
+  }
+  unsigned char* b = c->obs;
+  int* L = reinterpret_cast<int*>(b + o.labels);
+  int* area = reinterpret_cast<int*>(b + o.area);
+  int* wrap = reinterpret_cast<int*>(b + o.wrap);
+  int* count = reinterpret_cast<int*>(b + o.count);
+  double* sums = reinterpret_cast<double*>(b + o.sums);
+  obs::Particle* list = reinterpret_cast<obs::Particle*>(b + o.list);
+  double* part = reinterpret_cast<double*>(b + o.part);
+  const T* phi = c->ptr<T>(c->L.phi);
+  hipStream_t s = c->stream;
+  const dim3 grid(unsigned(o.nblocks)), blk(256);
+  HIPCHK(hipMemsetAsync(area, 0, 4 * size_t(n), s));
+  HIPCHK(hipMemsetAsync(wrap, 0, 4 * size_t(n), s));
+  HIPCHK(hipMemsetAsync(count, 0, 4, s));
+  HIPCHK(hipMemsetAsync(sums, 0, 48 * size_t(n), s));
+  hipLaunchKernelGGL(obs::k_obs_init<T>, grid, blk, 0, s, phi, n, p.nx, p.ny, thr, p.phi_P, L, part);
+  hipLaunchKernelGGL(obs::k_ccl_merge, grid, blk, 0, s, L, n, p.nx, p.ny);
+  hipLaunchKernelGGL(obs::k_ccl_compress, grid, blk, 0, s, L, n);
+  hipLaunchKernelGGL(obs::k_particle_accum<T>, grid, blk, 0, s, phi, (const int*)L, n, p.nx, p.ny, area, sums, wrap);
+  hipLaunchKernelGGL(obs::k_particle_list, grid, blk, 0, s, (const int*)L, (const int*)area, (const double*)sums,
+                     (const int*)wrap, n, p.nx, p.ny, count, list, o.cap);
+  HIPCHK(hipGetLastError());
+  std::vector<double> hp(2 * size_t(o.nblocks));
+  int cnt = 0;
+  HIPCHK(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&cnt, count, 4, hipMemcpyDeviceToHost, s));
+  if (labels) HIPCHK(hipMemcpyAsync(labels, L, 4 * size_t(n), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (cnt < 0 || cnt > o.cap) return fail(EPDLB_EHIP, "particle count out of range");
+  std::vector<obs::Particle> hl(static_cast<size_t>(cnt));
+  if (cnt) {
+    HIPCHK(hipMemcpyAsync(hl.data(), list, sizeof(obs::Particle) * size_t(cnt), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  std::sort(hl.begin(), hl.end(), [](const obs::Particle& x, const obs::Particle& y) { return x.label < y.label; });
+  // block partials in block order: deterministic sums
+  double ssum = 0.0, msum = 0.0;
+  for (int k = 0; k < o.nblocks; ++k) {
+    ssum += hp[2 * size_t(k)];
+    msum += hp[2 * size_t(k) + 1];
+  }
+  const double ny = p.ny;
+  const double y2sum = (ny * ny * ny - ny) / 12.0;  // sum over rows of (row + 1/2 - ny/2)^2
+  out->sigma = ssum / double(n);
+  out->y2p = std::sqrt(msum / (double(p.nx) * p.phi_P * y2sum));
+  out->n_particles = cnt;
+  int nw = 0;
+  for (const auto& q : hl) nw += q.wraps ? 1 : 0;
+  out->n_wrapping = nw;
+  const int m = std::min(cnt, max_particles);
+  for (int k = 0; k < m; ++k) {
+    const obs::Particle& q = hl[size_t(k)];
+    epdlb_particle& r = particles[k];
+    r.label = q.label;
+    r.area = q.area;
+    r.wraps = q.wraps;
+    r.pad = 0;
+    r.content = q.content;
+    r.cx = q.cx;
+    r.cy = q.cy;
+    r.gxx = q.gxx;
+    r.gxy = q.gxy;
+    r.gyy = q.gyy;
+    r.R = q.R;
+    r.c_rel = q.c_rel;
+  }
+  return EPDLB_OK;
+}
+
+template <typename T>
+int sigma_delta_t(epdlb_ctx* a, epdlb_ctx* b, double* out) {
+  const long n = long(a->p.nx) * a->p.ny;
+  const int nblocks = int((n + 255) / 256);
+  HIPCHK(hipStreamSynchronize(b->stream));
+  void* m = nullptr;
+  if (hipMalloc(&m, 16 * size_t(nblocks)) != hipSuccess) return fail(EPDLB_ENOMEM, "sigma_delta scratch allocation failed");
+  double* part = static_cast<double*>(m);
+  hipLaunchKernelGGL(obs::k_sigma_delta<T>, dim3(unsigned(nblocks)), dim3(256), 0, a->stream,
+                     (const T*)a->ptr<T>(a->L.phi), (const T*)b->ptr<T>(b->L.phi), n, part);
+  std::vector<double> hp(2 * size_t(nblocks));
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, a->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(a->stream);
+  (void)hipFree(m);
+  if (e != hipSuccess) return fail(EPDLB_EHIP, std::string("sigma_delta: ") + hipGetErrorString(e));
+  double sum = 0.0;
+  for (int k = 0; k < nblocks; ++k) sum += hp[2 * size_t(k)];
+  *out = sum / double(n);
+  return EPDLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int epdlb_observables(epdlb_ctx* c, double threshold, epdlb_obs* out, epdlb_particle* particles,
+                      int32_t max_particles, int32_t* labels) {
+  if (!c || !out) return fail(EPDLB_EINVAL, "NULL argument");
+  if (max_particles < 0 || (max_particles > 0 && !particles)) return fail(EPDLB_EINVAL, "bad particle array");
+  if (!std::isfinite(threshold)) return fail(EPDLB_EINVAL, "non-finite threshold");
+  if (!c->seeded) return fail(EPDLB_ESTATE, "no state before seed/set_fields/set_state");
+  HIPCHK(hipSetDevice(c->device));
+  return c->p.precision == 0 ? observables_t<double>(c, threshold, out, particles, max_particles, labels)
+                             : observables_t<float>(c, threshold, out, particles, max_particles, labels);
+}
+
+int epdlb_sigma_delta(epdlb_ctx* a, epdlb_ctx* b, double* out) {
+  if (!a || !b || !out) return fail(EPDLB_EINVAL, "NULL argument");
+  if (a->device != b->device || a->p.nx != b->p.nx || a->p.ny != b->p.ny || a->p.precision != b->p.precision)
+    return fail(EPDLB_EINVAL, "sigma_delta needs two contexts on one device with the same grid and precision");
+  if (!a->seeded || !b->seeded) return fail(EPDLB_ESTATE, "no state before seed/set_fields/set_state");
+  HIPCHK(hipSetDevice(a->device));
+  return a->p.precision == 0 ? sigma_delta_t<double>(a, b, out) : sigma_delta_t<float>(a, b, out);
+}
+
 int epdlb_read_diag(epdlb_ctx* c, epdlb_diag* d) {
   if (!c || !d) return fail(EPDLB_EINVAL, "NULL argument");
   double s[kNumScal];
@@ -1665,6 +1824,7 @@ void epdlb_destroy(epdlb_ctx* c) {
   for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->own_mem && c->base) (void)hipFree(c->base);
+  if (c->obs) (void)hipFree(c->obs);
   if (c->snap) (void)hipHostFree(c->snap);
   if (c->snap_ev) (void)hipEventDestroy(c->snap_ev);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
