@@ -121,14 +121,15 @@ def cpu_baseline(preset_name, seconds):
                        f"N={p['n_contour']}, FP64 NumPy oracle, single thread, {dt:.1f} s")
 
 
-def surrogate_summary(steps):
-    """Plain vs surrogate on the 512^2 quench (cfg5q), full runs from the seed."""
+def surrogate_summary(steps, tune_cache=None):
+    """Plain vs surrogate on the 512^2 quench (cfg5q), full runs from the seed, both
+    with the autotuned FFT launch shapes when a tune cache is given."""
     import numpy as np
     from paper_1804_02883_amd.surrogate_eval import compare
     from seeded_inputs import PRESETS
     cfg = PRESETS["cfg5q"]
     w = np.load(WEIGHTS)
-    r = compare(dict(cfg["params"]), cfg["seed"], cfg["sigma"], w, steps)
+    r = compare(dict(cfg["params"]), cfg["seed"], cfg["sigma"], w, steps, tune_cache=tune_cache)
     r["workload"] = f"cfg5q: {cfg['name']}, seed {cfg['seed']}, {r['steps']} steps from the seed"
     return r
 
@@ -142,11 +143,14 @@ def surrogate_line(args):
     p = dict(cfg["params"])
     n = p["nx"] * p["ny"]
     steps = args.steps if args.steps_given else cfg["steps"]
-    r = surrogate_summary(steps - 50)
+    tc = None if args.no_tune else args.tune_cache
+    r = surrogate_summary(steps - 50, tc)
     # per-kernel durations of surrogate steps (100 steps, 2 of them exact)
     sim = Simulation(dict(p, density_mode=1, fallback_every=50, check_every=10, resid_tol=1e-3, err_tol=0.0))
     sim.surrogate_set_weights(np.load(WEIGHTS))
     sim.seed(cfg["seed"], cfg["sigma"])
+    if tc:
+        sim.autotune(20, tc)
     sim.step(100)
     sim.sync()
     sim.profile_start(4000)
@@ -312,7 +316,7 @@ def main():
     else:
         out = plain_line(args, args.workload)
         if not args.no_secondary and args.workload != "cfg4":
-            out["surrogate"] = surrogate_summary(20000 - 50)
+            out["surrogate"] = surrogate_summary(20000 - 50, None if args.no_tune else args.tune_cache)
     if not args.no_cpu_baseline and args.workload != "cfg4":
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
     print(json.dumps(out), flush=True)

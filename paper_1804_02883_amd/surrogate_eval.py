@@ -25,8 +25,10 @@ def _timed_steps(sim, steps, stream):
 
 
 def compare(params, seed, sigma, weights, steps, fallback_every=50, check_every=10, resid_tol=1e-3,
-            err_tol=9e-4, warmup=None):
-    """Returns a dict: plain and surrogate site-updates/s, speedup, errors."""
+            err_tol=9e-4, warmup=None, tune_cache=None):
+    """Returns a dict: plain and surrogate site-updates/s, speedup, errors.  With
+    `tune_cache` both runs use the autotuned FFT launch shapes (read from the
+    cache, tuned and appended when missing)."""
     from paper_1804_02883_amd import Simulation
     n = params["nx"] * params["ny"]
     warm = fallback_every if warmup is None else warmup
@@ -35,6 +37,8 @@ def compare(params, seed, sigma, weights, steps, fallback_every=50, check_every=
     pp = dict(params, density_mode=0)
     sim = Simulation(pp)
     sim.seed(seed, sigma)
+    if tune_cache:
+        sim.autotune(20, tune_cache)
     sim.step(2)
     ms_warm = _timed_steps(sim, warm - 2, sim.stream)
     ms = _timed_steps(sim, steps, sim.stream)
@@ -48,6 +52,8 @@ def compare(params, seed, sigma, weights, steps, fallback_every=50, check_every=
     sim = Simulation(ps)
     sim.surrogate_set_weights(weights)
     sim.seed(seed, sigma)
+    if tune_cache:
+        sim.autotune(20, tune_cache)
     sim.step(2)
     _timed_steps(sim, warm - 2, sim.stream)
     ms_s = _timed_steps(sim, steps, sim.stream)
