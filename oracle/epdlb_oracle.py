@@ -20,7 +20,8 @@ import numpy as np
 
 READINGS = {
     "R1": "One propagator evaluation per step; omega after convection comes from the "
-          "auxiliary omega-convection (App. C comment 1) instead of a Phi->omega CG solve.",
+          "auxiliary omega-convection (App. C comment 1) instead of a Phi->omega CG solve "
+          "(cg_invert = 0, the default; cg_invert = 1 runs the solve, readings R21-R23).",
     "R2": "Step order: advection -> mu at the advected composition -> omega update -> "
           "densities -> force from the diffusive change -> LB; advection uses the "
           "previous LB velocity.",
@@ -46,6 +47,17 @@ READINGS = {
            "forcing stress Sigma of Eq. force_col uses the trace split of d = 2 "
            "(the printed 2/3 and 1/3 are the d = 3 values; the bulk-viscosity relation of "
            "the same passage carries d). u includes F/2; the momentum gains F.",
+    "R21": "Phi->omega inversion (App. C comments 2 and 3): Fletcher-Reeves conjugate "
+           "gradients on G(omega) = (V phibar_P/N) ln Q_P + V phibar_S ln Q_S + dA sum_I "
+           "sum_r omega_I Phi~_I, whose gradient is dA (Phi~ - Phi[omega]) exactly for the "
+           "trapezoid contour weights (the paper names the method, not the functional).",
+    "R22": "Line search: one secant step on the directional derivative from a trial point "
+           "at the previous step length (1 at the first iteration); a direction that is no "
+           "descent direction is replaced by the steepest descent; when the curvature along "
+           "the direction is not positive the trial step is taken.",
+    "R23": "Stopping: sqrt(sum_I sum_r (Phi~_I - Phi_I[omega])^2 / (nx ny)) < N_tr (1e-8), the "
+           "three fields together; start from the auxiliary-convected omega (comment 1); "
+           "after cg_max_iter iterations the last iterate is used unconverged.",
 }
 
 PARITY_UNPINNED = ()
@@ -469,10 +481,94 @@ def init_state(p, omega0):
                 Q_P=d["Q_P"], Q_S=d["Q_S"], S=np.zeros((ny, nx)), F=np.zeros((2, ny, nx)))
 
 
+# --------------------------------------------------------------------------
+# Phi -> omega inversion (App. C comments 1-3; readings R21-R23)
+# --------------------------------------------------------------------------
+
+def legendre_objective(omega, phi_target, p, gauge):
+    """G(omega) of reading R21 at a fixed gauge (cA, cB, cS).
+
+    G = (V phibar_P / N) ln Q_P + V phibar_S ln Q_S + dA sum_I sum_r omega_I Phi~_I.
+    Since Phi_I(r) = -(dA)^-1 dG_0/d omega_I(r) for the first two terms (the
+    density integrals are the derivatives of the log partition functions),
+    dG/d omega_I(r) = dA (Phi~_I(r) - Phi_I[omega](r)); G is convex, so its
+    minimisers are the fields that reproduce Phi~.
+    """
+    d = densities(omega, p, gauge)
+    dA = p["dx"] ** 2
+    V = p["nx"] * p["ny"] * dA
+    phiP = p["phi_P"]
+    return (V * phiP / p["n_contour"] * np.log(d["Q_P"]) + V * (1.0 - phiP) * np.log(d["Q_S"])
+            + dA * float(np.sum(omega * phi_target)))
+
+
+def secant_root(alpha_t, delta0, delta_t):
+    """Step length of the line search (reading R22): the root of the directional
+    derivative along the direction, linear through (0, delta0) and
+    (alpha_t, delta_t); the trial length itself when the slope is not negative."""
+    curv = delta0 - delta_t
+    return alpha_t * delta0 / curv if curv > 0.0 else alpha_t
+
+
+def invert_densities(phi_target, omega0, p, tol=1e-8, max_iter=1000):
+    """Potentials reproducing the composition phi_target (App. C comments 2 and 3).
+
+    Nonlinear conjugate gradients with the Fletcher-Reeves factor on the
+    functional of reading R21: the descent direction at omega is
+    s = Phi[omega] - Phi~ (minus the gradient over dA); directions
+    d_0 = s_0, d_{k+1} = s_{k+1} + (|s_{k+1}|^2 / |s_k|^2) d_k.  Each line search
+    (reading R22) evaluates the directional derivative d . s at a trial point
+    omega + alpha_t d and takes the secant root
+    alpha = alpha_t (d . s) / (d . s - d . s_t).  Stops when the RMS residual
+    over the three fields (reading R23) is below tol.
+    Returns dict(omega, phi, iters, evals, restarts, resid0, resid, converged).
+    """
+    n = p["nx"] * p["ny"]
+    x = np.array(omega0, dtype=np.float64, copy=True)
+
+    def descent(w):
+        return densities(w, p)["phi"] - phi_target
+
+    s = descent(x)
+    evals = 1
+    r2 = float(np.sum(s * s))
+    resid0 = np.sqrt(r2 / n)
+    out = dict(iters=0, restarts=0, resid0=resid0, resid=resid0, converged=resid0 < tol)
+    if out["converged"]:
+        return dict(out, omega=x, phi=s + phi_target, evals=evals)
+    d = s.copy()
+    alpha_t = 1.0
+    for it in range(1, max_iter + 1):
+        delta0 = float(np.sum(d * s))
+        if not delta0 > 0.0:
+            d = s.copy()
+            delta0 = r2
+            out["restarts"] += 1
+        delta_t = float(np.sum(d * descent(x + alpha_t * d)))
+        evals += 1
+        alpha = secant_root(alpha_t, delta0, delta_t)
+        x = x + alpha * d
+        s_new = descent(x)
+        evals += 1
+        r2_new = float(np.sum(s_new * s_new))
+        out["iters"] = it
+        out["resid"] = np.sqrt(r2_new / n)
+        if out["resid"] < tol:
+            out["converged"] = True
+            s = s_new
+            break
+        d = s_new + (r2_new / r2) * d
+        s, r2, alpha_t = s_new, r2_new, alpha
+    return dict(out, omega=x, phi=s + phi_target, evals=evals)
+
+
 def step(state, p):
     """One hybrid LB/EPD step (App. C flow, readings R1-R3).
 
     1. advect Phi^n and omega^n with u^{n-1};
+    1b. (cg_invert = 1) replace the advected omega by the potentials that
+        reproduce the advected composition (invert_densities, tolerance
+        cg_tol, at most cg_max_iter iterations);
     2. mu at the advected composition, omega^{n+1} by the EPD diffusion step;
     3. Phi^{n+1} = Phi[omega^{n+1}];
     4. S = sum_I (Phi_I^{n+1} - Phi~_I)/D_I, lattice force F;
@@ -481,6 +577,10 @@ def step(state, p):
     couple = p.get("couple_lb", 1)
     u_adv = state["u"] if couple else np.zeros_like(state["u"])
     phi_t, omega_t = advect(state["phi"], state["omega"], u_adv)
+    inv = None
+    if p.get("cg_invert", 0):
+        inv = invert_densities(phi_t, omega_t, p, p.get("cg_tol", 1e-8), p.get("cg_max_iter", 1000))
+        omega_t = inv["omega"]
     omega_new = field_update(phi_t, omega_t, p)
     d = densities(omega_new, p)
     D = diffusivities(p)
@@ -488,7 +588,7 @@ def step(state, p):
     F = lattice_force(S, p)
     fstar, rho, u = lb_advance(state["fstar"], F, p)
     return dict(omega=omega_new, phi=d["phi"], fstar=fstar, u=u, rho=rho, n=state["n"] + 1,
-                Q_P=d["Q_P"], Q_S=d["Q_S"], S=S, F=F, phi_t=phi_t)
+                Q_P=d["Q_P"], Q_S=d["Q_S"], S=S, F=F, phi_t=phi_t, omega_t=omega_t, cg=inv)
 
 
 def run(p, omega0, nsteps):
