@@ -1551,11 +1551,8 @@ int observables_t(epdlb_ctx* c, double thr, epdlb_obs* out, epdlb_particle* part
   const T* phi = c->ptr<T>(c->L.phi);
   hipStream_t s = c->stream;
   const dim3 grid(unsigned(o.nblocks)), blk(256);
-  HIPCHK(hipMemsetAsync(area, 0, 4 * size_t(n), s));
-  HIPCHK(hipMemsetAsync(wrap, 0, 4 * size_t(n), s));
-  HIPCHK(hipMemsetAsync(count, 0, 4, s));
-  HIPCHK(hipMemsetAsync(sums, 0, 48 * size_t(n), s));
-  hipLaunchKernelGGL(obs::k_obs_init<T>, grid, blk, 0, s, phi, n, p.nx, p.ny, thr, p.phi_P, L, part);
+  hipLaunchKernelGGL(obs::k_obs_init<T>, grid, blk, 0, s, phi, n, p.nx, p.ny, thr, p.phi_P, L, part, area, wrap, sums,
+                     count);
   hipLaunchKernelGGL(obs::k_ccl_merge, grid, blk, 0, s, L, n, p.nx, p.ny);
   hipLaunchKernelGGL(obs::k_ccl_compress, grid, blk, 0, s, L, n);
   hipLaunchKernelGGL(obs::k_particle_accum<T>, grid, blk, 0, s, phi, (const int*)L, n, p.nx, p.ny, area, sums, wrap);

@@ -46,14 +46,21 @@ __device__ __forceinline__ void block_pair(double a, double b, double* part) {
   }
 }
 
-// Labels (site index on the particles, -1 elsewhere) and the block partial
-// sums of |Phi_P - phibar_P| and y^2 Phi_P.
+// Labels (site index on the particles, -1 elsewhere), the block partial sums
+// of |Phi_P - phibar_P| and y^2 Phi_P, and cleared per-site accumulators.
 template <typename T>
 __global__ void __launch_bounds__(256) k_obs_init(const T* __restrict__ phi, long n, int nx, int ny, double thr,
-                                                  double phibar, int* __restrict__ label, double* __restrict__ part) {
+                                                  double phibar, int* __restrict__ label, double* __restrict__ part,
+                                                  int* __restrict__ area, int* __restrict__ wrap,
+                                                  double* __restrict__ sums, int* __restrict__ count) {
   const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
   double s = 0.0, m = 0.0;
+  if (i == 0) *count = 0;
   if (i < n) {
+    area[i] = 0;
+    wrap[i] = 0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sums[6 * i + k] = 0.0;
     const T pP = phi[i] + phi[n + i];
     const double p = double(pP);
     label[i] = p >= thr ? int(i) : -1;
@@ -189,8 +196,17 @@ __global__ void __launch_bounds__(256) k_particle_list(const int* __restrict__ L
                                                        const double* __restrict__ sums, const int* __restrict__ wrap,
                                                        long n, int nx, int ny, int* count, Particle* out, int cap) {
   const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n || L[i] != int(i)) return;
-  const int k = atomicAdd(count, 1);
+  const bool root = i < n && L[i] == int(i);
+  // one counter update per wave
+  const unsigned long long mask = __ballot(root);
+  if (!mask) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll(mask) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(count, __popcll(mask));
+  base = __shfl(base, leader, 64);
+  if (!root) return;
+  const int k = base + __popcll(mask & ((1ull << lane) - 1));
   if (k >= cap) return;
   const double* s = sums + 6L * i;
   const double N = s[0];
