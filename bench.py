@@ -43,13 +43,13 @@ METRIC = "lattice site-updates/s per hybrid step, plain vs surrogate at <=1e-3 d
 _PROP_FILES = ("fft.hpp", "kernels.hpp")
 _NN_FILES = ("kernels.hpp", "nn.hpp")
 MEASURED_TRAFFIC = {
-    ("cfg3", "prop_col"): dict(bytes_per_launch=17277052, files=_PROP_FILES,
-                               source_sha256="ee0abf9a2afb06b4113b1e020cbd83ef37b0b422a17353386528cb244d97770a"),
-    ("cfg3", "prop_row"): dict(bytes_per_launch=16033716, files=_PROP_FILES,
-                               source_sha256="ee0abf9a2afb06b4113b1e020cbd83ef37b0b422a17353386528cb244d97770a"),
+    ("cfg3", "prop_col"): dict(bytes_per_launch=17274966, files=_PROP_FILES,
+                               source_sha256="60a1c33677698e8cd0df1248651bc262941b567cf5c079d3f45151329679aab5"),
+    ("cfg3", "prop_row"): dict(bytes_per_launch=16033645, files=_PROP_FILES,
+                               source_sha256="60a1c33677698e8cd0df1248651bc262941b567cf5c079d3f45151329679aab5"),
     # mean over the two 64 -> 64 launches of a surrogate step
-    ("cfg5q", "nn_conv"): dict(bytes_per_launch=63956971, files=_NN_FILES,
-                               source_sha256="e824ea993e56df05c99da17f3d8a591609a20d013459db82cb6df84c3a511944"),
+    ("cfg5q", "nn_conv"): dict(bytes_per_launch=63995971, files=_NN_FILES,
+                               source_sha256="6c686eb4ac93d791f85bb8afe472a53f44bbcf97b01ec2803006e021ae1fbd91"),
 }
 
 

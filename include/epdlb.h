@@ -97,6 +97,21 @@ typedef struct {
    * gamma_s = gamma_b = -0.8050541516245486 (lattice nu = 0.018). */
   int32_t lb_mrt;         /* default 0 */
   double lb_gamma_s, lb_gamma_b, lb_gamma_g; /* defaults 0 */
+  /* Omega after convection (App. C, flow chart and its comments 1-3).
+   * 0: the auxiliary convection of omega alone.  1: the convected composition
+   * Phi~ is inverted, starting from the auxiliary-convected omega: Fletcher-
+   * Reeves conjugate gradients on the convex functional
+   *   G(omega) = (V phibar_P/N) ln Q_P + V phibar_S ln Q_S + dA sum_I sum_r omega_I Phi~_I
+   * (gradient dA (Phi~ - Phi[omega])), one secant line search per iteration
+   * (two density evaluations), until sqrt(sum_I sum_r (Phi~_I - Phi_I)^2 / (nx ny))
+   * < cg_tol or cg_max_iter iterations (then the step goes on with the last
+   * iterate; epdlb_cg_stats counts it).  Steps then run eagerly (the host
+   * reads two sums per line search), not as captured graphs.  Needs
+   * density_mode 0 and a single context (no batch); FP32 fields need
+   * cg_tol >= 1e-6.  Allocates 18 field planes of scratch at create. */
+  int32_t cg_invert;      /* default 0 */
+  int32_t cg_max_iter;    /* default 1000 */
+  double cg_tol;          /* default 1e-8 (the paper's N_tr) */
 } epdlb_params;
 
 /* Observables of the current densities (Sec. III and IV).  Phi_P = Phi_A +
@@ -243,6 +258,37 @@ int epdlb_observables(epdlb_ctx* c, double threshold, epdlb_obs* out, epdlb_part
  * the same device with the same grid and precision (e.g. runs with and
  * without LB coupling from the same start).  Synchronises both streams. */
 int epdlb_sigma_delta(epdlb_ctx* a, epdlb_ctx* b, double* out);
+
+/* Result of one Phi -> omega inversion (App. C, comments 2 and 3). */
+typedef struct {
+  int32_t iters;         /* Fletcher-Reeves iterations taken */
+  int32_t evals;         /* density evaluations (2 per iteration + 1, + 1 per restart) */
+  int32_t restarts;      /* directions replaced by the steepest descent */
+  int32_t converged;     /* 1: resid < tolerance */
+  double resid0;         /* RMS of Phi[omega] - Phi~ over the three fields at the start */
+  double resid;          /* the same at the end */
+} epdlb_cg_info;
+
+/* Potentials that reproduce a given composition: starting from the context's
+ * current omega, iterate as for cg_invert = 1 (any cg_invert setting) towards
+ * Phi[omega] = phi_target, at most max_iter iterations (0: only measure the
+ * residual), tolerance tol on the RMS residual.  phi_target: host, 3 * nx * ny
+ * doubles, planes A, B, S, each [y][x], every value > 0; it should carry the
+ * context's totals (sum Phi_A = f_A phi_P nx ny, sum Phi_B = (1 - f_A) phi_P
+ * nx ny, sum Phi_S = (1 - phi_P) nx ny), which no omega can change.  The
+ * result replaces omega and the densities become Phi[omega].  Each field is
+ * determined up to an additive constant.  info (may be NULL) gets the counts
+ * and residuals; an unconverged run still returns EPDLB_OK with
+ * info->converged = 0.  Synchronises the stream.  EINVAL on bad arguments, a
+ * batch replica group or density_mode 1; ESTATE before any state; ENOMEM if
+ * the scratch (18 field planes, allocated once) cannot be allocated. */
+int epdlb_invert_densities(epdlb_ctx* ctx, const double* phi_target, int32_t max_iter, double tol,
+                           epdlb_cg_info* info);
+
+/* The last inversion's result (an inversion step or a direct call) and
+ * running totals: totals[0] inversions, [1] iterations, [2] density
+ * evaluations, [3] unconverged inversions.  Either pointer may be NULL. */
+int epdlb_cg_stats(epdlb_ctx* ctx, epdlb_cg_info* last, int64_t* totals /* 4 */);
 
 /* Launch shape of one FFT pass family: R values per lane, nf transforms per
  * block, and the time per launch the autotuner measured (0 if not tuned). */

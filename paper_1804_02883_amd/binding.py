@@ -54,6 +54,7 @@ class epdlb_params(ctypes.Structure):
         ("check_every", ctypes.c_int32), ("resid_tol", ctypes.c_double), ("err_tol", ctypes.c_double),
         ("lb_mrt", ctypes.c_int32),
         ("lb_gamma_s", ctypes.c_double), ("lb_gamma_b", ctypes.c_double), ("lb_gamma_g", ctypes.c_double),
+        ("cg_invert", ctypes.c_int32), ("cg_max_iter", ctypes.c_int32), ("cg_tol", ctypes.c_double),
     ]
 
 
@@ -99,6 +100,11 @@ class epdlb_particle(ctypes.Structure):
                 ("pad", ctypes.c_int32), ("content", ctypes.c_double), ("cx", ctypes.c_double),
                 ("cy", ctypes.c_double), ("gxx", ctypes.c_double), ("gxy", ctypes.c_double),
                 ("gyy", ctypes.c_double), ("R", ctypes.c_double), ("c_rel", ctypes.c_double)]
+
+
+class epdlb_cg_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("evals", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("resid0", ctypes.c_double), ("resid", ctypes.c_double)]
 
 
 class EpdlbError(RuntimeError):
@@ -175,6 +181,8 @@ SIGNATURES = {
     "epdlb_observables": (ctypes.c_int, [_vp, ctypes.c_double, _P(epdlb_obs), _P(epdlb_particle), ctypes.c_int32,
                                          _P(ctypes.c_int32)]),
     "epdlb_sigma_delta": (ctypes.c_int, [_vp, _vp, _dp]),
+    "epdlb_invert_densities": (ctypes.c_int, [_vp, _dp, ctypes.c_int32, ctypes.c_double, _P(epdlb_cg_info)]),
+    "epdlb_cg_stats": (ctypes.c_int, [_vp, _P(epdlb_cg_info), _P(ctypes.c_int64)]),
     "epdlb_last_error": (ctypes.c_char_p, []),
 }
 
@@ -380,6 +388,35 @@ def epdlb_sigma_delta(ctx_a, ctx_b):
     return v.value
 
 
+def np_shape(a):
+    import numpy as np
+    return tuple(np.shape(a))
+
+
+def _cg_dict(r):
+    return dict(iters=r.iters, evals=r.evals, restarts=r.restarts, converged=bool(r.converged),
+                resid0=r.resid0, resid=r.resid)
+
+
+def epdlb_invert_densities(ctx, phi_target, max_iter=1000, tol=1e-8):
+    """Replace the context's omega by the potentials reproducing phi_target
+    (3 x ny x nx, planes A, B, S), starting from the current omega."""
+    import numpy as np
+    t = np.ascontiguousarray(phi_target, dtype=np.float64)
+    r = epdlb_cg_info()
+    _check(load_library().epdlb_invert_densities(ctx, t.ctypes.data_as(_dp), int(max_iter), float(tol),
+                                                 ctypes.byref(r)), "epdlb_invert_densities")
+    return _cg_dict(r)
+
+
+def epdlb_cg_stats(ctx):
+    """(last inversion, totals dict of inversions, iterations, evals, unconverged)."""
+    r = epdlb_cg_info()
+    t = (ctypes.c_int64 * 4)()
+    _check(load_library().epdlb_cg_stats(ctx, ctypes.byref(r), t), "epdlb_cg_stats")
+    return _cg_dict(r), dict(inversions=t[0], iterations=t[1], evals=t[2], unconverged=t[3])
+
+
 def _diag_dict(d):
     return dict(step=d.step, Q_P=d.Q_P, Q_P_bwd=d.Q_P_bwd, Q_S=d.Q_S, gauge_S=d.gauge_S,
                 mean_omega=tuple(d.mean_omega), n_exact=d.n_exact, n_triggered=d.n_triggered,
@@ -514,6 +551,15 @@ class Simulation:
     def sigma_delta(self, other):
         """sigma_Delta between this run's and another run's polymer densities (Sec. III)."""
         return epdlb_sigma_delta(self.ctx, other.ctx)
+
+    def invert_densities(self, phi_target, max_iter=1000, tol=1e-8):
+        """Potentials reproducing phi_target (App. C), from the current omega; see epdlb.h."""
+        if np_shape(phi_target) != (3,) + self.shape:
+            raise ValueError(f"phi_target must have shape {(3,) + self.shape}")
+        return epdlb_invert_densities(self.ctx, phi_target, max_iter, tol)
+
+    def cg_stats(self):
+        return epdlb_cg_stats(self.ctx)
 
     def autotune(self, reps=20, cache_path=None):
         epdlb_autotune(self.ctx, reps, cache_path)

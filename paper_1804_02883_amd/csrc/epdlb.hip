@@ -16,6 +16,7 @@
 #include "kernels.hpp"
 #include "nn.hpp"
 #include "obs.hpp"
+#include "cg.hpp"
 
 using namespace epdlb;
 
@@ -170,7 +171,19 @@ struct epdlb_ctx {
   int64_t snap_exact = 0;     // exact steps taken when the snapshot was queued
   // observables scratch, allocated at the first epdlb_observables call
   unsigned char* obs = nullptr;
-  template <typename T> T* ptr(size_t off) const { return reinterpret_cast<T*>(base + off); }
+  // Phi -> omega inversion: device scratch (6 field sets, partials, results)
+  // and a pinned pair of doubles for the host's decisions; allocated at
+  // create (cg_invert = 1) or at the first epdlb_invert_densities call
+  unsigned char* cg = nullptr;
+  double* cg_host = nullptr;
+  epdlb_cg_info cg_last{};
+  int64_t cg_totals[4] = {0, 0, 0, 0};  // inversions, iterations, evaluations, unconverged
+  // offsets are taken modulo 2^64 so that buffers outside the arena (the
+  // inversion's scratch) can stand in for arena buffers in a stage
+  template <typename T> T* ptr(size_t off) const {
+    return reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(base) + off);
+  }
+  size_t off_of(const void* q) const { return size_t(reinterpret_cast<uintptr_t>(q) - reinterpret_cast<uintptr_t>(base)); }
 };
 
 namespace {
@@ -178,11 +191,13 @@ namespace {
 int nn_after_seed(epdlb_ctx* c);
 
 enum Kind { K_STATS, K_ADVECT, K_FINISH, K_BOLTZ, K_PROP_ROW, K_PROP_COL, K_DENSITY, K_FROW_FWD, K_FCOL,
-            K_FROW_INV, K_LB, K_NN_CONV0, K_NN_CONV, K_NN_OUT, K_NN_NORM, K_NN_RESET, K_NUM };
+            K_FROW_INV, K_LB, K_NN_CONV0, K_NN_CONV, K_NN_OUT, K_NN_NORM, K_NN_RESET, K_ADVECT_ONLY, K_CG,
+            K_NUM };
 const char* const kKindName[K_NUM] = {"field_stats", "advect_update", "finish_stats",  "boltzmann",
                                       "prop_row",    "prop_col",      "density",       "force_row_fwd",
                                       "force_col",   "force_row_inv", "lb",            "nn_conv0",
-                                      "nn_conv",     "nn_out",        "nn_norm",       "nn_reset"};
+                                      "nn_conv",     "nn_out",        "nn_norm",       "nn_reset",
+                                      "advect_only", "cg_vector"};
 
 // Profiling: while the profiler has room, the next kernel launch records a
 // start/stop event pair at the kernel's own start and end (AMD's extended
@@ -251,6 +266,14 @@ int validate(const epdlb_params* p) {
        !(p->err_tol >= 0.0) || !std::isfinite(p->err_tol)))
     return fail(EPDLB_EINVAL,
                 "surrogate mode needs fallback_every >= 1, check_every >= 1, resid_tol > 0, err_tol >= 0");
+  if (p->cg_invert != 0 && p->cg_invert != 1) return fail(EPDLB_EINVAL, "cg_invert must be 0 or 1");
+  if (p->cg_invert == 1) {
+    if (p->density_mode != 0) return fail(EPDLB_EINVAL, "cg_invert needs exact densities (density_mode 0)");
+    if (p->cg_max_iter < 0 || p->cg_max_iter > 1000000) return fail(EPDLB_EINVAL, "cg_max_iter must be in [0, 1e6]");
+    if (!(p->cg_tol > 0.0) || !std::isfinite(p->cg_tol)) return fail(EPDLB_EINVAL, "cg_tol must be > 0");
+    if (p->precision == 1 && p->cg_tol < 1e-6)
+      return fail(EPDLB_EINVAL, "cg_tol below 1e-6 needs FP64 fields (precision 0)");
+  }
   return EPDLB_OK;
 }
 
@@ -473,7 +496,7 @@ int stage_stats(epdlb_ctx* c) {
 }
 
 template <typename T>
-int stage_advect_update(epdlb_ctx* c) {
+UpdArgs<T> make_upd_args(epdlb_ctx* c, bool flow) {
   const epdlb_params& p = c->p;
   UpdArgs<T> a;
   const long n = long(p.nx) * p.ny;
@@ -496,9 +519,19 @@ int stage_advect_update(epdlb_ctx* c) {
     a.coef[i] = T(D[i] * p.dt / (p.dx * p.dx));
     a.invD[i] = T(1.0 / D[i]);
   }
-  a.advect = p.couple_lb ? 1 : 0;
+  a.advect = flow && p.couple_lb ? 1 : 0;
   a.nrep = c->nrep;
   a.rs = long(c->rstride);
+  return a;
+}
+
+// flow = false: mu and the omega update at the stored fields without
+// convection (used after the Phi -> omega inversion, which convects first).
+template <typename T>
+int stage_advect_update(epdlb_ctx* c, bool flow = true) {
+  const epdlb_params& p = c->p;
+  const long n = long(p.nx) * p.ny;
+  UpdArgs<T> a = make_upd_args<T>(c, flow);
   {
     ProfScope ps(c, K_ADVECT);
     launch_k((k_advect_update<T>), dim3(p.nx / kTX, p.ny / kTY, c->nrep), dim3(kTX * kTY), 0, c->stream, a);
@@ -702,10 +735,199 @@ int stage_lb(epdlb_ctx* c) {
   return EPDLB_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Phi -> omega inversion (App. C, comments 1-3): the scratch holds the target
+// composition Phi~, the iterate x, the direction d, the descent direction s,
+// the trial point xt and the evaluated densities, 3 planes each.
+// ---------------------------------------------------------------------------
+struct CgLayout {
+  size_t set[6];  // target, x, d, s, xt, phi
+  size_t part, out, total;
+};
+enum { CG_TARGET, CG_X, CG_D, CG_S, CG_XT, CG_PHI };
+
+CgLayout cg_layout(const epdlb_params& p) {
+  const size_t es = p.precision == 0 ? 8 : 4;
+  const size_t set = 3 * size_t(p.nx) * p.ny * es;
+  CgLayout L{};
+  size_t off = 0;
+  for (int i = 0; i < 6; ++i) {
+    L.set[i] = off;
+    off = align256(off + set);
+  }
+  L.part = off;
+  off = align256(off + 2 * cg::kBlocks * sizeof(double));
+  L.out = off;
+  off = align256(off + 2 * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+int ensure_cg(epdlb_ctx* c) {
+  if (c->cg) return EPDLB_OK;
+  void* m = nullptr;
+  if (hipMalloc(&m, cg_layout(c->p).total) != hipSuccess) return fail(EPDLB_ENOMEM, "inversion scratch allocation failed");
+  void* h = nullptr;
+  if (hipHostMalloc(&h, 2 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    (void)hipFree(m);
+    return fail(EPDLB_ENOMEM, "pinned host allocation failed");
+  }
+  c->cg = static_cast<unsigned char*>(m);
+  c->cg_host = static_cast<double*>(h);
+  return EPDLB_OK;
+}
+
+template <typename T> T* cg_set(epdlb_ctx* c, int which) {
+  return reinterpret_cast<T*>(c->cg + cg_layout(c->p).set[which]);
+}
+
+// Densities of the field set at `w` into `phi` through the ordinary stages
+// (field statistics, propagators, density integrals), the arena's omega and
+// Phi buffers standing in for them during the call.
+template <typename T>
+int cg_eval(epdlb_ctx* c, const T* w, T* phi) {
+  const size_t w0 = c->L.omega[c->cur], p0 = c->L.phi;
+  c->L.omega[c->cur] = c->off_of(w);
+  c->L.phi = c->off_of(phi);
+  int r = stage_stats<T>(c);
+  if (r == EPDLB_OK) r = stage_densities<T>(c, false);
+  c->L.omega[c->cur] = w0;
+  c->L.phi = p0;
+  return r;
+}
+
+// Sums the partials of nq quantities and brings them to the host (synchronises).
+int cg_reduce(epdlb_ctx* c, int nq, double* out) {
+  const CgLayout L = cg_layout(c->p);
+  double* part = reinterpret_cast<double*>(c->cg + L.part);
+  double* dev = reinterpret_cast<double*>(c->cg + L.out);
+  {
+    ProfScope ps(c, K_CG);
+    launch_k(cg::k_cg_finish, dim3(1), dim3(cg::kThreads), 0, c->stream, (const double*)part, cg::kBlocks, nq, dev);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(c->cg_host, dev, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  out[0] = c->cg_host[0];
+  out[1] = c->cg_host[1];
+  return EPDLB_OK;
+}
+
+// Fletcher-Reeves iteration from x towards Phi[x] = target (both in the
+// scratch); x holds the result.  info gets the counts and residuals.
+template <typename T>
+int cg_invert(epdlb_ctx* c, double tol, int max_iter, epdlb_cg_info* info) {
+  const long n = long(c->p.nx) * c->p.ny, m = 3 * n;
+  const CgLayout L = cg_layout(c->p);
+  T* tgt = cg_set<T>(c, CG_TARGET);
+  T* x = cg_set<T>(c, CG_X);
+  T* d = cg_set<T>(c, CG_D);
+  T* s = cg_set<T>(c, CG_S);
+  T* xt = cg_set<T>(c, CG_XT);
+  T* phi = cg_set<T>(c, CG_PHI);
+  double* part = reinterpret_cast<double*>(c->cg + L.part);
+  const dim3 grid(cg::kBlocks), blk(cg::kThreads);
+  *info = epdlb_cg_info{};
+  double r2 = 0.0, sums[2];
+  // descent direction s = Phi[x] - target and |s|^2
+  auto resid = [&](double* out) -> int {
+    CHK(cg_eval<T>(c, x, phi));
+    ++info->evals;
+    {
+      ProfScope ps(c, K_CG);
+      launch_k((cg::k_cg_resid<T>), grid, blk, 0, c->stream, (const T*)phi, (const T*)tgt, s, m, part);
+    }
+    HIPCHK(hipGetLastError());
+    double v[2];
+    CHK(cg_reduce(c, 1, v));
+    *out = v[0];
+    return EPDLB_OK;
+  };
+  // d = s (first) or s + beta d, trial point x + alpha_t d; returns d.s and d.s(trial)
+  auto trial = [&](double beta, int first, double alpha_t) -> int {
+    {
+      ProfScope ps(c, K_CG);
+      launch_k((cg::k_cg_trial<T>), grid, blk, 0, c->stream, (const T*)s, d, (const T*)x, xt, T(beta), first,
+               T(alpha_t), m, part);
+    }
+    HIPCHK(hipGetLastError());
+    CHK(cg_eval<T>(c, xt, phi));
+    ++info->evals;
+    {
+      ProfScope ps(c, K_CG);
+      launch_k((cg::k_cg_dirdot<T>), grid, blk, 0, c->stream, (const T*)d, (const T*)phi, (const T*)tgt, m,
+               part + cg::kBlocks);
+    }
+    HIPCHK(hipGetLastError());
+    return cg_reduce(c, 2, sums);
+  };
+  CHK(resid(&r2));
+  info->resid0 = info->resid = std::sqrt(r2 / double(n));
+  info->converged = info->resid < tol;
+  double beta = 0.0, alpha_t = 1.0;
+  int first = 1;
+  for (int it = 1; it <= max_iter && !info->converged; ++it) {
+    CHK(trial(beta, first, alpha_t));
+    if (!(sums[0] > 0.0) && !first) {
+      // not a descent direction: restart along s
+      ++info->restarts;
+      first = 1;
+      CHK(trial(0.0, 1, alpha_t));
+    }
+    const double delta0 = sums[0], curv = sums[0] - sums[1];
+    const double alpha = curv > 0.0 ? alpha_t * delta0 / curv : alpha_t;
+    {
+      ProfScope ps(c, K_CG);
+      launch_k((cg::k_cg_axpy<T>), grid, blk, 0, c->stream, x, (const T*)d, T(alpha), m);
+    }
+    HIPCHK(hipGetLastError());
+    double r2n = 0.0;
+    CHK(resid(&r2n));
+    info->iters = it;
+    info->resid = std::sqrt(r2n / double(n));
+    info->converged = info->resid < tol;
+    beta = r2n / r2;
+    r2 = r2n;
+    alpha_t = alpha;
+    first = 0;
+  }
+  ++c->cg_totals[0];
+  c->cg_totals[1] += info->iters;
+  c->cg_totals[2] += info->evals;
+  if (!info->converged) ++c->cg_totals[3];
+  c->cg_last = *info;
+  return EPDLB_OK;
+}
+
+// Convection, inversion of the convected composition from the auxiliary-
+// convected omega, then mu and the omega update at (Phi~, omega~).
+template <typename T>
+int stage_advect_cg(epdlb_ctx* c) {
+  const epdlb_params& p = c->p;
+  CHK(ensure_cg(c));
+  {
+    const UpdArgs<T> a = make_upd_args<T>(c, true);
+    ProfScope ps(c, K_ADVECT_ONLY);
+    launch_k((k_advect_only<T>), dim3(p.nx / kTX, p.ny / kTY), dim3(kTX * kTY), 0, c->stream, a,
+             cg_set<T>(c, CG_TARGET), cg_set<T>(c, CG_X));
+  }
+  HIPCHK(hipGetLastError());
+  epdlb_cg_info info;
+  CHK(cg_invert<T>(c, p.cg_tol, p.cg_max_iter, &info));
+  const int cur0 = c->cur;
+  const size_t w0 = c->L.omega[cur0], p0 = c->L.phi;
+  c->L.omega[cur0] = c->off_of(cg_set<T>(c, CG_X));
+  c->L.phi = c->off_of(cg_set<T>(c, CG_TARGET));
+  const int r = stage_advect_update<T>(c, false);
+  c->L.omega[cur0] = w0;
+  c->L.phi = p0;
+  return r;
+}
+
 template <typename T>
 int run_stage_t(epdlb_ctx* c, int stage) {
   switch (stage) {
-    case EPDLB_STAGE_ADVECT_UPDATE: return stage_advect_update<T>(c);
+    case EPDLB_STAGE_ADVECT_UPDATE: return c->p.cg_invert ? stage_advect_cg<T>(c) : stage_advect_update<T>(c);
     case EPDLB_STAGE_DENSITIES: return stage_densities<T>(c, true);
     case EPDLB_STAGE_FORCE: return stage_force<T>(c);
     case EPDLB_STAGE_LB: return stage_lb<T>(c);
@@ -1227,6 +1449,9 @@ int epdlb_params_default(epdlb_params* p) {
   p->err_tol = 1e-3;
   p->lb_mrt = 0;
   p->lb_gamma_s = p->lb_gamma_b = p->lb_gamma_g = 0.0;
+  p->cg_invert = 0;
+  p->cg_max_iter = 1000;
+  p->cg_tol = 1e-8;
   return EPDLB_OK;
 }
 
@@ -1301,6 +1526,10 @@ int epdlb_create(const epdlb_params* p, int device, void* stream, void* workspac
     c->own_mem = true;
   }
   default_shapes(c);
+  if (p->cg_invert == 1 && ensure_cg(c) != EPDLB_OK) {
+    epdlb_destroy(c);
+    return fail(EPDLB_ENOMEM, "inversion scratch allocation failed");
+  }
   if (p->density_mode == 1) {
     if (hipHostMalloc(reinterpret_cast<void**>(&c->snap), 3 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&c->snap_ev, hipEventDisableTiming) != hipSuccess) {
@@ -1405,7 +1634,8 @@ int epdlb_step(epdlb_ctx* c, int64_t n) {
     }
     return EPDLB_OK;
   }
-  if (c->use_graph && !c->prof_on) {
+  // the inversion decides its iteration count on the host: no graphs
+  if (c->use_graph && !c->prof_on && !c->p.cg_invert) {
     // replay captured two-step graphs (buffer parity returns to its start),
     // then a one-step graph for an odd remainder
     while (n > 0) {
@@ -1652,6 +1882,49 @@ int epdlb_sigma_delta(epdlb_ctx* a, epdlb_ctx* b, double* out) {
   return a->p.precision == 0 ? sigma_delta_t<double>(a, b, out) : sigma_delta_t<float>(a, b, out);
 }
 
+int epdlb_invert_densities(epdlb_ctx* c, const double* phi_target, int32_t max_iter, double tol,
+                           epdlb_cg_info* info) {
+  if (!c || !phi_target) return fail(EPDLB_EINVAL, "ctx or phi_target is NULL");
+  if (!c->seeded) return fail(EPDLB_ESTATE, "inversion before seed/set_fields/set_state");
+  if (c->nrep != 1) return fail(EPDLB_EINVAL, "inversion of a batch replica group is not supported");
+  if (c->p.density_mode != 0) return fail(EPDLB_EINVAL, "inversion needs exact densities (density_mode 0)");
+  if (max_iter < 0 || max_iter > 1000000 || !(tol > 0.0) || !std::isfinite(tol))
+    return fail(EPDLB_EINVAL, "max_iter must be in [0, 1e6] and tol > 0");
+  HIPCHK(hipSetDevice(c->device));
+  CHK(ensure_cg(c));
+  const size_t n = size_t(c->p.nx) * c->p.ny;
+  for (size_t i = 0; i < 3 * n; ++i)
+    if (!std::isfinite(phi_target[i]) || !(phi_target[i] > 0.0))
+      return fail(EPDLB_EINVAL, "phi_target must be finite and positive");
+  auto run = [&](auto tag) -> int {
+    using T = decltype(tag);
+    T* tgt = cg_set<T>(c, CG_TARGET);
+    T* x = cg_set<T>(c, CG_X);
+    T* w = c->ptr<T>(c->L.omega[c->cur]);
+    std::vector<T> tmp(3 * n);
+    for (size_t i = 0; i < 3 * n; ++i) tmp[i] = T(phi_target[i]);
+    HIPCHK(hipMemcpyAsync(tgt, tmp.data(), 3 * n * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(x, w, 3 * n * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+    epdlb_cg_info r;
+    CHK(cg_invert<T>(c, tol, max_iter, &r));
+    HIPCHK(hipMemcpyAsync(w, x, 3 * n * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+    CHK(stage_stats<T>(c));
+    CHK(stage_densities<T>(c, false));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (info) *info = r;
+    return EPDLB_OK;
+  };
+  return c->p.precision == 0 ? run(double()) : run(float());
+}
+
+int epdlb_cg_stats(epdlb_ctx* c, epdlb_cg_info* last, int64_t* totals) {
+  if (!c) return fail(EPDLB_EINVAL, "ctx is NULL");
+  if (last) *last = c->cg_last;
+  if (totals)
+    for (int i = 0; i < 4; ++i) totals[i] = c->cg_totals[i];
+  return EPDLB_OK;
+}
+
 int epdlb_read_diag(epdlb_ctx* c, epdlb_diag* d) {
   if (!c || !d) return fail(EPDLB_EINVAL, "NULL argument");
   double s[kNumScal];
@@ -1822,6 +2095,8 @@ void epdlb_destroy(epdlb_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->own_mem && c->base) (void)hipFree(c->base);
   if (c->obs) (void)hipFree(c->obs);
+  if (c->cg) (void)hipFree(c->cg);
+  if (c->cg_host) (void)hipHostFree(c->cg_host);
   if (c->snap) (void)hipHostFree(c->snap);
   if (c->snap_ev) (void)hipEventDestroy(c->snap_ev);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -1834,6 +2109,7 @@ int epdlb_batch_create(const epdlb_params* params, int32_t n_replicas, int devic
   *out = nullptr;
   for (int r = 0; r < n_replicas; ++r) {
     CHK(validate(&params[r]));
+    if (params[r].cg_invert) return fail(EPDLB_EINVAL, "cg_invert is not supported in a batch");
     if (!same_model(params[0], params[r]))
       return fail(EPDLB_EINVAL, "replicas may differ only in nx, ny, g and f_A");
     if (params[r].density_mode != 0) return fail(EPDLB_EINVAL, "batched replicas run the exact densities only");

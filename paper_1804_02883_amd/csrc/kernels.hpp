@@ -539,17 +539,39 @@ template <typename T> struct UpdArgs {
   }
 };
 
+// One Euler-forward convection step at LDS position (lx, ly) of a tile holding
+// phi[3], omega[3], ux, uy: donor-cell flux form for Phi (face velocity the
+// mean of the two cell velocities, upwind cell by its sign), upwind form for
+// the auxiliary convection of omega (App. C, first comment).
 template <typename T>
-__global__ void __launch_bounds__(256) k_advect_update(UpdArgs<T> P) {
-  __shared__ T sIn[8][kHY][kHX];   // phi[3], w[3], ux, uy
-  __shared__ T sMu[3][kMY][kMX];
-  __shared__ T sWt[3][kMY][kMX];
-  __shared__ double red[16 * 4];
-  P.shift(long(blockIdx.z) * P.rs);
-  const int lt = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-  const int tx0 = (lt % gridDim.x) * kTX, ty0 = (lt / gridDim.x) * kTY;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < kHX * kHY; e += blockDim.x) {
+__device__ __forceinline__ void advect_site(const T (&sIn)[8][kHY][kHX], int lx, int ly, T (&pt)[3], T (&wt)[3]) {
+  const T uxc = sIn[6][ly][lx], uyc = sIn[7][ly][lx];
+  // face velocities
+  const T uxe = T(0.5) * (uxc + sIn[6][ly][lx + 1]);
+  const T uxw = T(0.5) * (sIn[6][ly][lx - 1] + uxc);
+  const T uyn = T(0.5) * (uyc + sIn[7][ly + 1][lx]);
+  const T uys = T(0.5) * (sIn[7][ly - 1][lx] + uyc);
+#pragma unroll
+  for (int I = 0; I < 3; ++I) {
+    const T c = sIn[I][ly][lx];
+    const T Je = uxe >= T(0) ? uxe * c : uxe * sIn[I][ly][lx + 1];
+    const T Jw = uxw >= T(0) ? uxw * sIn[I][ly][lx - 1] : uxw * c;
+    const T Jn = uyn >= T(0) ? uyn * c : uyn * sIn[I][ly + 1][lx];
+    const T Js = uys >= T(0) ? uys * sIn[I][ly - 1][lx] : uys * c;
+    pt[I] = c - (Je - Jw) - (Jn - Js);
+    const T w = sIn[3 + I][ly][lx];
+    const T upx = uxc > T(0) ? uxc : T(0), umx = uxc < T(0) ? uxc : T(0);
+    const T upy = uyc > T(0) ? uyc : T(0), umy = uyc < T(0) ? uyc : T(0);
+    wt[I] = w - (upx * (w - sIn[3 + I][ly][lx - 1]) + umx * (sIn[3 + I][ly][lx + 1] - w)) -
+            (upy * (w - sIn[3 + I][ly - 1][lx]) + umy * (sIn[3 + I][ly + 1][lx] - w));
+  }
+}
+
+// Loads the tile at (tx0, ty0) with a halo of 2 into sIn (velocities zero
+// when the flow does not advect).
+template <typename T>
+__device__ __forceinline__ void load_advect_tile(const UpdArgs<T>& P, int tx0, int ty0, T (&sIn)[8][kHY][kHX]) {
+  for (int e = threadIdx.x; e < kHX * kHY; e += blockDim.x) {
     const int lx = e % kHX, ly = e / kHX;
     const int gx = (tx0 + lx - 2 + P.nx) & (P.nx - 1);
     const int gy = (ty0 + ly - 2 + P.ny) & (P.ny - 1);
@@ -567,32 +589,25 @@ __global__ void __launch_bounds__(256) k_advect_update(UpdArgs<T> P) {
       sIn[7][ly][lx] = T(0);
     }
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_advect_update(UpdArgs<T> P) {
+  __shared__ T sIn[8][kHY][kHX];   // phi[3], w[3], ux, uy
+  __shared__ T sMu[3][kMY][kMX];
+  __shared__ T sWt[3][kMY][kMX];
+  __shared__ double red[16 * 4];
+  P.shift(long(blockIdx.z) * P.rs);
+  const int lt = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int tx0 = (lt % gridDim.x) * kTX, ty0 = (lt / gridDim.x) * kTY;
+  const int tid = threadIdx.x;
+  load_advect_tile(P, tx0, ty0, sIn);
   __syncthreads();
   // advected fields and mu~ on the halo-1 region
   for (int e = tid; e < kMX * kMY; e += blockDim.x) {
     const int mx = e % kMX, my = e / kMX;
-    const int lx = mx + 1, ly = my + 1;  // position in sIn
-    const T uxc = sIn[6][ly][lx], uyc = sIn[7][ly][lx];
-    // face velocities
-    const T uxe = T(0.5) * (uxc + sIn[6][ly][lx + 1]);
-    const T uxw = T(0.5) * (sIn[6][ly][lx - 1] + uxc);
-    const T uyn = T(0.5) * (uyc + sIn[7][ly + 1][lx]);
-    const T uys = T(0.5) * (sIn[7][ly - 1][lx] + uyc);
     T pt[3], wt[3];
-#pragma unroll
-    for (int I = 0; I < 3; ++I) {
-      const T c = sIn[I][ly][lx];
-      const T Je = uxe >= T(0) ? uxe * c : uxe * sIn[I][ly][lx + 1];
-      const T Jw = uxw >= T(0) ? uxw * sIn[I][ly][lx - 1] : uxw * c;
-      const T Jn = uyn >= T(0) ? uyn * c : uyn * sIn[I][ly + 1][lx];
-      const T Js = uys >= T(0) ? uys * sIn[I][ly - 1][lx] : uys * c;
-      pt[I] = c - (Je - Jw) - (Jn - Js);
-      const T w = sIn[3 + I][ly][lx];
-      const T upx = uxc > T(0) ? uxc : T(0), umx = uxc < T(0) ? uxc : T(0);
-      const T upy = uyc > T(0) ? uyc : T(0), umy = uyc < T(0) ? uyc : T(0);
-      wt[I] = w - (upx * (w - sIn[3 + I][ly][lx - 1]) + umx * (sIn[3 + I][ly][lx + 1] - w)) -
-              (upy * (w - sIn[3 + I][ly - 1][lx]) + umy * (sIn[3 + I][ly + 1][lx] - w));
-    }
+    advect_site(sIn, mx + 1, my + 1, pt, wt);  // position in sIn
     const T tot = pt[0] + pt[1] + pt[2];
 #pragma unroll
     for (int I = 0; I < 3; ++I) {
@@ -626,6 +641,26 @@ __global__ void __launch_bounds__(256) k_advect_update(UpdArgs<T> P) {
     }
   }
   block_partial<4>(v, red, P.partials, lt);
+}
+
+// The convection step alone: Phi~ -> phit and the auxiliary-convected omega
+// -> wt (3 planes each), for the Phi -> omega inversion that follows it.
+template <typename T>
+__global__ void __launch_bounds__(256) k_advect_only(UpdArgs<T> P, T* __restrict__ phit, T* __restrict__ wt) {
+  __shared__ T sIn[8][kHY][kHX];
+  const int lt = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int tx0 = (lt % gridDim.x) * kTX, ty0 = (lt / gridDim.x) * kTY;
+  load_advect_tile(P, tx0, ty0, sIn);
+  __syncthreads();
+  const int ox = threadIdx.x % kTX, oy = threadIdx.x / kTX;  // 256 threads = 32 x 8 sites
+  T pt[3], w[3];
+  advect_site(sIn, ox + 2, oy + 2, pt, w);
+  const long gi = long(ty0 + oy) * P.nx + (tx0 + ox);
+#pragma unroll
+  for (int I = 0; I < 3; ++I) {
+    phit[I * P.n + gi] = pt[I];
+    wt[I * P.n + gi] = w[I];
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -57,12 +57,18 @@ def test_defaults_and_validation():
     gs, gb = B.mrt_gammas(1.0, 1.0)  # the paper's eta = eta_B at its dx, dt
     assert abs(gs + 0.8050541516245486) < 1e-15 and gs == gb
     assert B.epdlb_validate(B.make_params(lb_mrt=1, lb_gamma_s=gs, lb_gamma_b=gb, lb_gamma_g=0.5)) == 0
+    assert (p.cg_invert, p.cg_max_iter, p.cg_tol) == (0, 1000, 1e-8)
+    assert B.epdlb_validate(B.make_params(cg_invert=1)) == 0
+    assert B.epdlb_validate(B.make_params(cg_invert=1, precision=1, cg_tol=1e-6)) == 0
     for bad in [dict(nx=48), dict(nx=16), dict(ny=8), dict(n_contour=1), dict(f_A=1.0),
                 dict(phi_P=0.0), dict(lb_tau=0.5), dict(precision=2), dict(abi_version=7),
                 dict(g=float("nan")), dict(density_mode=2), dict(density_mode=1, fallback_every=0),
                 dict(density_mode=1, check_every=0), dict(density_mode=1, resid_tol=0.0),
                 dict(density_mode=1, err_tol=-1.0), dict(lb_mrt=2), dict(lb_mrt=1, lb_gamma_s=1.0),
-                dict(lb_mrt=1, lb_gamma_b=-1.0), dict(lb_mrt=1, lb_gamma_g=float("nan"))]:
+                dict(lb_mrt=1, lb_gamma_b=-1.0), dict(lb_mrt=1, lb_gamma_g=float("nan")),
+                dict(cg_invert=2), dict(cg_invert=1, density_mode=1), dict(cg_invert=1, cg_tol=0.0),
+                dict(cg_invert=1, cg_max_iter=-1), dict(cg_invert=1, cg_tol=float("inf")),
+                dict(cg_invert=1, precision=1)]:
         q = B.make_params(**bad)
         assert B.epdlb_validate(q) == B.EPDLB_EINVAL, bad
         assert B.epdlb_last_error() != ""
@@ -120,3 +126,17 @@ def test_batch_rejects_mixed_collision_models_before_device_calls():
         with pytest.raises(B.EpdlbError) as e:
             B.epdlb_batch_create(pair)
         assert e.value.code == B.EPDLB_EINVAL
+
+
+def test_inversion_arguments_checked_before_device_calls():
+    # a batch cannot run the host-driven inversion; a NULL context is refused
+    with pytest.raises(B.EpdlbError) as e:
+        B.epdlb_batch_create([B.make_params(nx=64, ny=64, cg_invert=1)] * 2)
+    assert e.value.code == B.EPDLB_EINVAL
+    import numpy as np
+    with pytest.raises(B.EpdlbError) as e:
+        B.epdlb_invert_densities(None, np.ones((3, 32, 32)))
+    assert e.value.code == B.EPDLB_EINVAL
+    with pytest.raises(B.EpdlbError) as e:
+        B.epdlb_cg_stats(None)
+    assert e.value.code == B.EPDLB_EINVAL
