@@ -17,6 +17,14 @@ R19  Positions in the gyration tensor: each site of a particle is placed at
      y is flagged as wrapping; its tensor is then not meaningful.
 R20  Y_2^P: y is measured from the box centre at cell centres, y = j + 1/2 -
      L_y/2, and the integrals are the sums over rows of the x-averaged Phi_P.
+R24  Nucleation events (Sec. IV, nucleation stage): sampled every few steps,
+     a particle of the current sample none of whose sites was a particle
+     site (Phi_P >= threshold) at the previous sample is a new nucleus; its
+     time is the sample's and its position the centroid.  At the first sample
+     every particle counts.  The sampling interval must be short against the
+     time a particle takes to move by its own size, or a moving particle is
+     counted again.  The particle density n_p is the particle count over the
+     system size V = nx ny dx^2.
 """
 from collections import deque
 
@@ -108,3 +116,19 @@ def particle_table(phiP, threshold=0.5):
                         G=(float(G[0, 0]), float(G[0, 1]), float(G[1, 1])), R=float(R), c_rel=float(c_rel),
                         wraps=wraps))
     return out
+
+
+def nucleation_events(phiP_prev, phiP, threshold=0.5):
+    """Particles of phiP that are new since the sample phiP_prev (reading R24),
+    as particle_table entries in label order; phiP_prev None: every particle."""
+    table = particle_table(phiP, threshold)
+    if phiP_prev is None:
+        return table
+    was = np.asarray(phiP_prev, dtype=np.float64) >= threshold
+    lab = label_particles(phiP, threshold)
+    return [t for t in table if not np.any(was[lab == t["label"]])]
+
+
+def particle_density(n_particles, nx, ny, dx):
+    """n_p (Sec. IV, nucleation stage): particles per unit area of the system (reading R24)."""
+    return n_particles / (nx * ny * dx * dx)

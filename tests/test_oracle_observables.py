@@ -143,3 +143,41 @@ def test_rotation_and_covariance_form():
     cxy = np.average((xs - mx) * (ys - my), weights=w)
     cyy = np.average((ys - my) ** 2, weights=w)
     assert np.allclose(big["G"], (cxx, cxy, cyy), atol=1e-12)
+
+
+def _disk(ny, nx, cy, cx, r, inside=0.8, outside=0.1):
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    d2 = ((yy - cy + ny / 2) % ny - ny / 2) ** 2 + ((xx - cx + nx / 2) % nx - nx / 2) ** 2
+    return np.where(d2 <= r * r, inside, outside)
+
+
+def test_nucleation_events_cases():
+    """New, persisting, moved, merged and vanished particles between two samples."""
+    ny, nx = 32, 48
+    a = np.maximum(_disk(ny, nx, 8, 8, 3), _disk(ny, nx, 20, 30, 3))
+    # the first sample: every particle is new
+    assert [t["label"] for t in B.nucleation_events(None, a)] == [t["label"] for t in B.particle_table(a)]
+    assert len(B.nucleation_events(None, a)) == 2
+    # unchanged, or shifted by one site (overlapping): nothing new
+    assert B.nucleation_events(a, a) == []
+    shifted = np.maximum(_disk(ny, nx, 9, 8, 3), _disk(ny, nx, 20, 31, 3))
+    assert B.nucleation_events(a, shifted) == []
+    # one old particle stays, one vanishes, two appear: the two new ones, with their tables
+    b = np.maximum.reduce([_disk(ny, nx, 8, 8, 3), _disk(ny, nx, 26, 4, 2), _disk(ny, nx, 4, 40, 2.5)])
+    ev = B.nucleation_events(a, b)
+    assert len(ev) == 2
+    new = [t for t in B.particle_table(b) if abs(t["centroid"][0] - 8) > 1e-9 or abs(t["centroid"][1] - 8) > 1e-9]
+    assert ev == new
+    assert {(round(t["centroid"][1]), round(t["centroid"][0])) for t in ev} == {(26, 4), (4, 40)}
+    # two old particles merging into one: not new
+    c = np.maximum(_disk(ny, nx, 8, 8, 3), _disk(ny, nx, 8, 13, 3))
+    pre = np.maximum(_disk(ny, nx, 8, 8, 2), _disk(ny, nx, 8, 14, 2))
+    assert len(B.particle_table(pre)) == 2 and len(B.particle_table(c)) == 1
+    assert B.nucleation_events(pre, c) == []
+    # a particle that jumps by more than its size counts again (the sampling caveat)
+    far = np.maximum(_disk(ny, nx, 8, 20, 3), _disk(ny, nx, 20, 30, 3))
+    assert len(B.nucleation_events(a, far)) == 1
+
+
+def test_particle_density():
+    assert B.particle_density(10, 64, 32, 1 / 3) == 10 / (64 * 32 / 9)
