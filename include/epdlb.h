@@ -129,7 +129,7 @@ typedef struct {
   int32_t label;         /* lowest flat site index y * nx + x of the particle */
   int32_t area;          /* number of sites */
   int32_t wraps;         /* 1: offsets from the label site reach half the box (tensor not meaningful) */
-  int32_t pad;
+  int32_t born;          /* epdlb_track_particles: 1 if no site was a particle site at the previous sample; else 0 */
   double content;        /* N = sum of Phi_P over the sites */
   double cx, cy;         /* Phi_P-weighted centroid, in site units inside the box */
   double gxx, gxy, gyy;  /* Eq. gyration_tensor, positions as minimum-image offsets from the label site */
@@ -253,6 +253,23 @@ int epdlb_read_diag(epdlb_ctx* ctx, epdlb_diag* d);
  * EINVAL on a bad argument, ESTATE before any state. */
 int epdlb_observables(epdlb_ctx* c, double threshold, epdlb_obs* out, epdlb_particle* particles,
                       int32_t max_particles, int32_t* labels);
+
+/* Nucleation events (Sec. IV, nucleation stage): the observables of the
+ * current densities as epdlb_observables computes them, and the particles
+ * none of whose sites was a particle site (Phi_P >= the threshold of that
+ * call) at the previous tracking call, i.e. nuclei formed since then.  The
+ * first call after create, seed, set_fields or epdlb_track_reset counts
+ * every particle (set_state keeps the previous sample: it resumes a run).  events: host array of max_events entries (NULL if
+ * max_events = 0), the first min(n_events, max_events) new particles in label
+ * order with born = 1; n_events: their number.  Sample often enough that a
+ * particle moves less than its own size between calls, or it is counted
+ * again.  The particle sites of this call are kept (one byte per site, in
+ * the observables scratch) for the next.  Synchronises the stream.  EINVAL on
+ * a bad argument or a batch replica group, ESTATE before any state. */
+int epdlb_track_particles(epdlb_ctx* c, double threshold, epdlb_obs* out, epdlb_particle* events,
+                          int32_t max_events, int32_t* n_events);
+/* Forget the previous tracking sample. */
+int epdlb_track_reset(epdlb_ctx* c);
 
 /* sigma_Delta (Sec. III): (1/V) sum |Phi_P^a - Phi_P^b| over two contexts on
  * the same device with the same grid and precision (e.g. runs with and

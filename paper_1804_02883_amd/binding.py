@@ -97,7 +97,7 @@ class epdlb_obs(ctypes.Structure):
 
 class epdlb_particle(ctypes.Structure):
     _fields_ = [("label", ctypes.c_int32), ("area", ctypes.c_int32), ("wraps", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("content", ctypes.c_double), ("cx", ctypes.c_double),
+                ("born", ctypes.c_int32), ("content", ctypes.c_double), ("cx", ctypes.c_double),
                 ("cy", ctypes.c_double), ("gxx", ctypes.c_double), ("gxy", ctypes.c_double),
                 ("gyy", ctypes.c_double), ("R", ctypes.c_double), ("c_rel", ctypes.c_double)]
 
@@ -181,6 +181,9 @@ SIGNATURES = {
     "epdlb_observables": (ctypes.c_int, [_vp, ctypes.c_double, _P(epdlb_obs), _P(epdlb_particle), ctypes.c_int32,
                                          _P(ctypes.c_int32)]),
     "epdlb_sigma_delta": (ctypes.c_int, [_vp, _vp, _dp]),
+    "epdlb_track_particles": (ctypes.c_int, [_vp, ctypes.c_double, _P(epdlb_obs), _P(epdlb_particle), ctypes.c_int32,
+                                             _P(ctypes.c_int32)]),
+    "epdlb_track_reset": (ctypes.c_int, [_vp]),
     "epdlb_invert_densities": (ctypes.c_int, [_vp, _dp, ctypes.c_int32, ctypes.c_double, _P(epdlb_cg_info)]),
     "epdlb_cg_stats": (ctypes.c_int, [_vp, _P(epdlb_cg_info), _P(ctypes.c_int64)]),
     "epdlb_last_error": (ctypes.c_char_p, []),
@@ -377,9 +380,29 @@ def epdlb_observables(ctx, threshold, max_particles, shape=None):
     parts = []
     for k in range(min(o.n_particles, max_particles)):
         q = arr[k]
-        parts.append(dict(label=q.label, area=q.area, wraps=bool(q.wraps), content=q.content,
-                          centroid=(q.cx, q.cy), G=(q.gxx, q.gxy, q.gyy), R=q.R, c_rel=q.c_rel))
+        parts.append(_particle_dict(q))
     return dict(sigma=o.sigma, y2p=o.y2p, n_particles=o.n_particles, n_wrapping=o.n_wrapping), parts, lab
+
+
+def _particle_dict(q):
+    return dict(label=q.label, area=q.area, wraps=bool(q.wraps), content=q.content,
+                centroid=(q.cx, q.cy), G=(q.gxx, q.gxy, q.gyy), R=q.R, c_rel=q.c_rel)
+
+
+def epdlb_track_particles(ctx, threshold, max_events):
+    """(observables dict, list of new particles since the previous call in label order,
+    number of new particles)."""
+    o = epdlb_obs()
+    arr = (epdlb_particle * max_events)() if max_events > 0 else None
+    n = ctypes.c_int32(0)
+    _check(load_library().epdlb_track_particles(ctx, threshold, ctypes.byref(o), arr, max_events, ctypes.byref(n)),
+           "epdlb_track_particles")
+    ev = [_particle_dict(arr[k]) for k in range(min(n.value, max_events))]
+    return dict(sigma=o.sigma, y2p=o.y2p, n_particles=o.n_particles, n_wrapping=o.n_wrapping), ev, n.value
+
+
+def epdlb_track_reset(ctx):
+    _check(load_library().epdlb_track_reset(ctx), "epdlb_track_reset")
 
 
 def epdlb_sigma_delta(ctx_a, ctx_b):
@@ -547,6 +570,13 @@ class Simulation:
     def observables(self, threshold=0.5, max_particles=4096, labels=False):
         """sigma, Y_2^P and the particles of the current densities (Sec. III, IV)."""
         return epdlb_observables(self.ctx, threshold, max_particles, self.shape if labels else None)
+
+    def track_particles(self, threshold=0.5, max_events=4096):
+        """Observables and the particles nucleated since the previous call (Sec. IV)."""
+        return epdlb_track_particles(self.ctx, threshold, max_events)
+
+    def track_reset(self):
+        epdlb_track_reset(self.ctx)
 
     def sigma_delta(self, other):
         """sigma_Delta between this run's and another run's polymer densities (Sec. III)."""

@@ -171,6 +171,7 @@ struct epdlb_ctx {
   int64_t snap_exact = 0;     // exact steps taken when the snapshot was queued
   // observables scratch, allocated at the first epdlb_observables call
   unsigned char* obs = nullptr;
+  bool track_valid = false;   // the scratch holds the particle sites of a previous tracking sample
   // Phi -> omega inversion: device scratch (6 field sets, partials, results)
   // and a pinned pair of doubles for the host's decisions; allocated at
   // create (cg_invert = 1) or at the first epdlb_invert_densities call
@@ -1188,6 +1189,7 @@ int set_fields_group(epdlb_ctx* c, const double* const* omega) {
     if (omega[r]) CHK(init_lb(c, r));
   HIPCHK(hipStreamSynchronize(c->stream));
   c->seeded = true;
+  c->track_valid = false;
   if (c->p.density_mode == 1) CHK(nn_after_seed(c));
   return EPDLB_OK;
 }
@@ -1739,7 +1741,7 @@ namespace {
 // Scratch layout: labels, areas, wrap flags, counter (int32), per-site sums
 // (6 doubles), particle list (n/2 + 1 entries), block partials.
 struct ObsLayout {
-  size_t labels, area, wrap, count, sums, list, part, total;
+  size_t labels, area, wrap, count, sums, list, part, ov, prev, total;
   int cap, nblocks;
 };
 ObsLayout obs_layout(long n) {
@@ -1755,13 +1757,18 @@ ObsLayout obs_layout(long n) {
   o.sums = off; off = up(off + 48 * size_t(n));
   o.list = off; off = up(off + sizeof(obs::Particle) * size_t(o.cap));
   o.part = off; off = up(off + 16 * size_t(o.nblocks));
+  o.ov = off; off = up(off + 4 * size_t(n));
+  o.prev = off; off = up(off + size_t(n));
   o.total = off;
   return o;
 }
 
+// track: also mark each particle new (born) unless it covers a particle site
+// of the previous tracking sample, then keep this sample's particle sites.
+// all (may be null) receives every particle in label order.
 template <typename T>
 int observables_t(epdlb_ctx* c, double thr, epdlb_obs* out, epdlb_particle* particles, int max_particles,
-                  int32_t* labels) {
+                  int32_t* labels, bool track = false, std::vector<obs::Particle>* all = nullptr) {
   const epdlb_params& p = c->p;
   const long n = long(p.nx) * p.ny;
   const ObsLayout o = obs_layout(n);
@@ -1778,16 +1785,21 @@ int observables_t(epdlb_ctx* c, double thr, epdlb_obs* out, epdlb_particle* part
   double* sums = reinterpret_cast<double*>(b + o.sums);
   obs::Particle* list = reinterpret_cast<obs::Particle*>(b + o.list);
   double* part = reinterpret_cast<double*>(b + o.part);
+  int* ov = track ? reinterpret_cast<int*>(b + o.ov) : nullptr;
+  unsigned char* prev = b + o.prev;
   const T* phi = c->ptr<T>(c->L.phi);
   hipStream_t s = c->stream;
   const dim3 grid(unsigned(o.nblocks)), blk(256);
   hipLaunchKernelGGL(obs::k_obs_init<T>, grid, blk, 0, s, phi, n, p.nx, p.ny, thr, p.phi_P, L, part, area, wrap, sums,
-                     count);
+                     count, ov);
   hipLaunchKernelGGL(obs::k_ccl_merge, grid, blk, 0, s, L, n, p.nx, p.ny);
   hipLaunchKernelGGL(obs::k_ccl_compress, grid, blk, 0, s, L, n);
+  if (track && c->track_valid)
+    hipLaunchKernelGGL(obs::k_overlap, grid, blk, 0, s, (const int*)L, (const unsigned char*)prev, ov, n);
   hipLaunchKernelGGL(obs::k_particle_accum<T>, grid, blk, 0, s, phi, (const int*)L, n, p.nx, p.ny, area, sums, wrap);
   hipLaunchKernelGGL(obs::k_particle_list, grid, blk, 0, s, (const int*)L, (const int*)area, (const double*)sums,
-                     (const int*)wrap, n, p.nx, p.ny, count, list, o.cap);
+                     (const int*)wrap, (const int*)ov, n, p.nx, p.ny, count, list, o.cap);
+  if (track) hipLaunchKernelGGL(obs::k_store_prev, grid, blk, 0, s, (const int*)L, prev, n);
   HIPCHK(hipGetLastError());
   std::vector<double> hp(2 * size_t(o.nblocks));
   int cnt = 0;
@@ -1823,7 +1835,7 @@ int observables_t(epdlb_ctx* c, double thr, epdlb_obs* out, epdlb_particle* part
     r.label = q.label;
     r.area = q.area;
     r.wraps = q.wraps;
-    r.pad = 0;
+    r.born = q.born;
     r.content = q.content;
     r.cx = q.cx;
     r.cy = q.cy;
@@ -1833,6 +1845,8 @@ int observables_t(epdlb_ctx* c, double thr, epdlb_obs* out, epdlb_particle* part
     r.R = q.R;
     r.c_rel = q.c_rel;
   }
+  if (track) c->track_valid = true;
+  if (all) *all = std::move(hl);
   return EPDLB_OK;
 }
 
@@ -1871,6 +1885,47 @@ int epdlb_observables(epdlb_ctx* c, double threshold, epdlb_obs* out, epdlb_part
   HIPCHK(hipSetDevice(c->device));
   return c->p.precision == 0 ? observables_t<double>(c, threshold, out, particles, max_particles, labels)
                              : observables_t<float>(c, threshold, out, particles, max_particles, labels);
+}
+
+int epdlb_track_particles(epdlb_ctx* c, double threshold, epdlb_obs* out, epdlb_particle* events,
+                          int32_t max_events, int32_t* n_events) {
+  if (!c || !out || !n_events) return fail(EPDLB_EINVAL, "NULL argument");
+  if (max_events < 0 || (max_events > 0 && !events)) return fail(EPDLB_EINVAL, "bad event array");
+  if (!std::isfinite(threshold)) return fail(EPDLB_EINVAL, "non-finite threshold");
+  if (!c->seeded) return fail(EPDLB_ESTATE, "no state before seed/set_fields/set_state");
+  if (c->nrep != 1) return fail(EPDLB_EINVAL, "tracking a batch replica group is not supported");
+  HIPCHK(hipSetDevice(c->device));
+  std::vector<obs::Particle> all;
+  CHK(c->p.precision == 0 ? observables_t<double>(c, threshold, out, nullptr, 0, nullptr, true, &all)
+                          : observables_t<float>(c, threshold, out, nullptr, 0, nullptr, true, &all));
+  int k = 0;
+  for (const obs::Particle& q : all) {
+    if (!q.born) continue;
+    if (k < max_events) {
+      epdlb_particle& r = events[k];
+      r.label = q.label;
+      r.area = q.area;
+      r.wraps = q.wraps;
+      r.born = 1;
+      r.content = q.content;
+      r.cx = q.cx;
+      r.cy = q.cy;
+      r.gxx = q.gxx;
+      r.gxy = q.gxy;
+      r.gyy = q.gyy;
+      r.R = q.R;
+      r.c_rel = q.c_rel;
+    }
+    ++k;
+  }
+  *n_events = k;
+  return EPDLB_OK;
+}
+
+int epdlb_track_reset(epdlb_ctx* c) {
+  if (!c) return fail(EPDLB_EINVAL, "ctx is NULL");
+  c->track_valid = false;
+  return EPDLB_OK;
 }
 
 int epdlb_sigma_delta(epdlb_ctx* a, epdlb_ctx* b, double* out) {

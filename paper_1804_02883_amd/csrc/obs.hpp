@@ -9,6 +9,8 @@
 //   evaluated as the weighted covariance (the double sum over site pairs
 //   equals it), from minimum-image offsets to the particle's label site;
 //   R and c_rel from its eigenvalues (Eqs. asph, rel_asph).
+//   nucleation events (Sec. IV, nucleation stage): a particle none of whose
+//   sites was a particle site at the previous tracking sample is new.
 // Phi_P = Phi_A + Phi_B is formed in the storage precision; sums in FP64.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -47,18 +49,21 @@ __device__ __forceinline__ void block_pair(double a, double b, double* part) {
 }
 
 // Labels (site index on the particles, -1 elsewhere), the block partial sums
-// of |Phi_P - phibar_P| and y^2 Phi_P, and cleared per-site accumulators.
+// of |Phi_P - phibar_P| and y^2 Phi_P, and cleared per-site accumulators
+// (ov, the overlap flags of tracking, may be null).
 template <typename T>
 __global__ void __launch_bounds__(256) k_obs_init(const T* __restrict__ phi, long n, int nx, int ny, double thr,
                                                   double phibar, int* __restrict__ label, double* __restrict__ part,
                                                   int* __restrict__ area, int* __restrict__ wrap,
-                                                  double* __restrict__ sums, int* __restrict__ count) {
+                                                  double* __restrict__ sums, int* __restrict__ count,
+                                                  int* __restrict__ ov) {
   const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
   double s = 0.0, m = 0.0;
   if (i == 0) *count = 0;
   if (i < n) {
     area[i] = 0;
     wrap[i] = 0;
+    if (ov) ov[i] = 0;
 #pragma unroll
     for (int k = 0; k < 6; ++k) sums[6 * i + k] = 0.0;
     const T pP = phi[i] + phi[n + i];
@@ -186,15 +191,34 @@ __global__ void __launch_bounds__(256) k_particle_accum(const T* __restrict__ ph
   }
 }
 
+// Tracking: flags the particles (by label) that cover a site which was a
+// particle site at the previous sample.  Every writer stores the same value.
+__global__ void __launch_bounds__(256) k_overlap(const int* __restrict__ L, const unsigned char* __restrict__ prev,
+                                                 int* __restrict__ ov, long n) {
+  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n && prev[i]) {
+    const int key = L[i];
+    if (key >= 0) ov[key] = 1;
+  }
+}
+
+// Tracking: the particle sites of this sample, for the next one.
+__global__ void __launch_bounds__(256) k_store_prev(const int* __restrict__ L, unsigned char* __restrict__ prev,
+                                                    long n) {
+  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) prev[i] = L[i] >= 0 ? 1 : 0;
+}
+
 // One entry per particle (label sites), in arrival order; the host sorts.
 struct Particle {
-  int label, area, wraps, pad;
+  int label, area, wraps, born;
   double content, cx, cy, gxx, gxy, gyy, R, c_rel;
 };
 
 __global__ void __launch_bounds__(256) k_particle_list(const int* __restrict__ L, const int* __restrict__ area,
                                                        const double* __restrict__ sums, const int* __restrict__ wrap,
-                                                       long n, int nx, int ny, int* count, Particle* out, int cap) {
+                                                       const int* __restrict__ ov, long n, int nx, int ny, int* count,
+                                                       Particle* out, int cap) {
   const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
   const bool root = i < n && L[i] == int(i);
   // one counter update per wave
@@ -220,7 +244,7 @@ __global__ void __launch_bounds__(256) k_particle_list(const int* __restrict__ L
   p.label = int(i);
   p.area = area[i];
   p.wraps = wrap[i];
-  p.pad = 0;
+  p.born = ov ? (ov[i] == 0 ? 1 : 0) : 0;
   p.content = N;
   const int rx = int(i % nx), ry = int(i / nx);
   double cx = fmod(double(rx) + mx, double(nx));

@@ -144,3 +144,52 @@ def test_observables_after_steps():
     sim.sync()
     _compare(sim, p, 0)
     sim.close()
+
+
+def _disk(ny, nx, cy, cx, r, inside=0.8, outside=0.1):
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    d2 = ((yy - cy + ny / 2) % ny - ny / 2) ** 2 + ((xx - cx + nx / 2) % nx - nx / 2) ** 2
+    return np.where(d2 <= r * r, inside, outside)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_nucleation_tracking_vs_oracle(prec):
+    """A sequence of hand-built samples (set_state keeps the tracking sample):
+    first sample, one kept + two new + one vanished, a merge, a jump, a reset;
+    the new particles agree with the oracle's events on the stored densities."""
+    say(f"[tracking] 64x32 prec={prec}")
+    nx, ny = 64, 32
+    p = preset("cfg1", nx=nx, ny=ny, precision=prec)
+    d = lambda cy, cx, r: _disk(ny, nx, cy, cx, r)  # noqa: E731
+    samples = [
+        np.maximum(d(8, 8, 3), d(20, 40, 3)),
+        np.maximum.reduce([d(8, 9, 3), d(26, 4, 2), d(4, 52, 2.5)]),
+        np.maximum.reduce([d(8, 9, 3), d(8, 14, 3), d(4, 52, 2.5), d(26, 4, 2)]),
+        np.maximum(d(8, 9, 3), d(20, 30, 3)),
+    ]
+    sim = _sim(p)
+    prev = None
+    counts = []
+    for k, phiP in enumerate(samples):
+        sim.set_state(*_state(p, phiP))
+        obs, ev, n_ev = sim.track_particles(0.5)
+        cur = _stored_phiP(sim, prec)
+        ref = B.nucleation_events(prev, cur)
+        assert n_ev == len(ev) == len(ref), k
+        for g, r in zip(ev, ref):
+            assert (g["label"], g["area"]) == (r["label"], r["area"]), k
+            assert abs(g["content"] - r["content"]) <= 1e-12 * r["content"]
+            assert np.max(np.abs(np.array(g["centroid"]) - np.array(r["centroid"]))) <= 1e-10
+        assert obs["n_particles"] == len(B.particle_table(cur))
+        counts.append(n_ev)
+        prev = cur
+    assert counts == [2, 2, 0, 1]
+    # a truncated event list still reports the count
+    sim.track_reset()
+    obs, ev, n_ev = sim.track_particles(0.5, max_events=1)
+    assert n_ev == obs["n_particles"] == 2 and len(ev) == 1 and ev[0]["label"] == B.particle_table(prev)[0]["label"]
+    # set_fields starts a new run: every particle counts again
+    sim.set_fields(np.zeros((3, ny, nx)))
+    obs, ev, n_ev = sim.track_particles(0.5)
+    assert n_ev == obs["n_particles"] == 0
+    sim.close()
