@@ -374,6 +374,15 @@ int epdlb_batch_autotune(epdlb_batch* b, int32_t reps, const char* cache_path);
  * merged over the groups; see epdlb_profile_start / epdlb_profile_read. */
 int epdlb_batch_profile_start(epdlb_batch* b, int32_t max_launches);
 int epdlb_batch_profile_read(epdlb_batch* b, epdlb_kernel_stat* out, int32_t cap, int32_t* n_out);
+/* Observables and nucleation tracking of one replica, as epdlb_observables and
+ * epdlb_track_particles for a single context (after the queued steps: the
+ * batch stream is synchronised).  Each replica keeps its own tracking
+ * sample; seeding or setting a replica's fields starts it over. */
+int epdlb_batch_observables(epdlb_batch* b, int32_t replica, double threshold, epdlb_obs* out,
+                            epdlb_particle* particles, int32_t max_particles, int32_t* labels);
+int epdlb_batch_track_particles(epdlb_batch* b, int32_t replica, double threshold, epdlb_obs* out,
+                                epdlb_particle* events, int32_t max_events, int32_t* n_events);
+int epdlb_batch_track_reset(epdlb_batch* b, int32_t replica);
 /* Number of replica groups (grid shape, A fraction) and total lattice sites. */
 int epdlb_batch_info(epdlb_batch* b, int32_t* n_groups, int64_t* sites);
 void epdlb_batch_destroy(epdlb_batch* b);

@@ -184,6 +184,11 @@ SIGNATURES = {
     "epdlb_track_particles": (ctypes.c_int, [_vp, ctypes.c_double, _P(epdlb_obs), _P(epdlb_particle), ctypes.c_int32,
                                              _P(ctypes.c_int32)]),
     "epdlb_track_reset": (ctypes.c_int, [_vp]),
+    "epdlb_batch_observables": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_double, _P(epdlb_obs),
+                                               _P(epdlb_particle), ctypes.c_int32, _P(ctypes.c_int32)]),
+    "epdlb_batch_track_particles": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_double, _P(epdlb_obs),
+                                                   _P(epdlb_particle), ctypes.c_int32, _P(ctypes.c_int32)]),
+    "epdlb_batch_track_reset": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "epdlb_invert_densities": (ctypes.c_int, [_vp, _dp, ctypes.c_int32, ctypes.c_double, _P(epdlb_cg_info)]),
     "epdlb_cg_stats": (ctypes.c_int, [_vp, _P(epdlb_cg_info), _P(ctypes.c_int64)]),
     "epdlb_last_error": (ctypes.c_char_p, []),
@@ -364,9 +369,10 @@ def epdlb_read_diag(ctx):
     return _diag_dict(d)
 
 
-def epdlb_observables(ctx, threshold, max_particles, shape=None):
+def epdlb_observables(ctx, threshold, max_particles, shape=None, replica=None):
     """(dict of sigma, y2p, n_particles, n_wrapping; list of particle dicts in label
-    order; labels [ny, nx] int32 or None).  Labels are returned when `shape` is given."""
+    order; labels [ny, nx] int32 or None).  Labels are returned when `shape` is given.
+    With `replica`, ctx is a batch and the replica's observables are measured."""
     import numpy as np
     o = epdlb_obs()
     arr = (epdlb_particle * max_particles)() if max_particles > 0 else None
@@ -375,8 +381,12 @@ def epdlb_observables(ctx, threshold, max_particles, shape=None):
     if shape is not None:
         lab = np.empty(shape, dtype=np.int32)
         lab_ptr = lab.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
-    _check(load_library().epdlb_observables(ctx, threshold, ctypes.byref(o), arr, max_particles, lab_ptr),
-           "epdlb_observables")
+    if replica is None:
+        _check(load_library().epdlb_observables(ctx, threshold, ctypes.byref(o), arr, max_particles, lab_ptr),
+               "epdlb_observables")
+    else:
+        _check(load_library().epdlb_batch_observables(ctx, replica, threshold, ctypes.byref(o), arr, max_particles,
+                                                      lab_ptr), "epdlb_batch_observables")
     parts = []
     for k in range(min(o.n_particles, max_particles)):
         q = arr[k]
@@ -389,14 +399,18 @@ def _particle_dict(q):
                 centroid=(q.cx, q.cy), G=(q.gxx, q.gxy, q.gyy), R=q.R, c_rel=q.c_rel)
 
 
-def epdlb_track_particles(ctx, threshold, max_events):
+def epdlb_track_particles(ctx, threshold, max_events, replica=None):
     """(observables dict, list of new particles since the previous call in label order,
-    number of new particles)."""
+    number of new particles).  With `replica`, ctx is a batch."""
     o = epdlb_obs()
     arr = (epdlb_particle * max_events)() if max_events > 0 else None
     n = ctypes.c_int32(0)
-    _check(load_library().epdlb_track_particles(ctx, threshold, ctypes.byref(o), arr, max_events, ctypes.byref(n)),
-           "epdlb_track_particles")
+    if replica is None:
+        _check(load_library().epdlb_track_particles(ctx, threshold, ctypes.byref(o), arr, max_events,
+                                                    ctypes.byref(n)), "epdlb_track_particles")
+    else:
+        _check(load_library().epdlb_batch_track_particles(ctx, replica, threshold, ctypes.byref(o), arr, max_events,
+                                                          ctypes.byref(n)), "epdlb_batch_track_particles")
     ev = [_particle_dict(arr[k]) for k in range(min(n.value, max_events))]
     return dict(sigma=o.sigma, y2p=o.y2p, n_particles=o.n_particles, n_wrapping=o.n_wrapping), ev, n.value
 
@@ -870,6 +884,18 @@ class Batch:
 
     def seed(self, seeds, sigma):
         epdlb_batch_seed(self.b, seeds, sigma)
+
+    def observables(self, replica, threshold=0.5, max_particles=4096, labels=False):
+        """sigma, Y_2^P and the particles of one replica (Sec. III, IV)."""
+        return epdlb_observables(self.b, threshold, max_particles, self.shapes[replica] if labels else None,
+                                 replica=replica)
+
+    def track_particles(self, replica, threshold=0.5, max_events=4096):
+        """Observables of one replica and its particles nucleated since its previous call."""
+        return epdlb_track_particles(self.b, threshold, max_events, replica=replica)
+
+    def track_reset(self, replica):
+        _check(load_library().epdlb_batch_track_reset(self.b, replica), "epdlb_batch_track_reset")
 
     def set_fields(self, replica, omega):
         ny, nx = self.shapes[replica]

@@ -171,7 +171,8 @@ struct epdlb_ctx {
   int64_t snap_exact = 0;     // exact steps taken when the snapshot was queued
   // observables scratch, allocated at the first epdlb_observables call
   unsigned char* obs = nullptr;
-  bool track_valid = false;   // the scratch holds the particle sites of a previous tracking sample
+  // per replica: the scratch holds the particle sites of a previous tracking sample
+  std::vector<unsigned char> track_valid;
   // Phi -> omega inversion: device scratch (6 field sets, partials, results)
   // and a pinned pair of doubles for the host's decisions; allocated at
   // create (cg_invert = 1) or at the first epdlb_invert_densities call
@@ -1178,10 +1179,12 @@ int init_lb(epdlb_ctx* c, int r) {
 int set_fields_group(epdlb_ctx* c, const double* const* omega) {
   HIPCHK(hipSetDevice(c->device));
   const size_t n = size_t(c->p.nx) * c->p.ny;
+  if (c->track_valid.size() != size_t(c->nrep)) c->track_valid.assign(size_t(c->nrep), 0);
   for (int r = 0; r < c->nrep; ++r) {
     if (!omega[r]) continue;
     CHK(upload(c, c->roff(r) + c->L.omega[c->cur], omega[r], 3 * n));
     CHK(reset_scal(c, r));
+    c->track_valid[size_t(r)] = 0;  // a new run for tracking
   }
   CHK(compute_stats(c));
   CHK(c->p.precision == 0 ? stage_densities<double>(c, false) : stage_densities<float>(c, false));
@@ -1189,7 +1192,6 @@ int set_fields_group(epdlb_ctx* c, const double* const* omega) {
     if (omega[r]) CHK(init_lb(c, r));
   HIPCHK(hipStreamSynchronize(c->stream));
   c->seeded = true;
-  c->track_valid = false;
   if (c->p.density_mode == 1) CHK(nn_after_seed(c));
   return EPDLB_OK;
 }
@@ -1744,7 +1746,7 @@ struct ObsLayout {
   size_t labels, area, wrap, count, sums, list, part, ov, prev, total;
   int cap, nblocks;
 };
-ObsLayout obs_layout(long n) {
+ObsLayout obs_layout(long n, int nrep) {
   auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
   ObsLayout o{};
   o.nblocks = int((n + 255) / 256);
@@ -1758,20 +1760,22 @@ ObsLayout obs_layout(long n) {
   o.list = off; off = up(off + sizeof(obs::Particle) * size_t(o.cap));
   o.part = off; off = up(off + 16 * size_t(o.nblocks));
   o.ov = off; off = up(off + 4 * size_t(n));
-  o.prev = off; off = up(off + size_t(n));
+  o.prev = off; off = up(off + size_t(n) * size_t(nrep));
   o.total = off;
   return o;
 }
 
-// track: also mark each particle new (born) unless it covers a particle site
-// of the previous tracking sample, then keep this sample's particle sites.
-// all (may be null) receives every particle in label order.
+// Observables of replica r of the context.  track: also mark each particle
+// new (born) unless it covers a particle site of the replica's previous
+// tracking sample, then keep this sample's particle sites.  all (may be
+// null) receives every particle in label order.
 template <typename T>
-int observables_t(epdlb_ctx* c, double thr, epdlb_obs* out, epdlb_particle* particles, int max_particles,
+int observables_t(epdlb_ctx* c, int r, double thr, epdlb_obs* out, epdlb_particle* particles, int max_particles,
                   int32_t* labels, bool track = false, std::vector<obs::Particle>* all = nullptr) {
-  const epdlb_params& p = c->p;
+  const epdlb_params& p = c->rp[size_t(r)];
   const long n = long(p.nx) * p.ny;
-  const ObsLayout o = obs_layout(n);
+  const ObsLayout o = obs_layout(n, c->nrep);
+  if (c->track_valid.size() != size_t(c->nrep)) c->track_valid.assign(size_t(c->nrep), 0);
   if (!c->obs) {
     void* m = nullptr;
     if (hipMalloc(&m, o.total) != hipSuccess) return fail(EPDLB_ENOMEM, "observables scratch allocation failed");
@@ -1786,15 +1790,15 @@ int observables_t(epdlb_ctx* c, double thr, epdlb_obs* out, epdlb_particle* part
   obs::Particle* list = reinterpret_cast<obs::Particle*>(b + o.list);
   double* part = reinterpret_cast<double*>(b + o.part);
   int* ov = track ? reinterpret_cast<int*>(b + o.ov) : nullptr;
-  unsigned char* prev = b + o.prev;
-  const T* phi = c->ptr<T>(c->L.phi);
+  unsigned char* prev = b + o.prev + size_t(r) * size_t(n);
+  const T* phi = c->ptr<T>(c->roff(r) + c->L.phi);
   hipStream_t s = c->stream;
   const dim3 grid(unsigned(o.nblocks)), blk(256);
   hipLaunchKernelGGL(obs::k_obs_init<T>, grid, blk, 0, s, phi, n, p.nx, p.ny, thr, p.phi_P, L, part, area, wrap, sums,
                      count, ov);
   hipLaunchKernelGGL(obs::k_ccl_merge, grid, blk, 0, s, L, n, p.nx, p.ny);
   hipLaunchKernelGGL(obs::k_ccl_compress, grid, blk, 0, s, L, n);
-  if (track && c->track_valid)
+  if (track && c->track_valid[size_t(r)])
     hipLaunchKernelGGL(obs::k_overlap, grid, blk, 0, s, (const int*)L, (const unsigned char*)prev, ov, n);
   hipLaunchKernelGGL(obs::k_particle_accum<T>, grid, blk, 0, s, phi, (const int*)L, n, p.nx, p.ny, area, sums, wrap);
   hipLaunchKernelGGL(obs::k_particle_list, grid, blk, 0, s, (const int*)L, (const int*)area, (const double*)sums,
@@ -1845,8 +1849,42 @@ int observables_t(epdlb_ctx* c, double thr, epdlb_obs* out, epdlb_particle* part
     r.R = q.R;
     r.c_rel = q.c_rel;
   }
-  if (track) c->track_valid = true;
+  if (track) c->track_valid[size_t(r)] = 1;
   if (all) *all = std::move(hl);
+  return EPDLB_OK;
+}
+
+// Observables of replica r with tracking; the new particles go to events.
+int track_replica(epdlb_ctx* c, int r, double threshold, epdlb_obs* out, epdlb_particle* events, int max_events,
+                  int32_t* n_events) {
+  if (!out || !n_events) return fail(EPDLB_EINVAL, "NULL argument");
+  if (max_events < 0 || (max_events > 0 && !events)) return fail(EPDLB_EINVAL, "bad event array");
+  if (!std::isfinite(threshold)) return fail(EPDLB_EINVAL, "non-finite threshold");
+  HIPCHK(hipSetDevice(c->device));
+  std::vector<obs::Particle> all;
+  CHK(c->p.precision == 0 ? observables_t<double>(c, r, threshold, out, nullptr, 0, nullptr, true, &all)
+                          : observables_t<float>(c, r, threshold, out, nullptr, 0, nullptr, true, &all));
+  int k = 0;
+  for (const obs::Particle& q : all) {
+    if (!q.born) continue;
+    if (k < max_events) {
+      epdlb_particle& e = events[k];
+      e.label = q.label;
+      e.area = q.area;
+      e.wraps = q.wraps;
+      e.born = 1;
+      e.content = q.content;
+      e.cx = q.cx;
+      e.cy = q.cy;
+      e.gxx = q.gxx;
+      e.gxy = q.gxy;
+      e.gyy = q.gyy;
+      e.R = q.R;
+      e.c_rel = q.c_rel;
+    }
+    ++k;
+  }
+  *n_events = k;
   return EPDLB_OK;
 }
 
@@ -1883,48 +1921,55 @@ int epdlb_observables(epdlb_ctx* c, double threshold, epdlb_obs* out, epdlb_part
   if (!std::isfinite(threshold)) return fail(EPDLB_EINVAL, "non-finite threshold");
   if (!c->seeded) return fail(EPDLB_ESTATE, "no state before seed/set_fields/set_state");
   HIPCHK(hipSetDevice(c->device));
-  return c->p.precision == 0 ? observables_t<double>(c, threshold, out, particles, max_particles, labels)
-                             : observables_t<float>(c, threshold, out, particles, max_particles, labels);
+  return c->p.precision == 0 ? observables_t<double>(c, 0, threshold, out, particles, max_particles, labels)
+                             : observables_t<float>(c, 0, threshold, out, particles, max_particles, labels);
 }
 
 int epdlb_track_particles(epdlb_ctx* c, double threshold, epdlb_obs* out, epdlb_particle* events,
                           int32_t max_events, int32_t* n_events) {
-  if (!c || !out || !n_events) return fail(EPDLB_EINVAL, "NULL argument");
-  if (max_events < 0 || (max_events > 0 && !events)) return fail(EPDLB_EINVAL, "bad event array");
-  if (!std::isfinite(threshold)) return fail(EPDLB_EINVAL, "non-finite threshold");
+  if (!c) return fail(EPDLB_EINVAL, "NULL argument");
   if (!c->seeded) return fail(EPDLB_ESTATE, "no state before seed/set_fields/set_state");
-  if (c->nrep != 1) return fail(EPDLB_EINVAL, "tracking a batch replica group is not supported");
-  HIPCHK(hipSetDevice(c->device));
-  std::vector<obs::Particle> all;
-  CHK(c->p.precision == 0 ? observables_t<double>(c, threshold, out, nullptr, 0, nullptr, true, &all)
-                          : observables_t<float>(c, threshold, out, nullptr, 0, nullptr, true, &all));
-  int k = 0;
-  for (const obs::Particle& q : all) {
-    if (!q.born) continue;
-    if (k < max_events) {
-      epdlb_particle& r = events[k];
-      r.label = q.label;
-      r.area = q.area;
-      r.wraps = q.wraps;
-      r.born = 1;
-      r.content = q.content;
-      r.cx = q.cx;
-      r.cy = q.cy;
-      r.gxx = q.gxx;
-      r.gxy = q.gxy;
-      r.gyy = q.gyy;
-      r.R = q.R;
-      r.c_rel = q.c_rel;
-    }
-    ++k;
-  }
-  *n_events = k;
-  return EPDLB_OK;
+  return track_replica(c, 0, threshold, out, events, max_events, n_events);
 }
 
 int epdlb_track_reset(epdlb_ctx* c) {
   if (!c) return fail(EPDLB_EINVAL, "ctx is NULL");
-  c->track_valid = false;
+  c->track_valid.assign(size_t(c->nrep), 0);
+  return EPDLB_OK;
+}
+
+int epdlb_batch_observables(epdlb_batch* b, int32_t replica, double threshold, epdlb_obs* out,
+                            epdlb_particle* particles, int32_t max_particles, int32_t* labels) {
+  epdlb_ctx* c;
+  int i;
+  CHK(batch_replica(b, replica, &c, &i));
+  if (!out) return fail(EPDLB_EINVAL, "NULL argument");
+  if (max_particles < 0 || (max_particles > 0 && !particles)) return fail(EPDLB_EINVAL, "bad particle array");
+  if (!std::isfinite(threshold)) return fail(EPDLB_EINVAL, "non-finite threshold");
+  if (!c->seeded) return fail(EPDLB_ESTATE, "no state before seed/set_fields");
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  return c->p.precision == 0 ? observables_t<double>(c, i, threshold, out, particles, max_particles, labels)
+                             : observables_t<float>(c, i, threshold, out, particles, max_particles, labels);
+}
+
+int epdlb_batch_track_particles(epdlb_batch* b, int32_t replica, double threshold, epdlb_obs* out,
+                                epdlb_particle* events, int32_t max_events, int32_t* n_events) {
+  epdlb_ctx* c;
+  int i;
+  CHK(batch_replica(b, replica, &c, &i));
+  if (!c->seeded) return fail(EPDLB_ESTATE, "no state before seed/set_fields");
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  return track_replica(c, i, threshold, out, events, max_events, n_events);
+}
+
+int epdlb_batch_track_reset(epdlb_batch* b, int32_t replica) {
+  epdlb_ctx* c;
+  int i;
+  CHK(batch_replica(b, replica, &c, &i));
+  if (c->track_valid.size() != size_t(c->nrep)) c->track_valid.assign(size_t(c->nrep), 0);
+  c->track_valid[size_t(i)] = 0;
   return EPDLB_OK;
 }
 

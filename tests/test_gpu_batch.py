@@ -113,3 +113,56 @@ def test_cfg4_manifest_two_steps():
         phi = b.densities(r)
         assert abs(phi.sum(axis=0).mean() - 1) < 1e-6
     b.close()
+
+
+def _wells(ny, nx, centres, depth=0.2):
+    """Potentials with wells that gather the polymer into disks (Phi_P >= 0.5)."""
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    blob = np.zeros((ny, nx))
+    for cy, cx, r in centres:
+        d2 = ((yy - cy + ny / 2) % ny - ny / 2) ** 2 + ((xx - cx + nx / 2) % nx - nx / 2) ** 2
+        blob = np.maximum(blob, (d2 <= r * r).astype(float))
+    return np.stack([-depth * blob, -depth * blob, depth * blob])
+
+
+def test_batch_observables_and_tracking_per_replica():
+    """Replicas of one group (two 64x64) and of another (128x64), FP64: each
+    replica's particles match the oracle on its stored densities; tracking
+    keeps one sample per replica (a reset of one replica leaves the others)."""
+    _need_gpu()
+    from oracle import observables_oracle as B
+    from paper_1804_02883_amd import Batch
+    params = [base_params(64, 64, 16, 0.5, 0.1, "L", 1e-5, precision=0),
+              base_params(64, 64, 16, 0.5, 0.1, "L", 1e-5, precision=0),
+              base_params(128, 64, 16, 0.5, 0.1, "L", 1e-5, precision=0)]
+    wells = [[(16, 16, 5), (40, 44, 4)], [(10, 50, 4), (30, 20, 6), (52, 8, 3)], [(20, 100, 5), (44, 30, 4)]]
+    say("[batch] observables and tracking, 3 replicas in 2 groups")
+    b = Batch(params)
+    b.seed([1, 2, 3], 1e-3)
+    for r, (p, wl) in enumerate(zip(params, wells)):
+        b.set_fields(r, _wells(p["ny"], p["nx"], wl))
+    prev = []
+    for r, p in enumerate(params):
+        phiP = b.densities(r)[0] + b.densities(r)[1]
+        obs, parts, lab = b.observables(r, labels=True)
+        table = B.particle_table(phiP)
+        assert np.array_equal(lab.astype(np.int64), B.label_particles(phiP)), r
+        assert obs["n_particles"] == len(table) == len(wells[r]) == len(parts), r
+        for g, t in zip(parts, table):
+            assert (g["label"], g["area"]) == (t["label"], t["area"])
+            assert abs(g["content"] - t["content"]) <= 1e-12 * t["content"]
+        assert abs(obs["sigma"] - B.sigma(b.densities(r), p["phi_P"])) <= 1e-12 * obs["sigma"]
+        # first tracking sample of each replica: every particle is new
+        _, ev, n_ev = b.track_particles(r)
+        assert n_ev == len(table) and [e["label"] for e in ev] == [t["label"] for t in table]
+        prev.append(phiP)
+    b.step(5)
+    b.sync()
+    b.track_reset(1)
+    for r in range(3):
+        phiP = b.densities(r)[0] + b.densities(r)[1]
+        _, ev, n_ev = b.track_particles(r)
+        ref = B.nucleation_events(None if r == 1 else prev[r], phiP)
+        assert n_ev == len(ref) == (len(wells[r]) if r == 1 else 0), r
+        assert [e["label"] for e in ev] == [t["label"] for t in ref]
+    b.close()
