@@ -43,13 +43,13 @@ METRIC = "lattice site-updates/s per hybrid step, plain vs surrogate at <=1e-3 d
 _PROP_FILES = ("fft.hpp", "kernels.hpp")
 _NN_FILES = ("kernels.hpp", "nn.hpp")
 MEASURED_TRAFFIC = {
-    ("cfg3", "prop_col"): dict(bytes_per_launch=17274966, files=_PROP_FILES,
-                               source_sha256="60a1c33677698e8cd0df1248651bc262941b567cf5c079d3f45151329679aab5"),
-    ("cfg3", "prop_row"): dict(bytes_per_launch=16033645, files=_PROP_FILES,
-                               source_sha256="60a1c33677698e8cd0df1248651bc262941b567cf5c079d3f45151329679aab5"),
+    ("cfg3", "prop_col"): dict(bytes_per_launch=17284328, files=_PROP_FILES,
+                               source_sha256="dfeadbf448cd9fe2f65ec00e536070e07a831eff76acf5b0ff744a9dcb1f1e1e"),
+    ("cfg3", "prop_row"): dict(bytes_per_launch=16012374, files=_PROP_FILES,
+                               source_sha256="dfeadbf448cd9fe2f65ec00e536070e07a831eff76acf5b0ff744a9dcb1f1e1e"),
     # mean over the two 64 -> 64 launches of a surrogate step
-    ("cfg5q", "nn_conv"): dict(bytes_per_launch=63995971, files=_NN_FILES,
-                               source_sha256="6c686eb4ac93d791f85bb8afe472a53f44bbcf97b01ec2803006e021ae1fbd91"),
+    ("cfg5q", "nn_conv"): dict(bytes_per_launch=64014263, files=_NN_FILES,
+                               source_sha256="b54800d0cf58cdfef51c01d3158fa5daf81fddb71245db8ac26d93bce56d3d26"),
 }
 
 

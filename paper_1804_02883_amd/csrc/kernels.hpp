@@ -87,14 +87,28 @@ __device__ __forceinline__ void block_partial(double (&v)[NV], double* red, doub
 }
 
 // Sums nslots partials of NV values each, in slot order, over one block.
+// Each thread loads four of its slots at a time before adding them in order,
+// so the loads of a batch are in flight together.
 template <int NV>
 __device__ __forceinline__ void sum_partials(const double* partials, int nslots, double (&acc)[NV],
                                              double* red) {
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-  for (int s = threadIdx.x; s < nslots; s += blockDim.x)
+  const int step = blockDim.x;
+  for (int s0 = threadIdx.x; s0 < nslots; s0 += 4 * step) {
+    double v[4][NV];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] += partials[s * NV + i];
+    for (int k = 0; k < 4; ++k) {
+      const int s = s0 + k * step;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) v[k][i] = s < nslots ? partials[s * NV + i] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (s0 + k * step < nslots)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[i] += v[k][i];
+  }
   block_sum<NV>(acc, red);
 }
 
@@ -568,25 +582,38 @@ __device__ __forceinline__ void advect_site(const T (&sIn)[8][kHY][kHX], int lx,
 }
 
 // Loads the tile at (tx0, ty0) with a halo of 2 into sIn (velocities zero
-// when the flow does not advect).
+// when the flow does not advect).  Launched with kTX * kTY threads; every
+// thread issues all its loads before the first LDS write, so the block waits
+// for one memory round trip instead of one per pass.
 template <typename T>
 __device__ __forceinline__ void load_advect_tile(const UpdArgs<T>& P, int tx0, int ty0, T (&sIn)[8][kHY][kHX]) {
-  for (int e = threadIdx.x; e < kHX * kHY; e += blockDim.x) {
-    const int lx = e % kHX, ly = e / kHX;
-    const int gx = (tx0 + lx - 2 + P.nx) & (P.nx - 1);
-    const int gy = (ty0 + ly - 2 + P.ny) & (P.ny - 1);
-    const long gi = long(gy) * P.nx + gx;
+  constexpr int kThr = kTX * kTY, kIt = (kHX * kHY + kThr - 1) / kThr;
+  T v[kIt][8];
+  long gi[kIt];
 #pragma unroll
-    for (int I = 0; I < 3; ++I) {
-      sIn[I][ly][lx] = P.phi[I * P.n + gi];
-      sIn[3 + I][ly][lx] = P.w[I * P.n + gi];
+  for (int it = 0; it < kIt; ++it) {
+    const int e = threadIdx.x + it * kThr;
+    if (e < kHX * kHY) {
+      const int lx = e % kHX, ly = e / kHX;
+      const int gx = (tx0 + lx - 2 + P.nx) & (P.nx - 1);
+      const int gy = (ty0 + ly - 2 + P.ny) & (P.ny - 1);
+      gi[it] = long(gy) * P.nx + gx;
+#pragma unroll
+      for (int I = 0; I < 3; ++I) {
+        v[it][I] = P.phi[I * P.n + gi[it]];
+        v[it][3 + I] = P.w[I * P.n + gi[it]];
+      }
+      v[it][6] = P.advect ? P.u[gi[it]] : T(0);
+      v[it][7] = P.advect ? P.u[P.n + gi[it]] : T(0);
     }
-    if (P.advect) {
-      sIn[6][ly][lx] = P.u[gi];
-      sIn[7][ly][lx] = P.u[P.n + gi];
-    } else {
-      sIn[6][ly][lx] = T(0);
-      sIn[7][ly][lx] = T(0);
+  }
+#pragma unroll
+  for (int it = 0; it < kIt; ++it) {
+    const int e = threadIdx.x + it * kThr;
+    if (e < kHX * kHY) {
+      const int lx = e % kHX, ly = e / kHX;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) sIn[k][ly][lx] = v[it][k];
     }
   }
 }

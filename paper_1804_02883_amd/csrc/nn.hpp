@@ -1003,10 +1003,23 @@ __global__ void __launch_bounds__(256) k_nn_norm(NormArgs<T> P) {
     }
   }
   {
+    // four slots per thread in flight at a time, added in slot order
     double acc[2] = {0.0, 0.0};
-    for (int s = threadIdx.x; s < P.nslots; s += blockDim.x) {
-      acc[0] += P.part[2 * s];
-      acc[1] += P.part[2 * s + 1];
+    const int step = blockDim.x;
+    for (int s0 = threadIdx.x; s0 < P.nslots; s0 += 4 * step) {
+      double v[4][2];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int s = s0 + k * step;
+        v[k][0] = s < P.nslots ? P.part[2 * s] : 0.0;
+        v[k][1] = s < P.nslots ? P.part[2 * s + 1] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (s0 + k * step < P.nslots) {
+          acc[0] += v[k][0];
+          acc[1] += v[k][1];
+        }
     }
     nn_block_reduce<2, 2>(acc, red);
     if (threadIdx.x == 0) {
