@@ -299,8 +299,8 @@ def main():
     args = ap.parse_args()
     args.steps_given = args.steps is not None
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "sharding over several GPUs is designed but not built", file=sys.stderr)
+        print(f"bench.py: the benchmark runs on one GPU (asked for --gpus {args.gpus}); "
+              "the library has no multi-GPU sharding", file=sys.stderr)
         sys.exit(2)
 
     import torch
