@@ -43,13 +43,13 @@ METRIC = "lattice site-updates/s per hybrid step, plain vs surrogate at <=1e-3 d
 _PROP_FILES = ("fft.hpp", "kernels.hpp")
 _NN_FILES = ("kernels.hpp", "nn.hpp")
 MEASURED_TRAFFIC = {
-    ("cfg3", "prop_col"): dict(bytes_per_launch=17284328, files=_PROP_FILES,
-                               source_sha256="dfeadbf448cd9fe2f65ec00e536070e07a831eff76acf5b0ff744a9dcb1f1e1e"),
-    ("cfg3", "prop_row"): dict(bytes_per_launch=16012374, files=_PROP_FILES,
-                               source_sha256="dfeadbf448cd9fe2f65ec00e536070e07a831eff76acf5b0ff744a9dcb1f1e1e"),
+    ("cfg3", "prop_col"): dict(bytes_per_launch=17286289, files=_PROP_FILES,
+                               source_sha256="5c589c90c06f05169003f4394270b5a3fa1439f2fc85793fce6a43eb161ab220"),
+    ("cfg3", "prop_row"): dict(bytes_per_launch=16019178, files=_PROP_FILES,
+                               source_sha256="5c589c90c06f05169003f4394270b5a3fa1439f2fc85793fce6a43eb161ab220"),
     # mean over the two 64 -> 64 launches of a surrogate step
-    ("cfg5q", "nn_conv"): dict(bytes_per_launch=64014263, files=_NN_FILES,
-                               source_sha256="b54800d0cf58cdfef51c01d3158fa5daf81fddb71245db8ac26d93bce56d3d26"),
+    ("cfg5q", "nn_conv"): dict(bytes_per_launch=64002469, files=_NN_FILES,
+                               source_sha256="c1ec3945833900cb230db730d2f732425578f7cc5e97f75bbdb2bcb38cb29da8"),
 }
 
 
