@@ -58,6 +58,9 @@ READINGS = {
     "R23": "Stopping: sqrt(sum_I sum_r (Phi~_I - Phi_I[omega])^2 / (nx ny)) < N_tr (1e-8), the "
            "three fields together; start from the auxiliary-convected omega (comment 1); "
            "after cg_max_iter iterations the last iterate is used unconverged.",
+    "R25": "Optional diagonal preconditioning of the inversion (cg_precond = 1; the paper's "
+           "iteration is plain): directions from s divided by the local response "
+           "(N Phi_A, N Phi_B, Phi_S) at the current iterate; same fixed point and stopping test.",
 }
 
 PARITY_UNPINNED = ()
@@ -510,7 +513,15 @@ def secant_root(alpha_t, delta0, delta_t):
     return alpha_t * delta0 / curv if curv > 0.0 else alpha_t
 
 
-def invert_densities(phi_target, omega0, p, tol=1e-8, max_iter=1000):
+def local_response(phi, p):
+    """Diagonal of the density response used to precondition the inversion
+    (reading R25): N Phi_A, N Phi_B for the chain (the potential enters the
+    propagator multiplied by N) and Phi_S for the solvent (Eq. phi_s)."""
+    N = p["n_contour"]
+    return np.stack([N * phi[0], N * phi[1], phi[2]])
+
+
+def invert_densities(phi_target, omega0, p, tol=1e-8, max_iter=1000, precond=0):
     """Potentials reproducing the composition phi_target (App. C comments 2 and 3).
 
     Nonlinear conjugate gradients with the Fletcher-Reeves factor on the
@@ -521,45 +532,54 @@ def invert_densities(phi_target, omega0, p, tol=1e-8, max_iter=1000):
     omega + alpha_t d and takes the secant root
     alpha = alpha_t (d . s) / (d . s - d . s_t).  Stops when the RMS residual
     over the three fields (reading R23) is below tol.
+    precond = 1 (reading R25): the directions are built from z = s / m, m the
+    local response at the current iterate, and the factor is (s.z)_{k+1} /
+    (s.z)_k; the line search and the stopping test are unchanged.
     Returns dict(omega, phi, iters, evals, restarts, resid0, resid, converged).
     """
     n = p["nx"] * p["ny"]
     x = np.array(omega0, dtype=np.float64, copy=True)
 
     def descent(w):
-        return densities(w, p)["phi"] - phi_target
+        ph = densities(w, p)["phi"]
+        return ph - phi_target, ph
 
-    s = descent(x)
+    def scaled(s, ph):
+        return s / local_response(ph, p) if precond else s
+
+    s, ph = descent(x)
     evals = 1
     r2 = float(np.sum(s * s))
     resid0 = np.sqrt(r2 / n)
     out = dict(iters=0, restarts=0, resid0=resid0, resid=resid0, converged=resid0 < tol)
     if out["converged"]:
-        return dict(out, omega=x, phi=s + phi_target, evals=evals)
-    d = s.copy()
+        return dict(out, omega=x, phi=ph, evals=evals)
+    z = scaled(s, ph)
+    sz = float(np.sum(s * z))
+    d = z.copy()
     alpha_t = 1.0
     for it in range(1, max_iter + 1):
         delta0 = float(np.sum(d * s))
         if not delta0 > 0.0:
-            d = s.copy()
-            delta0 = r2
+            d = z.copy()
+            delta0 = sz
             out["restarts"] += 1
-        delta_t = float(np.sum(d * descent(x + alpha_t * d)))
+        delta_t = float(np.sum(d * descent(x + alpha_t * d)[0]))
         evals += 1
         alpha = secant_root(alpha_t, delta0, delta_t)
         x = x + alpha * d
-        s_new = descent(x)
+        s, ph = descent(x)
         evals += 1
-        r2_new = float(np.sum(s_new * s_new))
         out["iters"] = it
-        out["resid"] = np.sqrt(r2_new / n)
+        out["resid"] = np.sqrt(float(np.sum(s * s)) / n)
         if out["resid"] < tol:
             out["converged"] = True
-            s = s_new
             break
-        d = s_new + (r2_new / r2) * d
-        s, r2, alpha_t = s_new, r2_new, alpha
-    return dict(out, omega=x, phi=s + phi_target, evals=evals)
+        z = scaled(s, ph)
+        sz_new = float(np.sum(s * z))
+        d = z + (sz_new / sz) * d
+        sz, alpha_t = sz_new, alpha
+    return dict(out, omega=x, phi=ph, evals=evals)
 
 
 def step(state, p):
@@ -579,7 +599,8 @@ def step(state, p):
     phi_t, omega_t = advect(state["phi"], state["omega"], u_adv)
     inv = None
     if p.get("cg_invert", 0):
-        inv = invert_densities(phi_t, omega_t, p, p.get("cg_tol", 1e-8), p.get("cg_max_iter", 1000))
+        inv = invert_densities(phi_t, omega_t, p, p.get("cg_tol", 1e-8), p.get("cg_max_iter", 1000),
+                               p.get("cg_precond", 0))
         omega_t = inv["omega"]
     omega_new = field_update(phi_t, omega_t, p)
     d = densities(omega_new, p)

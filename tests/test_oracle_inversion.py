@@ -120,3 +120,23 @@ def test_step_with_inversion():
     # same advected composition, different potentials
     assert np.array_equal(plain["phi_t"], cg["phi_t"])
     assert np.max(np.abs(plain["omega_t"] - cg["omega_t"])) > 1e-6
+
+
+def test_preconditioned_iteration_same_solution_fewer_iterations():
+    """cg_precond = 1 (reading R25): the same potentials up to constants, the same
+    stopping test, and fewer iterations where the plain iteration needs many."""
+    p = preset("cfg1", nx=64, ny=64, n_contour=32, f_A=0.3)
+    w_star = _omega(64, 64, 5, 0.05)
+    phi_star = O.densities(w_star, p)["phi"]
+    rng = np.random.default_rng(1)
+    seed = w_star + 0.02 * rng.standard_normal(w_star.shape)
+    plain = O.invert_densities(phi_star, seed, p)
+    pre = O.invert_densities(phi_star, seed, p, precond=1)
+    assert plain["converged"] and pre["converged"] and pre["resid"] < 1e-8
+    assert pre["resid0"] == plain["resid0"]
+    assert pre["iters"] < 0.8 * plain["iters"], (pre["iters"], plain["iters"])
+    assert np.max(np.abs(_gauge_free(pre["omega"]) - _gauge_free(w_star))) < 2e-5
+    c = pre["omega"][2] + np.log(phi_star[2])
+    assert np.ptp(c) < 1e-6
+    m = O.local_response(phi_star, p)
+    assert np.array_equal(m[0], 32 * phi_star[0]) and np.array_equal(m[2], phi_star[2])
