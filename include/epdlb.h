@@ -112,6 +112,11 @@ typedef struct {
   int32_t cg_invert;      /* default 0 */
   int32_t cg_max_iter;    /* default 1000 */
   double cg_tol;          /* default 1e-8 (the paper's N_tr) */
+  /* 1: precondition the inversion (also epdlb_invert_densities) by the local
+   * density response: directions from s / (N Phi_A, N Phi_B, Phi_S) at the
+   * current iterate, factor (s.z)_new / (s.z)_old.  Same solution and
+   * stopping test, fewer iterations; 0 (default): the paper's plain iteration. */
+  int32_t cg_precond;
 } epdlb_params;
 
 /* Observables of the current densities (Sec. III and IV).  Phi_P = Phi_A +

@@ -55,6 +55,7 @@ class epdlb_params(ctypes.Structure):
         ("lb_mrt", ctypes.c_int32),
         ("lb_gamma_s", ctypes.c_double), ("lb_gamma_b", ctypes.c_double), ("lb_gamma_g", ctypes.c_double),
         ("cg_invert", ctypes.c_int32), ("cg_max_iter", ctypes.c_int32), ("cg_tol", ctypes.c_double),
+        ("cg_precond", ctypes.c_int32),
     ]
 
 

@@ -28,6 +28,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--tune-cache", default=None)
+    ap.add_argument("--precond", type=int, default=0, help="1: diagonal preconditioning of the iteration")
     args = ap.parse_args(argv)
     import torch
     from paper_1804_02883_amd import Simulation
@@ -36,7 +37,8 @@ def main(argv=None):
     over = dict(precision=0) if args.g_paper else dict(precision=0, g=args.g, g_units=1)
     base = preset(args.workload, **over)
     w0 = initial_omega(base["nx"], base["ny"], PRESETS[args.workload]["seed"], args.sigma)
-    out = dict(workload=args.workload, nx=base["nx"], ny=base["ny"], N=base["n_contour"],
+    base["cg_precond"] = args.precond
+    out = dict(workload=args.workload, precond=args.precond, nx=base["nx"], ny=base["ny"], N=base["n_contour"],
                g=base["g"], g_units=base["g_units"], sigma=args.sigma, steps=args.steps)
     for cg in (0, 1):
         sim = Simulation(dict(base, cg_invert=cg))

@@ -8,7 +8,9 @@
 // kernels do the vector updates and the dot products, all over the three
 // planes of a field set (m = 3 nx ny elements).  Dot products accumulate in
 // FP64: block partials in fixed slots, summed in slot order by k_cg_finish,
-// so the sums do not depend on scheduling.
+// so the sums do not depend on scheduling.  Optional diagonal preconditioning
+// builds the directions from z = s / m, m = (N Phi_A, N Phi_B, Phi_S) the
+// local response at the current iterate, with the factor (s.z)_new / (s.z)_old.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -20,32 +22,46 @@ namespace cg {
 constexpr int kBlocks = 1024;   // fixed grid of the vector kernels (grid-stride)
 constexpr int kThreads = 256;
 
-// s = phi - target; part[block] = sum s^2.
+// s = phi - target and, with z, z = s / m (planes A, B: m = N phi; S: m = phi);
+// part[block] = sum s^2, part[kBlocks + block] = sum s.z (s^2 without z).
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_cg_resid(const T* __restrict__ phi, const T* __restrict__ target,
-                                                       T* __restrict__ s, long m, double* __restrict__ part) {
-  __shared__ double red[16];
-  double acc[1] = {0.0};
+                                                       T* __restrict__ s, T* __restrict__ z, long m, long n,
+                                                       T Nc, double* __restrict__ part) {
+  __shared__ double red[16 * 2];
+  double acc[2] = {0.0, 0.0};
   for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < m; i += long(gridDim.x) * blockDim.x) {
-    const T v = phi[i] - target[i];
+    const T ph = phi[i];
+    const T v = ph - target[i];
     s[i] = v;
     acc[0] += double(v) * double(v);
+    if (z) {
+      const T zv = v / ((i < 2 * n ? Nc : T(1)) * ph);
+      z[i] = zv;
+      acc[1] += double(v) * double(zv);
+    }
   }
-  block_sum<1>(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+  if (!z) acc[1] = acc[0];
+  block_sum<2>(acc, red);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = acc[0];
+    part[kBlocks + blockIdx.x] = acc[1];
+  }
 }
 
-// New direction and trial point: d = s (first) or s + beta d; xt = x + alpha_t d;
-// part[block] = sum d . s.
+// New direction and trial point: d = z (first) or z + beta d (z = s without
+// preconditioning); xt = x + alpha_t d; part[block] = sum d . s.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_cg_trial(const T* __restrict__ s, T* __restrict__ d,
-                                                       const T* __restrict__ x, T* __restrict__ xt, T beta,
-                                                       int first, T alpha_t, long m, double* __restrict__ part) {
+__global__ void __launch_bounds__(kThreads) k_cg_trial(const T* __restrict__ s, const T* __restrict__ z,
+                                                       T* __restrict__ d, const T* __restrict__ x,
+                                                       T* __restrict__ xt, T beta, int first, T alpha_t, long m,
+                                                       double* __restrict__ part) {
   __shared__ double red[16];
   double acc[1] = {0.0};
   for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < m; i += long(gridDim.x) * blockDim.x) {
     const T sv = s[i];
-    const T dv = first ? sv : sv + beta * d[i];
+    const T zv = z[i];
+    const T dv = first ? zv : zv + beta * d[i];
     d[i] = dv;
     xt[i] = x[i] + alpha_t * dv;
     acc[0] += double(dv) * double(sv);

@@ -269,6 +269,7 @@ int validate(const epdlb_params* p) {
     return fail(EPDLB_EINVAL,
                 "surrogate mode needs fallback_every >= 1, check_every >= 1, resid_tol > 0, err_tol >= 0");
   if (p->cg_invert != 0 && p->cg_invert != 1) return fail(EPDLB_EINVAL, "cg_invert must be 0 or 1");
+  if (p->cg_precond != 0 && p->cg_precond != 1) return fail(EPDLB_EINVAL, "cg_precond must be 0 or 1");
   if (p->cg_invert == 1) {
     if (p->density_mode != 0) return fail(EPDLB_EINVAL, "cg_invert needs exact densities (density_mode 0)");
     if (p->cg_max_iter < 0 || p->cg_max_iter > 1000000) return fail(EPDLB_EINVAL, "cg_max_iter must be in [0, 1e6]");
@@ -743,17 +744,17 @@ int stage_lb(epdlb_ctx* c) {
 // the trial point xt and the evaluated densities, 3 planes each.
 // ---------------------------------------------------------------------------
 struct CgLayout {
-  size_t set[6];  // target, x, d, s, xt, phi
+  size_t set[7];  // target, x, d, s, xt, phi, z (preconditioned direction source)
   size_t part, out, total;
 };
-enum { CG_TARGET, CG_X, CG_D, CG_S, CG_XT, CG_PHI };
+enum { CG_TARGET, CG_X, CG_D, CG_S, CG_XT, CG_PHI, CG_Z, CG_NSETS };
 
 CgLayout cg_layout(const epdlb_params& p) {
   const size_t es = p.precision == 0 ? 8 : 4;
   const size_t set = 3 * size_t(p.nx) * p.ny * es;
   CgLayout L{};
   size_t off = 0;
-  for (int i = 0; i < 6; ++i) {
+  for (int i = 0; i < CG_NSETS; ++i) {
     L.set[i] = off;
     off = align256(off + set);
   }
@@ -827,30 +828,29 @@ int cg_invert(epdlb_ctx* c, double tol, int max_iter, epdlb_cg_info* info) {
   T* s = cg_set<T>(c, CG_S);
   T* xt = cg_set<T>(c, CG_XT);
   T* phi = cg_set<T>(c, CG_PHI);
+  T* z = c->p.cg_precond ? cg_set<T>(c, CG_Z) : nullptr;
   double* part = reinterpret_cast<double*>(c->cg + L.part);
   const dim3 grid(cg::kBlocks), blk(cg::kThreads);
   *info = epdlb_cg_info{};
-  double r2 = 0.0, sums[2];
-  // descent direction s = Phi[x] - target and |s|^2
-  auto resid = [&](double* out) -> int {
+  double r2 = 0.0, sz = 0.0, sums[2];
+  // descent direction s = Phi[x] - target (and z = s / m), |s|^2 and s.z
+  auto resid = [&](double* out2) -> int {
     CHK(cg_eval<T>(c, x, phi));
     ++info->evals;
     {
       ProfScope ps(c, K_CG);
-      launch_k((cg::k_cg_resid<T>), grid, blk, 0, c->stream, (const T*)phi, (const T*)tgt, s, m, part);
+      launch_k((cg::k_cg_resid<T>), grid, blk, 0, c->stream, (const T*)phi, (const T*)tgt, s, z, m, n,
+               T(c->p.n_contour), part);
     }
     HIPCHK(hipGetLastError());
-    double v[2];
-    CHK(cg_reduce(c, 1, v));
-    *out = v[0];
-    return EPDLB_OK;
+    return cg_reduce(c, 2, out2);
   };
-  // d = s (first) or s + beta d, trial point x + alpha_t d; returns d.s and d.s(trial)
+  // d = z (first) or z + beta d, trial point x + alpha_t d; returns d.s and d.s(trial)
   auto trial = [&](double beta, int first, double alpha_t) -> int {
     {
       ProfScope ps(c, K_CG);
-      launch_k((cg::k_cg_trial<T>), grid, blk, 0, c->stream, (const T*)s, d, (const T*)x, xt, T(beta), first,
-               T(alpha_t), m, part);
+      launch_k((cg::k_cg_trial<T>), grid, blk, 0, c->stream, (const T*)s, (const T*)(z ? z : s), d, (const T*)x,
+               xt, T(beta), first, T(alpha_t), m, part);
     }
     HIPCHK(hipGetLastError());
     CHK(cg_eval<T>(c, xt, phi));
@@ -863,7 +863,12 @@ int cg_invert(epdlb_ctx* c, double tol, int max_iter, epdlb_cg_info* info) {
     HIPCHK(hipGetLastError());
     return cg_reduce(c, 2, sums);
   };
-  CHK(resid(&r2));
+  {
+    double v[2];
+    CHK(resid(v));
+    r2 = v[0];
+    sz = v[1];
+  }
   info->resid0 = info->resid = std::sqrt(r2 / double(n));
   info->converged = info->resid < tol;
   double beta = 0.0, alpha_t = 1.0;
@@ -883,13 +888,14 @@ int cg_invert(epdlb_ctx* c, double tol, int max_iter, epdlb_cg_info* info) {
       launch_k((cg::k_cg_axpy<T>), grid, blk, 0, c->stream, x, (const T*)d, T(alpha), m);
     }
     HIPCHK(hipGetLastError());
-    double r2n = 0.0;
-    CHK(resid(&r2n));
+    double v[2];
+    CHK(resid(v));
     info->iters = it;
-    info->resid = std::sqrt(r2n / double(n));
+    info->resid = std::sqrt(v[0] / double(n));
     info->converged = info->resid < tol;
-    beta = r2n / r2;
-    r2 = r2n;
+    beta = v[1] / sz;
+    r2 = v[0];
+    sz = v[1];
     alpha_t = alpha;
     first = 0;
   }
@@ -1456,6 +1462,7 @@ int epdlb_params_default(epdlb_params* p) {
   p->cg_invert = 0;
   p->cg_max_iter = 1000;
   p->cg_tol = 1e-8;
+  p->cg_precond = 0;
   return EPDLB_OK;
 }
 

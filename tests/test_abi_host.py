@@ -57,7 +57,7 @@ def test_defaults_and_validation():
     gs, gb = B.mrt_gammas(1.0, 1.0)  # the paper's eta = eta_B at its dx, dt
     assert abs(gs + 0.8050541516245486) < 1e-15 and gs == gb
     assert B.epdlb_validate(B.make_params(lb_mrt=1, lb_gamma_s=gs, lb_gamma_b=gb, lb_gamma_g=0.5)) == 0
-    assert (p.cg_invert, p.cg_max_iter, p.cg_tol) == (0, 1000, 1e-8)
+    assert (p.cg_invert, p.cg_max_iter, p.cg_tol, p.cg_precond) == (0, 1000, 1e-8, 0)
     assert B.epdlb_validate(B.make_params(cg_invert=1)) == 0
     assert B.epdlb_validate(B.make_params(cg_invert=1, precision=1, cg_tol=1e-6)) == 0
     for bad in [dict(nx=48), dict(nx=16), dict(ny=8), dict(n_contour=1), dict(f_A=1.0),
@@ -68,7 +68,7 @@ def test_defaults_and_validation():
                 dict(lb_mrt=1, lb_gamma_b=-1.0), dict(lb_mrt=1, lb_gamma_g=float("nan")),
                 dict(cg_invert=2), dict(cg_invert=1, density_mode=1), dict(cg_invert=1, cg_tol=0.0),
                 dict(cg_invert=1, cg_max_iter=-1), dict(cg_invert=1, cg_tol=float("inf")),
-                dict(cg_invert=1, precision=1)]:
+                dict(cg_invert=1, precision=1), dict(cg_precond=2)]:
         q = B.make_params(**bad)
         assert B.epdlb_validate(q) == B.EPDLB_EINVAL, bad
         assert B.epdlb_last_error() != ""

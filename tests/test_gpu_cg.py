@@ -39,15 +39,16 @@ def _rms(a, b):
     return float(np.sqrt(np.sum((a - b) ** 2) / n))
 
 
-@pytest.mark.parametrize("nx,ny,N,fA", [(32, 32, 16, 0.5), (64, 32, 8, 0.3), (32, 64, 24, 0.7)])
-def test_invert_vs_oracle(nx, ny, N, fA):
-    say(f"[invert] {nx}x{ny} N={N} f_A={fA} FP64")
-    p = preset("cfg1", nx=nx, ny=ny, n_contour=N, f_A=fA)
+@pytest.mark.parametrize("nx,ny,N,fA,pc", [(32, 32, 16, 0.5, 0), (64, 32, 8, 0.3, 0), (32, 64, 24, 0.7, 0),
+                                            (32, 32, 16, 0.5, 1), (64, 64, 32, 0.3, 1)])
+def test_invert_vs_oracle(nx, ny, N, fA, pc):
+    say(f"[invert] {nx}x{ny} N={N} f_A={fA} FP64 precond={pc}")
+    p = preset("cfg1", nx=nx, ny=ny, n_contour=N, f_A=fA, cg_precond=pc)
     w_star = np.array(initial_omega(nx, ny, 2000 + nx + ny, 0.05))
     phi_star = O.densities(w_star, p)["phi"]
     rng = np.random.default_rng(nx * ny + N)
     seed = w_star + 0.02 * rng.standard_normal(w_star.shape)
-    ref = O.invert_densities(phi_star, seed, p, tol=1e-8, max_iter=1000)
+    ref = O.invert_densities(phi_star, seed, p, tol=1e-8, max_iter=1000, precond=pc)
     sim = _sim(p)
     sim.set_fields(seed)
     got = sim.invert_densities(phi_star, max_iter=1000, tol=1e-8)
@@ -111,11 +112,12 @@ def test_invert_rejects_bad_targets():
     sim.close()
 
 
-def test_steps_with_inversion_vs_oracle():
+@pytest.mark.parametrize("pc", [0, 1])
+def test_steps_with_inversion_vs_oracle(pc):
     """cfg1 under a strong lattice force (the convected composition then needs
     several iterations per step): 4 steps against the oracle's steps."""
-    say("[cg step] cfg1, lattice force 1e-4, 4 steps")
-    p = preset("cfg1", g=1e-4, g_units=1, cg_invert=1)
+    say(f"[cg step] cfg1, lattice force 1e-4, 4 steps, precond={pc}")
+    p = preset("cfg1", g=1e-4, g_units=1, cg_invert=1, cg_precond=pc)
     w0 = np.array(initial_omega(32, 32, 1001, 0.05))
     sim = _sim(p)
     sim.set_fields(w0)
