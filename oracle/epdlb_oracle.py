@@ -545,7 +545,10 @@ def invert_densities(phi_target, omega0, p, tol=1e-8, max_iter=1000, precond=0):
         return ph - phi_target, ph
 
     def scaled(s, ph):
-        return s / local_response(ph, p) if precond else s
+        if not precond:
+            return s
+        m = local_response(ph, p)
+        return np.where(m > 0.0, s / np.where(m > 0.0, m, 1.0), s)  # a density rounded to zero keeps s
 
     s, ph = descent(x)
     evals = 1

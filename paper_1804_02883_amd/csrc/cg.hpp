@@ -36,7 +36,8 @@ __global__ void __launch_bounds__(kThreads) k_cg_resid(const T* __restrict__ phi
     s[i] = v;
     acc[0] += double(v) * double(v);
     if (z) {
-      const T zv = v / ((i < 2 * n ? Nc : T(1)) * ph);
+      const T mv = (i < 2 * n ? Nc : T(1)) * ph;
+      const T zv = mv > T(0) ? v / mv : v;  // a density rounded to zero keeps s
       z[i] = zv;
       acc[1] += double(v) * double(zv);
     }
