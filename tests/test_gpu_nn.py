@@ -288,3 +288,42 @@ def test_surrogate_steps_match_oracle_shapes(nx, ny, prec, tol):
     print(f"{nx}x{ny} precision {prec}: max dPhi {err:.3e}, n_exact {d['n_exact']}")
     assert d["n_exact"] == 3
     assert err <= tol
+
+
+def test_surrogate_full_size_trained_weights(tmp_path):
+    """512x512, N = 32, reading Q, noise 0.05, the trained weights and the tuned
+    launch shapes: the bench's configuration.  One exact and one network step
+    against the oracle over the whole grid, in FP64 fields so that both sides
+    round the same network inputs to BF16.
+
+    The layers accumulate in FP32 on the matrix cores and in FP64 in the
+    oracle, so an activation that lies at a BF16 rounding tie can round to the
+    neighbouring value on one side: one BF16 step (2^-8 relative) of one
+    activation.  Over 262,144 sites such flips touch about 2% of the density
+    entries (measured 8.4e-5 at most, the rest at 1e-8 to 1e-7), so the bar is
+    the FP32 density tolerance 1e-4 for every entry, and 1e-6 for 95% of them."""
+    import shutil
+    from paper_1804_02883_amd import Simulation
+    from seeded_inputs import PRESETS, initial_omega
+    root = __import__("os").path.dirname(__import__("os").path.dirname(__file__))
+    w = np.load(root + "/paper_1804_02883_amd/weights/surrogate_q.npy").astype(np.float32)
+    cache = tmp_path / "tune.txt"
+    shutil.copy(root + "/paper_1804_02883_amd/tune/gfx950.txt", cache)
+    p = dict(preset("cfg5q", precision=0), density_mode=1, fallback_every=2, check_every=1, resid_tol=1e9,
+             err_tol=0.0)
+    w0 = initial_omega(512, 512, PRESETS["cfg5q"]["seed"], PRESETS["cfg5q"]["sigma"])
+    sim = Simulation(p)
+    sim.surrogate_set_weights(w)
+    sim.autotune(cache_path=str(cache))
+    sim.set_fields(w0)
+    sim.step(2)
+    sim.sync()
+    phi = sim.densities()
+    d = sim.diag()
+    sim.close()
+    ref = NN.surrogate_run(p, NN.round_params(unflatten(w), NN.bf16_round), w0, 2, 2, rnd=NN.bf16_round)
+    err = np.abs(phi - ref["phi"])
+    frac = float(np.mean(err > 1e-6))
+    print(f"512x512 FP64: max dPhi {err.max():.3e}, sites above 1e-6: {frac:.2e}, n_exact {d['n_exact']}")
+    assert d["n_exact"] == 1
+    assert err.max() <= 1e-4 and frac <= 0.05
