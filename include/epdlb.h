@@ -301,7 +301,8 @@ typedef struct {
  * result replaces omega and the densities become Phi[omega].  Each field is
  * determined up to an additive constant.  info (may be NULL) gets the counts
  * and residuals; an unconverged run still returns EPDLB_OK with
- * info->converged = 0.  Synchronises the stream.  EINVAL on bad arguments, a
+ * info->converged = 0 (also when the residual turns non-finite, which ends
+ * the iteration at once).  Synchronises the stream.  EINVAL on bad arguments, a
  * batch replica group or density_mode 1; ESTATE before any state; ENOMEM if
  * the scratch (18 field planes, allocated once) cannot be allocated. */
 int epdlb_invert_densities(epdlb_ctx* ctx, const double* phi_target, int32_t max_iter, double tol,

@@ -578,6 +578,8 @@ def invert_densities(phi_target, omega0, p, tol=1e-8, max_iter=1000, precond=0):
         if out["resid"] < tol:
             out["converged"] = True
             break
+        if not np.isfinite(out["resid"]):
+            break  # a state that blew up: stop, unconverged
         z = scaled(s, ph)
         sz_new = float(np.sum(s * z))
         d = z + (sz_new / sz) * d

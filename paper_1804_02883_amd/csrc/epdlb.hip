@@ -893,6 +893,7 @@ int cg_invert(epdlb_ctx* c, double tol, int max_iter, epdlb_cg_info* info) {
     info->iters = it;
     info->resid = std::sqrt(v[0] / double(n));
     info->converged = info->resid < tol;
+    if (!std::isfinite(info->resid)) break;  // a state that blew up: stop, unconverged
     beta = v[1] / sz;
     r2 = v[0];
     sz = v[1];
