@@ -158,6 +158,11 @@ struct epdlb_ctx {
   std::vector<GraphEntry> graphs;
   hipStream_t cap_stream = nullptr;
   bool use_graph = true;
+  // Surrogate steps are single steps whose kind the host picks per step; on
+  // MI355X (ROCm 7) their ~12 launches go out faster as stream launches than
+  // as a one-step graph (measured 0.110-0.114 against 0.115-0.120 ms per step
+  // at 512^2), so graphs are opt-in there (EPDLB_SUR_GRAPH=1).
+  bool sur_graph = false;
   // surrogate mode
   bool nn_ready = false;      // weights loaded
   bool last_exact = true;     // previous step (or the seed) had exact densities
@@ -1324,6 +1329,7 @@ int make_group(const std::vector<epdlb_params>& rp, int device, epdlb_ctx** out)
   c->nrep = int(rp.size());
   c->device = device;
   if (const char* env = std::getenv("EPDLB_GRAPH")) c->use_graph = std::atoi(env) != 0;
+  if (const char* env = std::getenv("EPDLB_SUR_GRAPH")) c->sur_graph = std::atoi(env) != 0;
   c->L = make_layout(c->p);
   c->rstride = c->L.total;
   if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
@@ -1511,6 +1517,7 @@ int epdlb_create(const epdlb_params* p, int device, void* stream, void* workspac
   c->nrep = 1;
   c->device = device;
   if (const char* env = std::getenv("EPDLB_GRAPH")) c->use_graph = std::atoi(env) != 0;
+  if (const char* env = std::getenv("EPDLB_SUR_GRAPH")) c->sur_graph = std::atoi(env) != 0;
   c->L = make_layout(*p);
   c->rstride = c->L.total;
   if (stream) {
@@ -1627,7 +1634,7 @@ int epdlb_step(epdlb_ctx* c, int64_t n) {
       const bool exact = c->force_exact || c->nstep % c->p.fallback_every == 0 ||
                          (c->p.err_tol > 0.0 && !c->validated);
       const int kind = (exact ? 3 : 1) + (c->last_exact ? 1 : 0);
-      if (c->use_graph && !c->prof_on) {
+      if (c->use_graph && c->sur_graph && !c->prof_on) {
         hipGraphExec_t g;
         CHK(get_graph(c, 1, kind, &g));
         HIPCHK(hipGraphLaunch(g, c->stream));

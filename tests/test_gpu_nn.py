@@ -231,6 +231,7 @@ def test_surrogate_fp32_graph_and_stream_paths_agree():
     out = []
     for graph in ("1", "0"):
         os.environ["EPDLB_GRAPH"] = graph
+        os.environ["EPDLB_SUR_GRAPH"] = graph  # surrogate steps replay graphs only on request
         sim = Simulation(p)
         sim.surrogate_set_weights(w32)
         sim.seed(1002, 1e-3)
@@ -239,6 +240,7 @@ def test_surrogate_fp32_graph_and_stream_paths_agree():
         out.append((sim.densities(), sim.velocity(), sim.diag()))
         sim.close()
     os.environ.pop("EPDLB_GRAPH")
+    os.environ.pop("EPDLB_SUR_GRAPH")
     assert np.array_equal(out[0][0], out[1][0])
     assert all(np.array_equal(a, b) for a, b in zip(out[0][1], out[1][1]))
     assert out[0][2]["n_exact"] == 3
