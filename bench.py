@@ -43,13 +43,13 @@ METRIC = "lattice site-updates/s per hybrid step, plain vs surrogate at <=1e-3 d
 _PROP_FILES = ("fft.hpp", "kernels.hpp")
 _NN_FILES = ("kernels.hpp", "nn.hpp")
 MEASURED_TRAFFIC = {
-    ("cfg3", "prop_col"): dict(bytes_per_launch=17286289, files=_PROP_FILES,
-                               source_sha256="5c589c90c06f05169003f4394270b5a3fa1439f2fc85793fce6a43eb161ab220"),
-    ("cfg3", "prop_row"): dict(bytes_per_launch=16019178, files=_PROP_FILES,
-                               source_sha256="5c589c90c06f05169003f4394270b5a3fa1439f2fc85793fce6a43eb161ab220"),
+    ("cfg3", "prop_col"): dict(bytes_per_launch=17284293, files=_PROP_FILES,
+                               source_sha256="09839588ecde426f14350f4230b579f6c49ce5e55f9ba4f31f96cd374db85421"),
+    ("cfg3", "prop_row"): dict(bytes_per_launch=16173527, files=_PROP_FILES,
+                               source_sha256="09839588ecde426f14350f4230b579f6c49ce5e55f9ba4f31f96cd374db85421"),
     # mean over the two 64 -> 64 launches of a surrogate step
-    ("cfg5q", "nn_conv"): dict(bytes_per_launch=64002469, files=_NN_FILES,
-                               source_sha256="c1ec3945833900cb230db730d2f732425578f7cc5e97f75bbdb2bcb38cb29da8"),
+    ("cfg5q", "nn_conv"): dict(bytes_per_launch=63970359, files=_NN_FILES,
+                               source_sha256="4f00c90da1997534e3811f0beb2591c36ceaec6e5898195cfffe087c312feb2d"),
 }
 
 
@@ -77,9 +77,9 @@ NN_FLOPS_PER_SITE = {"nn_conv0": 9 * 5 * 64 * 2, "nn_conv": 9 * 64 * 64 * 2}
 # Algorithmic bytes per site per hybrid STEP of each kernel family, in units
 # of the element size P (forward and backward chains counted together):
 #   advect_update : read Phi 3, omega 3, u 2; write omega 3, S~ 1        = 12P
-#   boltzmann     : read omega_A, omega_B; write their half-step factors =  4P
-#   prop_row/col  : per chain, the first launch reads a factor plane and
-#                   writes the scratch plane (2P); a fused boundary launch
+#   prop_row/col  : per chain, the first launch reads omega_A and omega_B and
+#                   writes one half-step factor plane and the scratch plane
+#                   (4P); a fused boundary launch
 #                   reads scratch + factor and writes q_{a+1} + scratch (4P);
 #                   the last reads scratch + factor and writes q_N (3P)
 #   density       : read 2N chain planes + omega_S + S~, write Phi 3 + S = (2N + 6)P
@@ -89,10 +89,10 @@ def step_bytes_per_site(kind, N, P):
     last_row = (N - 1) % 2 == 1           # the final propagator launch is x-oriented
     n_fused_row = sum(1 for s in range(N - 1) if s % 2 == 1)
     n_fused_col = sum(1 for s in range(N - 1) if s % 2 == 0)
-    per_chain_row = 2 + 4 * n_fused_row + (3 if last_row else 0)
+    per_chain_row = 4 + 4 * n_fused_row + (3 if last_row else 0)
     per_chain_col = 4 * n_fused_col + (0 if last_row else 3)
     return {
-        "advect_update": 12 * P, "boltzmann": 4 * P,
+        "advect_update": 12 * P,
         "prop_row": 2 * per_chain_row * P, "prop_col": 2 * per_chain_col * P,
         "density": (2 * N + 6) * P,
         "force_row_fwd": 3 * P, "force_col": 4 * P, "force_row_inv": 4 * P,
@@ -241,7 +241,7 @@ def plain_line(args, workload):
     sim.sync()
     # per-kernel durations: HIP start/stop events recorded by each kernel launch
     # itself (stream launches of the same workload, right after the timed region)
-    per_step = (N + 9) * (1 if workload != "cfg4" else sim.info()[0])
+    per_step = (N + 8) * (1 if workload != "cfg4" else sim.info()[0])
     prof_steps = max(1, min(50, args.profile_launches // per_step))
     sim.profile_start(prof_steps * per_step + 16)
     sim.step(prof_steps)

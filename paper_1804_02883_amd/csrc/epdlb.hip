@@ -197,10 +197,10 @@ namespace {
 
 int nn_after_seed(epdlb_ctx* c);
 
-enum Kind { K_STATS, K_ADVECT, K_FINISH, K_BOLTZ, K_PROP_ROW, K_PROP_COL, K_DENSITY, K_FROW_FWD, K_FCOL,
+enum Kind { K_STATS, K_ADVECT, K_FINISH, K_PROP_ROW, K_PROP_COL, K_DENSITY, K_FROW_FWD, K_FCOL,
             K_FROW_INV, K_LB, K_NN_CONV0, K_NN_CONV, K_NN_OUT, K_NN_NORM, K_NN_RESET, K_ADVECT_ONLY, K_CG,
             K_NUM };
-const char* const kKindName[K_NUM] = {"field_stats", "advect_update", "finish_stats",  "boltzmann",
+const char* const kKindName[K_NUM] = {"field_stats", "advect_update", "finish_stats",
                                       "prop_row",    "prop_col",      "density",       "force_row_fwd",
                                       "force_col",   "force_row_inv", "lb",            "nn_conv0",
                                       "nn_conv",     "nn_out",        "nn_norm",       "nn_reset",
@@ -591,12 +591,6 @@ int stage_densities(epdlb_ctx* c, bool with_S) {
   const int N = p.n_contour;
   const long n = long(p.nx) * p.ny;
   PropArgs<T> a = make_prop_args<T>(c);
-  {
-    ProfScope ps(c, K_BOLTZ);
-    launch_k((k_boltzmann<T>), dim3((n + 255) / 256, 1, c->nrep), dim3(256), 0, c->stream, a.wA,
-             c->ptr<T>(c->L.boltz), a.scal, n, long(c->rstride));
-  }
-  HIPCHK(hipGetLastError());
   auto launch = [&](bool row) -> int {
     if (row) {
       a.nf = c->sh_row.nf;
@@ -609,7 +603,8 @@ int stage_densities(epdlb_ctx* c, bool with_S) {
     }
     return EPDLB_OK;
   };
-  // step 0 starts with its x convolution of E(step 0)
+  // step 0 starts with its x convolution of E(step 0); that first pass also
+  // writes the half-step factor planes the later passes read
   // segment A fractions (uniform over the replicas of a launch)
   const std::vector<double> segA = segment_fractions(p);
   auto seg = [&](int chain, int step) { return T(segA[chain == 0 ? step : N - 1 - step]); };

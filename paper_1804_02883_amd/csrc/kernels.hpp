@@ -198,16 +198,6 @@ __device__ __forceinline__ T2<T> efactor2(const PropArgs<T>& P, T fr, T ca, T cb
   return e;
 }
 
-// Both half-step factor planes of the current potentials.
-template <typename T>
-__global__ void __launch_bounds__(256) k_boltzmann(const T* w, T* E, const double* scal, long n, long rs) {
-  const long o = long(blockIdx.z) * rs;
-  w = sh(w, o), E = sh(E, o), scal = sh(scal, o);
-  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  E[i] = exp(T(-0.5) * (w[i] - T(scal[kMeanA])));
-  E[n + i] = exp(T(-0.5) * (w[n + i] - T(scal[kMeanB])));
-}
 
 // Convolution with the real, even multiplier g in the lane layout.
 template <typename T, int L, int R, class V>
@@ -248,11 +238,32 @@ __global__ void __launch_bounds__(512) k_prop_row(PropArgs<T> P) {
   T* tmp = P.tmp + c * P.plane;
   // half-step factors of step a (loaded early: they overlap the first convolution)
   T ea[R], eb[R];
+  if (P.first) {
+    // the first pass takes its factors from the potentials and leaves the
+    // factor planes of the later passes: A's from the forward chain's blocks,
+    // B's from the backward chain's (the same values a separate pass gave)
+    T* Ep = const_cast<T*>(c == 0 ? P.EA : P.EB);
+    const T pure = c == 0 ? T(1) : T(0);
 #pragma unroll
-  for (int m = 0; m < R; ++m) {
-    const int x = j + TL * m;
-    ea[m] = active && (P.first || P.mid) ? efactor(P, fr0, ca, cb, r0 + x) : T(0);
-    eb[m] = active && (P.first || P.mid) ? efactor(P, fr0, ca, cb, r1 + x) : T(0);
+    for (int m = 0; m < R; ++m) {
+      const int x = j + TL * m;
+      ea[m] = eb[m] = T(0);
+      if (active) {
+        const T wa0 = P.wA[r0 + x], wb0 = P.wB[r0 + x], wa1 = P.wA[r1 + x], wb1 = P.wB[r1 + x];
+        const T p0 = boltz(wa0, wb0, pure, ca, cb), p1 = boltz(wa1, wb1, pure, ca, cb);
+        Ep[r0 + x] = p0;
+        Ep[r1 + x] = p1;
+        ea[m] = fr0 == pure ? p0 : boltz(wa0, wb0, fr0, ca, cb);
+        eb[m] = fr0 == pure ? p1 : boltz(wa1, wb1, fr0, ca, cb);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int x = j + TL * m;
+      ea[m] = active && P.mid ? efactor(P, fr0, ca, cb, r0 + x) : T(0);
+      eb[m] = active && P.mid ? efactor(P, fr0, ca, cb, r1 + x) : T(0);
+    }
   }
   T re[R], im[R];
 #pragma unroll

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def test_step_byte_model_totals():
     """Per-family algorithmic bytes per site and step add up to (10N + 58)P."""
-    fams = ["advect_update", "boltzmann", "prop_row", "prop_col", "density",
+    fams = ["advect_update", "prop_row", "prop_col", "density",
             "force_row_fwd", "force_col", "force_row_inv", "lb"]
     for N in (16, 32, 64):
         for P in (4, 8):
