@@ -329,3 +329,52 @@ def test_surrogate_full_size_trained_weights(tmp_path):
     print(f"512x512 FP64: max dPhi {err.max():.3e}, sites above 1e-6: {frac:.2e}, n_exact {d['n_exact']}")
     assert d["n_exact"] == 1
     assert err.max() <= 1e-4 and frac <= 0.05
+
+
+def test_trained_network_gain(tmp_path):
+    """What the learned part gains (512x512 quench, the bench's workload): with the
+    trained weights the gated surrogate path runs at least 1.5x the plain path's
+    throughput at an in-use density error <= 1e-3; an untrained network never
+    passes the error gate, so every step stays exact and nothing is gained."""
+    import shutil
+    import torch
+    from paper_1804_02883_amd import Simulation
+    from seeded_inputs import PRESETS
+    root = __import__("os").path.dirname(__import__("os").path.dirname(__file__))
+    cache = tmp_path / "tune.txt"
+    shutil.copy(root + "/paper_1804_02883_amd/tune/gfx950.txt", cache)
+    cfg = PRESETS["cfg5q"]
+    trained = np.load(root + "/paper_1804_02883_amd/weights/surrogate_q.npy").astype(np.float32)
+    untrained = flatten(init_params(5))
+    steps = 2000
+
+    def run(weights):
+        p = dict(cfg["params"], density_mode=0 if weights is None else 1, fallback_every=50, check_every=10,
+                 resid_tol=1e-3, err_tol=9e-4)
+        sim = Simulation(p)
+        if weights is not None:
+            sim.surrogate_set_weights(weights)
+        sim.seed(cfg["seed"], cfg["sigma"])
+        sim.autotune(20, str(cache))
+        sim.step(50)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(sim.stream)
+        sim.step(steps)
+        ev1.record(sim.stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / steps
+        d = sim.diag()
+        sim.close()
+        return ms, d
+
+    ms_plain, _ = run(None)
+    ms_tr, d_tr = run(trained)
+    ms_un, d_un = run(untrained)
+    print(f"ms/step plain {ms_plain:.4f}, trained {ms_tr:.4f} ({ms_plain / ms_tr:.2f}x, "
+          f"{d_tr['n_exact']} exact, in-use error {d_tr['nn_err_in_use']:.2e}), untrained {ms_un:.4f} "
+          f"({ms_plain / ms_un:.2f}x, {d_un['n_exact']} exact)")
+    assert d_tr["nn_err_in_use"] <= 1e-3 and d_tr["n_exact"] < 0.3 * (steps + 50)
+    assert ms_plain / ms_tr >= 1.5
+    assert d_un["n_exact"] == steps + 50 and ms_plain / ms_un < 1.1
