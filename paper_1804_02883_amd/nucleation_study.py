@@ -27,6 +27,14 @@ def channel_offset(cy, ny, dx):
     return (y - centre) * dx
 
 
+def paper_system(system):
+    """The paper's parameter set (Sec. III): N = 17, A fraction 0.882, phibar_P = 0.1,
+    kappa_H = 1.176, chi_AB = 1.05, chi_AS = 1.20, chi_BS = 0.75 (droplets) or -0.15
+    (vesicles), D_A = D_B = D_S / N with D_S = 1."""
+    return dict(n_contour=17, f_A=0.882, phi_P=0.1, kappa_H=1.176, chi_AB=1.05, chi_AS=1.20,
+                chi_BS=0.75 if system == "droplet" else -0.15, D_A=1 / 17, D_B=1 / 17)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="cfg5q")
@@ -51,10 +59,7 @@ def main(argv=None):
     if args.ny:
         over["ny"] = args.ny
     if args.system:
-        # Sec. III: N = 17, A fraction 0.882, phibar_P = 0.1, kappa_H = 1.176,
-        # chi_AB = 1.05, chi_AS = 1.20, chi_BS = 0.75 (droplets) or -0.15 (vesicles)
-        over.update(n_contour=17, f_A=0.882, phi_P=0.1, kappa_H=1.176, chi_AB=1.05, chi_AS=1.20,
-                    chi_BS=0.75 if args.system == "droplet" else -0.15, D_A=1 / 17, D_B=1 / 17)
+        over.update(paper_system(args.system))
     p = preset(args.workload, **over)
     cfg = PRESETS[args.workload]
     R = args.replicas
