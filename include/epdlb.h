@@ -448,6 +448,47 @@ int epdlb_nn_last_loss(epdlb_nn* nn, double* loss, double* max_err);
 int epdlb_nn_predict(epdlb_nn* nn, int32_t slot, double* phi_hat);
 void epdlb_nn_destroy(epdlb_nn* nn);
 
+/* Three-dimensional fluid.  The paper computes in two dimensions and names
+ * D3Q19 as the lattice that replaces D2Q9 in three (end of Sec. II).  This
+ * context advances a periodic box of nx*ny*nz sites with that lattice and
+ * the collision and body force of the two-dimensional fluid (Sec. II,
+ * Eq. LB_prop and Eq. force_col at gamma_s = gamma_b = 0): pull streaming
+ * f_i(x) = f*_i(x - c_i), rho = sum f_i, u = (sum f_i c_i + F/2)/rho, BGK
+ * relaxation with time tau to the second-order equilibrium, and the force
+ * term (1 - 1/(2 tau)) w_i [3 (c_i - u).F + 9 (c_i.u)(c_i.F)].  Lattice units.
+ *
+ * Velocities c_i, i = 0..18: rest; +x, -x, +y, -y, +z, -z; then (1,1,0),
+ * (-1,-1,0), (1,-1,0), (-1,1,0), (1,0,1), (-1,0,-1), (1,0,-1), (-1,0,1),
+ * (0,1,1), (0,-1,-1), (0,1,-1), (0,-1,1); weights 1/3, 1/18, 1/36.
+ * Host arrays are FP64, planes of nx*ny*nz values in [z][y][x] order (x
+ * contiguous): populations 19 planes, force and velocity 3 planes (x, y, z).
+ * The device holds FP64 (precision 0) or FP32 (1) deviations f_i - w_i.
+ * The context owns its device memory (2 x 19 + 7 planes); work is queued on
+ * its stream (the caller's, or its own when stream is NULL).  Return codes as
+ * above; EINVAL for a size outside [1, 4096], tau <= 1/2, a non-finite value
+ * or a density <= 0. */
+typedef struct epdlb_lb3 epdlb_lb3;
+int epdlb_lb3_create(int32_t nx, int32_t ny, int32_t nz, double tau, int32_t precision, int device,
+                     void* stream, epdlb_lb3** out); /* starts at rest (rho = 1, u = 0), F = 0 */
+/* Post-collision populations f* (19 planes) from which the next step streams. */
+int epdlb_lb3_set_populations(epdlb_lb3* c, const double* f);
+/* f* = f^eq(rho, u) at every site; rho (1 plane) NULL means 1, u (3 planes) NULL means 0. */
+int epdlb_lb3_set_equilibrium(epdlb_lb3* c, const double* rho, const double* u);
+/* Body force density F (3 planes), held for every following step; NULL clears it. */
+int epdlb_lb3_set_force(epdlb_lb3* c, const double* F);
+/* n steps, queued; the last one also stores rho and u.  Returns before the GPU finishes. */
+int epdlb_lb3_step(epdlb_lb3* c, int64_t n);
+/* n steps as epdlb_lb3_step (1 <= n <= 4096), each launch timed on the GPU
+ * from its own start to its end; ms[n] receives the durations.  Synchronous. */
+int epdlb_lb3_profile(epdlb_lb3* c, int32_t n, double* ms);
+int epdlb_lb3_sync(epdlb_lb3* c);
+/* The current f* (19 planes).  Synchronous. */
+int epdlb_lb3_read_populations(epdlb_lb3* c, double* f);
+/* rho (1 plane) and u (3 planes, including F/2) of the last step; ESTATE
+ * before any step since the populations were set.  Synchronous. */
+int epdlb_lb3_read_velocity(epdlb_lb3* c, double* rho, double* u);
+void epdlb_lb3_destroy(epdlb_lb3* c);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char* epdlb_last_error(void);
 

@@ -192,6 +192,17 @@ SIGNATURES = {
     "epdlb_batch_track_reset": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "epdlb_invert_densities": (ctypes.c_int, [_vp, _dp, ctypes.c_int32, ctypes.c_double, _P(epdlb_cg_info)]),
     "epdlb_cg_stats": (ctypes.c_int, [_vp, _P(epdlb_cg_info), _P(ctypes.c_int64)]),
+    "epdlb_lb3_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                        ctypes.c_int32, ctypes.c_int, _vp, _P(_vp)]),
+    "epdlb_lb3_set_populations": (ctypes.c_int, [_vp, _dp]),
+    "epdlb_lb3_set_equilibrium": (ctypes.c_int, [_vp, _dp, _dp]),
+    "epdlb_lb3_set_force": (ctypes.c_int, [_vp, _dp]),
+    "epdlb_lb3_step": (ctypes.c_int, [_vp, ctypes.c_int64]),
+    "epdlb_lb3_profile": (ctypes.c_int, [_vp, ctypes.c_int32, _dp]),
+    "epdlb_lb3_sync": (ctypes.c_int, [_vp]),
+    "epdlb_lb3_read_populations": (ctypes.c_int, [_vp, _dp]),
+    "epdlb_lb3_read_velocity": (ctypes.c_int, [_vp, _dp, _dp]),
+    "epdlb_lb3_destroy": (None, [_vp]),
     "epdlb_last_error": (ctypes.c_char_p, []),
 }
 
@@ -931,3 +942,69 @@ class Batch:
 
     def profile_read(self):
         return epdlb_batch_profile_read(self.b)
+
+
+class Fluid3D:
+    """Periodic D3Q19 fluid box (epdlb_lb3_* in include/epdlb.h): host arrays
+    are FP64 with shape (planes, nz, ny, nx); work is queued on torch's
+    current stream."""
+
+    def __init__(self, nx, ny, nz, tau, precision=1, device=0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("epdlb needs a ROCm GPU (gfx950); none is visible")
+        self.shape = (nz, ny, nx)
+        self.n = nx * ny * nz
+        self.stream = torch.cuda.current_stream(torch.device("cuda", device))
+        out = _vp()
+        _check(load_library().epdlb_lb3_create(nx, ny, nz, tau, precision, device, _vp(self.stream.cuda_stream),
+                                               ctypes.byref(out)), "epdlb_lb3_create")
+        self.ctx = out
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            load_library().epdlb_lb3_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_populations(self, f):
+        f = _f64(f, 19 * self.n)
+        _check(load_library().epdlb_lb3_set_populations(self.ctx, _ptr(f)), "epdlb_lb3_set_populations")
+
+    def set_equilibrium(self, rho=None, u=None):
+        r = None if rho is None else _f64(rho, self.n)
+        v = None if u is None else _f64(u, 3 * self.n)
+        _check(load_library().epdlb_lb3_set_equilibrium(self.ctx, None if r is None else _ptr(r),
+                                                        None if v is None else _ptr(v)),
+               "epdlb_lb3_set_equilibrium")
+
+    def set_force(self, F=None):
+        a = None if F is None else _f64(F, 3 * self.n)
+        _check(load_library().epdlb_lb3_set_force(self.ctx, None if a is None else _ptr(a)), "epdlb_lb3_set_force")
+
+    def step(self, n=1):
+        _check(load_library().epdlb_lb3_step(self.ctx, n), "epdlb_lb3_step")
+
+    def profile(self, n):
+        ms = np.zeros(n)
+        _check(load_library().epdlb_lb3_profile(self.ctx, n, _ptr(ms)), "epdlb_lb3_profile")
+        return ms
+
+    def sync(self):
+        _check(load_library().epdlb_lb3_sync(self.ctx), "epdlb_lb3_sync")
+
+    def populations(self):
+        f = np.empty((19,) + self.shape)
+        _check(load_library().epdlb_lb3_read_populations(self.ctx, _ptr(f)), "epdlb_lb3_read_populations")
+        return f
+
+    def velocity(self):
+        rho = np.empty(self.shape)
+        u = np.empty((3,) + self.shape)
+        _check(load_library().epdlb_lb3_read_velocity(self.ctx, _ptr(rho), _ptr(u)), "epdlb_lb3_read_velocity")
+        return rho, u

@@ -17,6 +17,7 @@
 #include "nn.hpp"
 #include "obs.hpp"
 #include "cg.hpp"
+#include "lb3.hpp"
 
 using namespace epdlb;
 
@@ -2787,4 +2788,280 @@ void epdlb_nn_destroy(epdlb_nn* t) {
   if (t->mem) (void)hipFree(t->mem);
   if (t->own_stream && t->stream) (void)hipStreamDestroy(t->stream);
   delete t;
+}
+
+// ---------------------------------------------------------------------------
+// Three-dimensional fluid: D3Q19 populations, force and moments of one box.
+// ---------------------------------------------------------------------------
+struct epdlb_lb3 {
+  int device = 0;
+  int nx = 0, ny = 0, nz = 0;
+  long n = 0;
+  int precision = 0;
+  double tau = 1.0;
+  void* mem = nullptr;
+  void* f[2] = {nullptr, nullptr};
+  void* F = nullptr;
+  void* rho = nullptr;
+  void* u = nullptr;
+  int cur = 0;  // f[cur] holds the post-collision populations of the last step
+  bool have_moments = false;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<hipEvent_t> ev;  // start/stop pairs of epdlb_lb3_profile
+  size_t es() const { return precision ? sizeof(float) : sizeof(double); }
+};
+
+namespace {
+
+double lb3_weight(int k) { return k == 0 ? 1.0 / 3.0 : (k < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
+
+template <typename T> lb3::Lb3Args<T> lb3_args(epdlb_lb3* c, int from) {
+  lb3::Lb3Args<T> a;
+  a.fin = static_cast<const T*>(c->f[from]);
+  a.fout = static_cast<T*>(c->f[from ^ 1]);
+  a.F = static_cast<const T*>(c->F);
+  a.rho = static_cast<T*>(c->rho);
+  a.u = static_cast<T*>(c->u);
+  a.nx = c->nx;
+  a.ny = c->ny;
+  a.nz = c->nz;
+  a.n = c->n;
+  a.omega = T(1.0 / c->tau);
+  a.fpre = T(1.0 - 0.5 / c->tau);
+  return a;
+}
+
+dim3 lb3_grid(const epdlb_lb3* c) { return dim3((c->ny + lb3::kRows - 1) / lb3::kRows, c->nz); }
+
+// One step from f[cur] into f[cur ^ 1]; the moments are stored when mom.
+template <typename T> int lb3_launch(epdlb_lb3* c, bool mom) {
+  const auto a = lb3_args<T>(c, c->cur);
+  if (mom)
+    launch_k((lb3::k_lb3<T, true>), lb3_grid(c), dim3(lb3::kThreads), 0, c->stream, a);
+  else
+    launch_k((lb3::k_lb3<T, false>), lb3_grid(c), dim3(lb3::kThreads), 0, c->stream, a);
+  HIPCHK(hipGetLastError());
+  c->cur ^= 1;
+  return EPDLB_OK;
+}
+
+int lb3_steps(epdlb_lb3* c, int64_t n, hipEvent_t* ev) {
+  for (int64_t s = 0; s < n; ++s) {
+    if (ev) {
+      tl_ev_start = ev[2 * s];
+      tl_ev_stop = ev[2 * s + 1];
+    }
+    const bool mom = s + 1 == n;
+    CHK(c->precision ? lb3_launch<float>(c, mom) : lb3_launch<double>(c, mom));
+  }
+  if (n > 0) c->have_moments = true;
+  return EPDLB_OK;
+}
+
+// Host FP64 values -> device planes in the context's precision.
+int lb3_upload(epdlb_lb3* c, void* dst, const double* src, size_t count, const double* minus_w) {
+  if (c->precision) {
+    std::vector<float> h(count);
+    for (size_t i = 0; i < count; ++i) h[i] = float(minus_w ? src[i] - minus_w[i / size_t(c->n)] : src[i]);
+    HIPCHK(hipMemcpyAsync(dst, h.data(), count * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  } else {
+    std::vector<double> h(count);
+    for (size_t i = 0; i < count; ++i) h[i] = minus_w ? src[i] - minus_w[i / size_t(c->n)] : src[i];
+    HIPCHK(hipMemcpyAsync(dst, h.data(), count * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  return EPDLB_OK;
+}
+
+int lb3_download(epdlb_lb3* c, double* dst, const void* src, size_t count, const double* plus_w) {
+  if (c->precision) {
+    std::vector<float> h(count);
+    HIPCHK(hipMemcpyAsync(h.data(), src, count * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < count; ++i) dst[i] = plus_w ? plus_w[i / size_t(c->n)] + double(h[i]) : double(h[i]);
+  } else {
+    std::vector<double> h(count);
+    HIPCHK(hipMemcpyAsync(h.data(), src, count * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < count; ++i) dst[i] = plus_w ? plus_w[i / size_t(c->n)] + h[i] : h[i];
+  }
+  return EPDLB_OK;
+}
+
+bool all_finite(const double* v, size_t count) {
+  for (size_t i = 0; i < count; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+int epdlb_lb3_create(int32_t nx, int32_t ny, int32_t nz, double tau, int32_t precision, int device, void* stream,
+                     epdlb_lb3** out) {
+  if (!out) return fail(EPDLB_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nx < 1 || ny < 1 || nz < 1 || nx > 4096 || ny > 4096 || nz > 4096)
+    return fail(EPDLB_EINVAL, "nx, ny, nz must lie in [1, 4096]");
+  if (!(tau > 0.5) || !std::isfinite(tau)) return fail(EPDLB_EINVAL, "tau must be a finite value > 1/2");
+  if (precision != 0 && precision != 1) return fail(EPDLB_EINVAL, "precision must be 0 or 1");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= device || device < 0)
+    return fail(EPDLB_ENODEV, "no HIP device with that index");
+  HIPCHK(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(EPDLB_ENODEV, std::string("library built for gfx950, device is ") + prop.gcnArchName);
+  epdlb_lb3* c = new (std::nothrow) epdlb_lb3();
+  if (!c) return fail(EPDLB_ENOMEM, "host allocation failed");
+  c->device = device;
+  c->nx = nx;
+  c->ny = ny;
+  c->nz = nz;
+  c->n = long(nx) * ny * nz;
+  c->precision = precision;
+  c->tau = tau;
+  const size_t plane = align256(size_t(c->n) * c->es());
+  const size_t fbytes = lb3::kQ * plane;
+  const size_t total = 2 * fbytes + 3 * plane + plane + 3 * plane;
+  if (hipMalloc(&c->mem, total) != hipSuccess) {
+    delete c;
+    return fail(EPDLB_ENOMEM, "hipMalloc of the populations failed");
+  }
+  unsigned char* b = static_cast<unsigned char*>(c->mem);
+  c->f[0] = b;
+  c->f[1] = b + fbytes;
+  c->F = b + 2 * fbytes;
+  c->rho = b + 2 * fbytes + 3 * plane;
+  c->u = b + 2 * fbytes + 4 * plane;
+  if (stream) {
+    c->stream = reinterpret_cast<hipStream_t>(stream);
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      epdlb_lb3_destroy(c);
+      return fail(EPDLB_EHIP, "hipStreamCreate failed");
+    }
+    c->own_stream = true;
+  }
+  // rest state (g = 0: rho = 1, u = 0) and no force
+  if (hipMemsetAsync(c->mem, 0, total, c->stream) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+    epdlb_lb3_destroy(c);
+    return fail(EPDLB_EHIP, "clearing the populations failed");
+  }
+  *out = c;
+  return EPDLB_OK;
+}
+
+int epdlb_lb3_set_populations(epdlb_lb3* c, const double* f) {
+  if (!c || !f) return fail(EPDLB_EINVAL, "NULL argument");
+  const size_t count = size_t(lb3::kQ) * size_t(c->n);
+  if (!all_finite(f, count)) return fail(EPDLB_EINVAL, "non-finite population");
+  HIPCHK(hipSetDevice(c->device));
+  double w[lb3::kQ];
+  for (int k = 0; k < lb3::kQ; ++k) w[k] = lb3_weight(k);
+  CHK(lb3_upload(c, c->f[c->cur], f, count, w));
+  c->have_moments = false;
+  return EPDLB_OK;
+}
+
+int epdlb_lb3_set_equilibrium(epdlb_lb3* c, const double* rho, const double* u) {
+  if (!c) return fail(EPDLB_EINVAL, "NULL context");
+  const size_t n = size_t(c->n);
+  if ((rho && !all_finite(rho, n)) || (u && !all_finite(u, 3 * n))) return fail(EPDLB_EINVAL, "non-finite moment");
+  if (rho)
+    for (size_t i = 0; i < n; ++i)
+      if (!(rho[i] > 0.0)) return fail(EPDLB_EINVAL, "density must be > 0");
+  HIPCHK(hipSetDevice(c->device));
+  std::vector<double> ones;
+  if (!rho) ones.assign(n, 1.0);
+  CHK(lb3_upload(c, c->rho, rho ? rho : ones.data(), n, nullptr));
+  if (u) {
+    CHK(lb3_upload(c, c->u, u, 3 * n, nullptr));
+  } else {
+    HIPCHK(hipMemsetAsync(c->u, 0, 3 * n * c->es(), c->stream));
+  }
+  // the arguments of a step from f[cur ^ 1] write f[cur], the state
+  if (c->precision)
+    launch_k((lb3::k_lb3_equilibrium<float>), lb3_grid(c), dim3(lb3::kThreads), 0, c->stream, lb3_args<float>(c, c->cur ^ 1));
+  else
+    launch_k((lb3::k_lb3_equilibrium<double>), lb3_grid(c), dim3(lb3::kThreads), 0, c->stream, lb3_args<double>(c, c->cur ^ 1));
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->have_moments = false;
+  return EPDLB_OK;
+}
+
+int epdlb_lb3_set_force(epdlb_lb3* c, const double* F) {
+  if (!c) return fail(EPDLB_EINVAL, "NULL context");
+  HIPCHK(hipSetDevice(c->device));
+  const size_t count = 3 * size_t(c->n);
+  if (!F) {
+    HIPCHK(hipMemsetAsync(c->F, 0, count * c->es(), c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return EPDLB_OK;
+  }
+  if (!all_finite(F, count)) return fail(EPDLB_EINVAL, "non-finite force");
+  return lb3_upload(c, c->F, F, count, nullptr);
+}
+
+int epdlb_lb3_step(epdlb_lb3* c, int64_t n) {
+  if (!c) return fail(EPDLB_EINVAL, "NULL context");
+  if (n < 0) return fail(EPDLB_EINVAL, "negative step count");
+  HIPCHK(hipSetDevice(c->device));
+  return lb3_steps(c, n, nullptr);
+}
+
+int epdlb_lb3_profile(epdlb_lb3* c, int32_t n, double* ms) {
+  if (!c || !ms) return fail(EPDLB_EINVAL, "NULL argument");
+  if (n < 1 || n > 4096) return fail(EPDLB_EINVAL, "n must lie in [1, 4096]");
+  HIPCHK(hipSetDevice(c->device));
+  while (c->ev.size() < size_t(2 * n)) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    c->ev.push_back(e);
+  }
+  const int r = lb3_steps(c, n, c->ev.data());
+  tl_ev_start = tl_ev_stop = nullptr;
+  CHK(r);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int s = 0; s < n; ++s) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, c->ev[2 * s], c->ev[2 * s + 1]));
+    ms[s] = t;
+  }
+  return EPDLB_OK;
+}
+
+int epdlb_lb3_sync(epdlb_lb3* c) {
+  if (!c) return fail(EPDLB_EINVAL, "NULL context");
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return EPDLB_OK;
+}
+
+int epdlb_lb3_read_populations(epdlb_lb3* c, double* f) {
+  if (!c || !f) return fail(EPDLB_EINVAL, "NULL argument");
+  HIPCHK(hipSetDevice(c->device));
+  double w[lb3::kQ];
+  for (int k = 0; k < lb3::kQ; ++k) w[k] = lb3_weight(k);
+  return lb3_download(c, f, c->f[c->cur], size_t(lb3::kQ) * size_t(c->n), w);
+}
+
+int epdlb_lb3_read_velocity(epdlb_lb3* c, double* rho, double* u) {
+  if (!c || !rho || !u) return fail(EPDLB_EINVAL, "NULL argument");
+  if (!c->have_moments) return fail(EPDLB_ESTATE, "no step since the populations were set");
+  HIPCHK(hipSetDevice(c->device));
+  CHK(lb3_download(c, rho, c->rho, size_t(c->n), nullptr));
+  return lb3_download(c, u, c->u, 3 * size_t(c->n), nullptr);
+}
+
+void epdlb_lb3_destroy(epdlb_lb3* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  if (c->mem) (void)hipFree(c->mem);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
 }

@@ -17,7 +17,7 @@ def declared_functions():
     text = "".join(open(os.path.join(ROOT, "include", f)).read()
                    for f in sorted(os.listdir(os.path.join(ROOT, "include"))) if f.endswith(".h"))
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(epdlb_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(epdlb_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():

@@ -1,0 +1,191 @@
+"""GPU parity of the three-dimensional fluid (D3Q19, epdlb_lb3_* in the C ABI)
+against the FP64 oracle oracle/lb3d_oracle.py on the same seeded inputs.
+
+Bars: FP64 storage agrees with the oracle to 1e-13 (rounding order only);
+FP32 storage keeps the deviations f_i - w_i, whose size here is at most
+about 0.05, to a few ulps per step: 5e-7 absolute on populations and
+velocities after a few steps.  Boxes are ragged against the kernel's tiling
+(64-site row chunks, 4 rows per block) and include the degenerate widths 1.
+At the benchmark's size (256^3, FP32) one step is checked at sampled sites
+(including the faces, where the streaming wraps) with the oracle's per-site
+step, and the exact balances (mass, momentum gain = total force) over the
+whole box after further steps.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lb3d_oracle as L
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _fluid(nx, ny, nz, tau, precision):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1804_02883_amd import Fluid3D
+    return Fluid3D(nx, ny, nz, tau, precision)
+
+
+def _state(shape, seed, amp=0.05, famp=1e-3):
+    rng = np.random.default_rng(seed)
+    rho = 1 + amp * rng.standard_normal(shape)
+    u = amp * rng.standard_normal((3,) + shape)
+    f = L.equilibrium(rho, u) + amp / 36 * rng.standard_normal((19,) + shape)
+    F = famp * rng.standard_normal((3,) + shape)
+    return f, F
+
+
+SHAPES = [(6, 10, 40), (3, 5, 130), (1, 1, 1), (2, 3, 1), (1, 7, 64), (5, 4, 65)]
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-13), (1, 5e-7)])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_steps_vs_oracle(shape, prec, tol):
+    nz, ny, nx = shape
+    say(f"[lb3] {nz}x{ny}x{nx} precision={prec} 4 steps")
+    tau = 0.8
+    f, F = _state(shape, nx * 7 + ny * 3 + nz)
+    fl = _fluid(nx, ny, nz, tau, prec)
+    fl.set_populations(f)
+    fl.set_force(F)
+    if prec == 1:  # the device holds FP32 deviations: start the oracle from those
+        w = L.W19[:, None, None, None]
+        f = w + (f - w).astype(np.float32).astype(np.float64)
+        F = F.astype(np.float32).astype(np.float64)
+    fl.step(4)
+    for _ in range(4):
+        f, rho, u = L.step(f, F, tau)
+    got = fl.populations()
+    grho, gu = fl.velocity()
+    err = np.max(np.abs(got - f))
+    say(f"  max |f - oracle| {err:.2e}, u {np.max(np.abs(gu - u)):.2e}")
+    assert err < tol
+    assert np.max(np.abs(grho - rho)) < tol and np.max(np.abs(gu - u)) < tol
+    fl.close()
+
+
+def test_equilibrium_and_rest_start():
+    nz, ny, nx = 3, 6, 70
+    rng = np.random.default_rng(5)
+    rho = 1 + 0.1 * rng.standard_normal((nz, ny, nx))
+    u = 0.05 * rng.standard_normal((3, nz, ny, nx))
+    fl = _fluid(nx, ny, nz, 1.0, 0)
+    # a new context is at rest: f = w everywhere
+    assert np.max(np.abs(fl.populations() - L.W19[:, None, None, None])) == 0.0
+    fl.set_equilibrium(rho, u)
+    assert np.max(np.abs(fl.populations() - L.equilibrium(rho, u))) < 1e-15
+    fl.set_equilibrium(None, u)
+    assert np.max(np.abs(fl.populations() - L.equilibrium(np.ones_like(rho), u))) < 1e-15
+    fl.set_equilibrium(rho, None)
+    assert np.max(np.abs(fl.populations() - L.equilibrium(rho, np.zeros_like(u)))) < 1e-15
+    fl.close()
+
+
+def test_argument_and_state_errors():
+    from paper_1804_02883_amd import EpdlbError, Fluid3D
+    _fluid(4, 4, 4, 1.0, 0).close()  # skips without a GPU
+    for args in [(0, 4, 4, 1.0), (4, 4, 5000, 1.0), (4, 4, 4, 0.5), (4, 4, 4, float("nan"))]:
+        with pytest.raises(EpdlbError):
+            Fluid3D(*args)
+    with pytest.raises(EpdlbError):
+        Fluid3D(4, 4, 4, 1.0, precision=2)
+    fl = _fluid(4, 4, 4, 1.0, 1)
+    with pytest.raises(EpdlbError):  # no step yet
+        fl.velocity()
+    bad = np.tile(L.W19[:, None, None, None], (1, 4, 4, 4))
+    bad[3, 1, 2, 3] = np.inf
+    with pytest.raises(EpdlbError):
+        fl.set_populations(bad)
+    with pytest.raises(EpdlbError):
+        fl.set_equilibrium(np.zeros((4, 4, 4)), None)
+    with pytest.raises(EpdlbError):
+        fl.set_force(np.full((3, 4, 4, 4), np.nan))
+    fl.step(0)
+    with pytest.raises(EpdlbError):
+        fl.velocity()
+    fl.step(1)
+    rho, u = fl.velocity()
+    assert np.all(rho == 1.0) and np.all(u == 0.0)
+    fl.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_kolmogorov_flow_on_the_gpu(prec):
+    """F_x = F0 sin(k y) on a 64 x 32 x 2 box settles at F0 sin(k y)/(nu k^2)
+    (to O(k^2), as in the oracle's pin), uniform in x and z."""
+    nz, ny, nx, tau, F0 = 2, 32, 64, 1.0, 1e-5
+    k = 2 * np.pi / ny
+    y = np.arange(ny, dtype=np.float64)
+    F = np.zeros((3, nz, ny, nx))
+    F[0] = F0 * np.sin(k * y)[None, :, None]
+    fl = _fluid(nx, ny, nz, tau, prec)
+    fl.set_force(F)
+    fl.step(3000)
+    rho, u = fl.velocity()
+    prof = u[0].mean(axis=(0, 2))
+    got = 2 * np.mean(prof * np.sin(k * y))
+    want = F0 / (L.viscosity(tau) * k * k)
+    say(f"  precision {prec}: amplitude / closed form {got / want:.5f}")
+    assert abs(got / want - 1) < 5e-3
+    assert np.max(np.abs(u[0] - prof[None, :, None])) < 1e-6 * want
+    # no cross flow: exact in FP64, FP32 rounding relaxes over about 1/(nu k^2) steps
+    assert np.max(np.abs(u[1:])) < (1e-9 if prec == 0 else 1e-4) * want
+    fl.close()
+
+
+def test_full_size_sampled_step_and_balances():
+    """256^3, FP32, tau = 0.8: one step at 4000 sampled sites (and all 8
+    corners) against the oracle's per-site step; then 3 more steps and the
+    balances over the whole box."""
+    n = 256
+    shape = (n, n, n)
+    say("[lb3] 256^3 FP32: generating the seeded state")
+    rng = np.random.default_rng(2024)
+    w = L.W19[:, None, None, None]
+    dev = (0.01 * rng.standard_normal((19,) + shape, dtype=np.float32)) * w.astype(np.float32)
+    f = dev.astype(np.float64) + w
+    del dev
+    F = (1e-4 * rng.standard_normal((3,) + shape, dtype=np.float32)).astype(np.float64)
+    tau = 0.8
+    fl = _fluid(n, n, n, tau, 1)
+    fl.set_populations(f)
+    fl.set_force(F)
+    ms = fl.profile(1)
+    say(f"  one launch {ms[0]:.3f} ms")
+    got = fl.populations()
+    rho_g, u_g = fl.velocity()
+    sites = [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(4000)]
+    sites += [(z, y, x) for z in (0, n - 1) for y in (0, n - 1) for x in (0, n - 1)]
+    worst = 0.0
+    for (z, y, x) in sites:
+        o, r, v = L.site(f, F, tau, z, y, x)
+        worst = max(worst, np.max(np.abs(got[:, z, y, x] - o)), abs(rho_g[z, y, x] - r),
+                    np.max(np.abs(u_g[:, z, y, x] - v)))
+    say(f"  sampled max error {worst:.2e}")
+    assert worst < 5e-7
+    # balances of the GPU's own steps: mass exact, momentum grows by the total force
+    c = L.C19.astype(np.float64)
+
+    def totals(a):
+        sums = [float(a[i].sum(dtype=np.float64)) for i in range(19)]
+        return sum(sums), [sum(c[i, d] * sums[i] for i in range(19)) for d in range(3)]
+
+    m0, j0 = totals(got)
+    del f
+    fl.step(3)
+    m1, j1 = totals(fl.populations())
+    N = float(n ** 3)
+    say(f"  mass change per site {(m1 - m0) / N:.2e}")
+    assert abs(m1 - m0) / N < 1e-9
+    for d in range(3):
+        gain = (j1[d] - j0[d]) - 3 * F[d].sum()
+        assert abs(gain) / N < 1e-9, (d, gain / N)
+    fl.close()
