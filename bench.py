@@ -12,7 +12,9 @@ on the residual test, and while the last measured network error exceeds
 9e-4) included; `density_err.in_use` is the largest network error measured
 at an exact step that ended surrogate steps.  `roofline` is the MFMA
 roofline of the 64 -> 64 convolution.  `plain_full_scale` adds the plain
-path on 1024 x 512, N = 64 with its HBM roofline.
+path on 1024 x 512, N = 64 with its HBM roofline, and `fluid3d` the
+three-dimensional D3Q19 fluid on a 256^3 box (FP32) with the HBM roofline of
+its step kernel (paper_1804_02883_amd/fluid3d_timing.py).
 
 `--workload cfg3` (or cfg2, cfg5, cfg4) reports a plain line instead.
 
@@ -50,6 +52,9 @@ MEASURED_TRAFFIC = {
     # mean over the two 64 -> 64 launches of a surrogate step
     ("cfg5q", "nn_conv"): dict(bytes_per_launch=63970359, files=_NN_FILES,
                                source_sha256="4f00c90da1997534e3811f0beb2591c36ceaec6e5898195cfffe087c312feb2d"),
+    # profiles/lb3_fluid3d_256_traffic.md: the step kernel without moment stores
+    ("fluid3d_256", "lb3"): dict(bytes_per_launch=2873793431, files=("lb3.hpp",),
+                                 source_sha256="e7e59f031e128b313dda272b0a26b0ab5c5fe413ad9252a506d9b009c091450e"),
 }
 
 
@@ -276,6 +281,15 @@ def plain_line(args, workload):
                 config=cfgd, roofline=roofline, breakdown=breakdown, shapes=shapes, Q_P=d["Q_P"])
 
 
+def fluid3d_line():
+    """The three-dimensional D3Q19 fluid on a 256^3 box (FP32), with the HBM
+    roofline of its step kernel."""
+    from paper_1804_02883_amd import fluid3d_timing
+    r = fluid3d_timing.measure(256, 40, 1)
+    r["roofline"]["traffic"] = measured_traffic("fluid3d_256", "lb3")
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,8 +308,8 @@ def main():
                     help="LB collision of the plain single-grid workloads: BGK at the preset's tau, or "
                          "the multi-relaxation collision at the paper's eta = eta_B")
     ap.add_argument("--no-secondary", action="store_true",
-                    help="skip the secondary comparison on the line (the 1024x512 plain run for cfg5q, "
-                         "the cfg5q plain vs surrogate run otherwise)")
+                    help="skip the secondary measurements on the line (the 1024x512 plain run for cfg5q, "
+                         "the cfg5q plain vs surrogate run otherwise, and the 256^3 D3Q19 fluid)")
     args = ap.parse_args()
     args.steps_given = args.steps is not None
     if args.gpus != 1:
@@ -313,6 +327,8 @@ def main():
             pl = plain_line(a3, "cfg3")
             out["plain_full_scale"] = dict(workload=pl["config"]["workload"], value=pl["value"],
                                            ms_per_step=pl["ms_per_step"], roofline=pl["roofline"])
+    if not args.no_secondary:
+        out["fluid3d"] = fluid3d_line()
     else:
         out = plain_line(args, args.workload)
         if not args.no_secondary and args.workload != "cfg4":

@@ -947,7 +947,8 @@ class Batch:
 class Fluid3D:
     """Periodic D3Q19 fluid box (epdlb_lb3_* in include/epdlb.h): host arrays
     are FP64 with shape (planes, nz, ny, nx); work is queued on torch's
-    current stream."""
+    current stream, or on a stream of the library's own when that is the
+    null stream."""
 
     def __init__(self, nx, ny, nz, tau, precision=1, device=0):
         import torch

@@ -41,3 +41,11 @@ def test_several_gpus_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_fluid3d_byte_model():
+    """Per site and step: 19 populations read and 19 written plus the 3 force
+    components, in the storage precision."""
+    from paper_1804_02883_amd import fluid3d_timing as ft
+    assert ft.bytes_per_site(1) == 164 and ft.bytes_per_site(0) == 328
+    assert bench.measured_traffic("fluid3d_256", "lb3") is not None
