@@ -189,3 +189,37 @@ def test_full_size_sampled_step_and_balances():
         gain = (j1[d] - j0[d]) - 3 * F[d].sum()
         assert abs(gain) / N < 1e-9, (d, gain / N)
     fl.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 1e-4)])
+def test_reverse_poiseuille_channel_on_the_gpu(prec, tol):
+    """A 48 x 32 x 3 box under the paper's drive (-F0 below the middle in y,
+    +F0 above) for 4000 steps: uniform in x and z, equal to the oracle's
+    channel of one column (relative to the peak speed), and within the
+    lattice's 1.5e-3 of Eq. flow_field."""
+    from oracle import epdlb_oracle as O
+    nz, ny, nx, F0, steps = 3, 32, 48, 1e-6, 4000
+    Y = np.arange(ny) + 0.5
+    Fx = np.where(Y < ny / 2, -F0, F0)
+    F = np.zeros((3, nz, ny, nx))
+    F[0] = Fx[None, :, None]
+    fl = _fluid(nx, ny, nz, 1.0, prec)
+    fl.set_force(F)
+    fl.step(steps)
+    rho, u = fl.velocity()
+    fl.close()
+    f = L.equilibrium(np.ones((1, ny, 1)), np.zeros((3, 1, ny, 1)))
+    F1 = np.zeros((3, 1, ny, 1))
+    F1[0, 0, :, 0] = Fx
+    for _ in range(steps):
+        f, _, u1 = L.step(f, F1, 1.0)
+    ref = u1[0, 0, :, 0]
+    peak = np.max(np.abs(ref))
+    err = np.max(np.abs(u[0] - ref[None, :, None])) / peak
+    exact = O.poiseuille_profile(ny, F0, 1.0)
+    say(f"  precision {prec}: |u - oracle| / peak {err:.2e}, "
+        f"|u - Eq. flow_field| / peak {np.max(np.abs(u[0, 0, :, 0] - exact)) / peak:.2e}")
+    assert err < tol
+    assert np.max(np.abs(u[0, 1, :, 7] - exact)) / np.max(np.abs(exact)) < 1.5e-3
+    # no cross flow beyond the rounding of the stored populations
+    assert np.max(np.abs(u[1:])) < (1e-14 if prec == 0 else 1e-9)

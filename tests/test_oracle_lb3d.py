@@ -187,3 +187,36 @@ def test_kolmogorov_flow_steady_amplitude(axis):
     others = [a for a in range(3) if a != comp]
     assert np.max(np.abs(u[others])) < 1e-12 * want
     assert np.max(np.abs(rho - 1)) < 1e-9
+
+
+def _channel(ny, F0, steps):
+    Y = np.arange(ny) + 0.5
+    Fx = np.where(Y < ny / 2, -F0, F0)
+    F = np.zeros((3, 1, ny, 1))
+    F[0, 0, :, 0] = Fx
+    f = L.equilibrium(np.ones((1, ny, 1)), np.zeros((3, 1, ny, 1)))
+    for _ in range(steps):
+        f, rho, u = L.step(f, F, 1.0)
+    return u, Fx
+
+
+def test_reverse_poiseuille_channel():
+    """The paper's drive (force -F0 in the lower half of the box, +F0 in the
+    upper) settles at the two parabolas of Eq. flow_field, with the
+    second-order discretisation error of the two-dimensional lattice, and
+    satisfies the lattice's discrete steady balance
+    nu (u_{y+1} - 2 u_y + u_{y-1}) = -F_y - (F_{y+1} - 2 F_y + F_{y-1})/12."""
+    from oracle import epdlb_oracle as O
+    F0, errs = 1e-6, []
+    for ny in (16, 32):
+        u, Fx = _channel(ny, F0, 4000)
+        ux = u[0, 0, :, 0]
+        exact = O.poiseuille_profile(ny, F0, 1.0)
+        errs.append(np.max(np.abs(ux - exact)) / np.max(np.abs(exact)))
+        nu = L.viscosity(1.0)
+        lhs = nu * (np.roll(ux, -1) - 2 * ux + np.roll(ux, 1))
+        rhs = -Fx - (np.roll(Fx, -1) - 2 * Fx + np.roll(Fx, 1)) / 12.0
+        assert np.max(np.abs(lhs - rhs)) < 1e-9 * F0
+        assert np.max(np.abs(u[1:])) < 1e-14  # rounding of O(1) populations
+    assert errs[0] < 6e-3 and errs[1] < 1.5e-3
+    assert 3.0 < errs[0] / errs[1] < 5.0
