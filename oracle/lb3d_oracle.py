@@ -24,6 +24,16 @@ R27  The step is the two-dimensional one (reading R12) in three dimensions:
      the second-order equilibrium with relaxation time tau, plus the
      second-order force term (1 - 1/(2 tau)) w_i [3 (c_i - u).F + 9 (c_i.u)(c_i.F)].
      Kinematic viscosity nu = (tau - 1/2)/3 in lattice units.
+R28  The multi-relaxation collision (the paper's, Sec. II, Eq. force_col) in
+     three dimensions, as the two-dimensional one (reading R17) with the trace
+     split of d = 3, where the printed 2/3 and 1/3 apply as printed: the
+     non-equilibrium stress keeps gamma_s of its traceless part and gamma_b of
+     its trace tr/3 I; the forcing stress is
+     Sigma = (1 + gamma_s)/2 [u F + F u - (2/3)(u.F) I] + (1 + gamma_b)/3 (u.F) I;
+     the nine non-hydrodynamic modes are scaled by gamma_g.  Shear viscosity
+     nu = (c_s^2/2)(1 + gamma_s)/(1 - gamma_s), bulk viscosity
+     nu_B = (c_s^2/3)(1 + gamma_b)/(1 - gamma_b) (the paper's relations with d = 3,
+     rho = 1, lattice units).
 """
 import numpy as np
 
@@ -100,3 +110,59 @@ def site(fstar, F, tau, z, y, x):
     Fs = np.array([F[a, z, y, x] for a in range(3)], dtype=np.float64)
     out, rho, u = collide(f.reshape(19, 1, 1, 1), Fs.reshape(3, 1, 1, 1), tau)
     return out[:, 0, 0, 0], float(rho[0, 0, 0]), u[:, 0, 0, 0]
+
+
+def stress_moments(f):
+    """rho, j and Pi = sum f_i c_i c_i (shapes (...), (3, ...), (3, 3, ...))."""
+    c = C19.astype(np.float64)
+    rho = f.sum(axis=0)
+    j = np.einsum("ia,i...->a...", c, f)
+    Pi = np.einsum("ia,ib,i...->ab...", c, c, f)
+    return rho, j, Pi
+
+
+def hermite(rho, j, Pi):
+    """Populations carrying the moments (rho, j, Pi) and nothing else:
+    n_i = w_i [rho + j.c_i/c_s^2 + (Pi - rho c_s^2 I):(c_i c_i - c_s^2 I)/(2 c_s^4)]."""
+    out = np.empty((19,) + np.shape(rho))
+    for i in range(19):
+        c = C19[i].astype(np.float64)
+        h = 0.0
+        for a in range(3):
+            for b in range(3):
+                h = h + (Pi[a, b] - (rho * CS2 if a == b else 0.0)) * (c[a] * c[b] - (CS2 if a == b else 0.0))
+        out[i] = W19[i] * (rho + (j[0] * c[0] + j[1] * c[1] + j[2] * c[2]) / CS2 + h / (2.0 * CS2 * CS2))
+    return out
+
+
+def collide_mrt(f, F, gamma_s, gamma_b, gamma_g):
+    """Multi-relaxation collision with the force term of Eq. force_col in three
+    dimensions (reading R28).  u = (j + F/2)/rho; Pi_eq = rho c_s^2 I + rho u u;
+    the non-equilibrium stress keeps gamma_s of its traceless part and gamma_b
+    of its trace; post-collision moments (rho, j + F, Pi_eq + relaxed + Sigma);
+    the remainder f - hermite(moments of f) is scaled by gamma_g.
+    Returns (f*, rho, u)."""
+    rho, j, Pi = stress_moments(f)
+    u = (j + 0.5 * F) / rho
+    eye = np.eye(3).reshape((3, 3) + (1,) * np.ndim(rho))
+    Pi_eq = rho * CS2 * eye + rho * np.einsum("a...,b...->ab...", u, u)
+    neq = Pi - Pi_eq
+    tr = neq[0, 0] + neq[1, 1] + neq[2, 2]
+    relaxed = gamma_s * (neq - tr / 3.0 * eye) + gamma_b * tr / 3.0 * eye
+    uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2]
+    sym = np.einsum("a...,b...->ab...", u, F) + np.einsum("a...,b...->ab...", F, u)
+    Sigma = 0.5 * (1.0 + gamma_s) * (sym - (2.0 / 3.0) * uF * eye) + (1.0 + gamma_b) / 3.0 * uF * eye
+    post = hermite(rho, j + F, Pi_eq + relaxed + Sigma)
+    ghost = f - hermite(rho, j, Pi)
+    return post + gamma_g * ghost, rho, u
+
+
+def step_mrt(fstar, F, gamma_s, gamma_b, gamma_g):
+    """Stream, then the multi-relaxation collision.  Returns (f*, rho, u)."""
+    return collide_mrt(stream(fstar), F, gamma_s, gamma_b, gamma_g)
+
+
+def mrt_viscosities(gamma_s, gamma_b):
+    """(nu, nu_B) of reading R28."""
+    return (0.5 * CS2 * (1.0 + gamma_s) / (1.0 - gamma_s),
+            CS2 / 3.0 * (1.0 + gamma_b) / (1.0 - gamma_b))

@@ -220,3 +220,87 @@ def test_reverse_poiseuille_channel():
         assert np.max(np.abs(u[1:])) < 1e-14  # rounding of O(1) populations
     assert errs[0] < 6e-3 and errs[1] < 1.5e-3
     assert 3.0 < errs[0] / errs[1] < 5.0
+
+
+# --- the multi-relaxation collision in three dimensions (reading R28) ---
+
+@pytest.mark.parametrize("tau", [0.6, 1.0, 1.7])
+def test_mrt_equal_rates_reduce_to_bgk(tau):
+    """gamma_s = gamma_b = gamma_g = 1 - 1/tau gives the pinned BGK step with its
+    second-order force term, population by population."""
+    f, F = _random_state((3, 4, 5), 21)
+    g = 1.0 - 1.0 / tau
+    a = L.step_mrt(f, F, g, g, g)[0]
+    b = L.step(f, F, tau)[0]
+    assert np.max(np.abs(a - b)) < 1e-15
+
+
+def test_hermite_expansion_carries_its_moments():
+    rng = np.random.default_rng(4)
+    shape = (2, 3, 4)
+    rho = 1 + 0.1 * rng.standard_normal(shape)
+    j = 0.05 * rng.standard_normal((3,) + shape)
+    A = 0.02 * rng.standard_normal((3, 3) + shape)
+    Pi = rho * L.CS2 * np.eye(3).reshape(3, 3, 1, 1, 1) + 0.5 * (A + A.transpose(1, 0, 2, 3, 4))
+    r2, j2, P2 = L.stress_moments(L.hermite(rho, j, Pi))
+    assert np.max(np.abs(r2 - rho)) < 1e-15 and np.max(np.abs(j2 - j)) < 1e-15
+    assert np.max(np.abs(P2 - Pi)) < 1e-15
+
+
+@pytest.mark.parametrize("gs,gb,gg", [(0.2, -0.5, 0.0), (-0.3, 0.6, 0.4)])
+def test_mrt_conservation(gs, gb, gg):
+    f, F = _random_state((4, 3, 5), 22)
+    out, rho, u = L.step_mrt(f, F, gs, gb, gg)
+    c = L.C19.astype(np.float64)
+    assert abs(out.sum() - f.sum()) < 1e-12
+    for a in range(3):
+        j0 = np.sum(np.einsum("i,i...->...", c[:, a], f))
+        j1 = np.sum(np.einsum("i,i...->...", c[:, a], out))
+        assert abs(j1 - (j0 + F[a].sum())) < 1e-12
+
+
+def _wave_rate(gs, gb, kind, n=64, T=1500, t0=200):
+    """Decay rate of a shear wave (u_y(x)) or of a sound wave (rho(x)) along x."""
+    k = 2 * np.pi / n
+    x = np.arange(n, dtype=np.float64)
+    rho0 = np.ones((1, 1, n))
+    u0 = np.zeros((3, 1, 1, n))
+    if kind == "shear":
+        u0[1, 0, 0] = 1e-4 * np.sin(k * x)
+    else:
+        rho0[0, 0] += 1e-4 * np.sin(k * x)
+    f = L.equilibrium(rho0, u0)
+    F = np.zeros((3, 1, 1, n))
+    E = []
+    for _ in range(T):
+        f, r, u = L.step_mrt(f, F, gs, gb, 0.0)
+        if kind == "shear":
+            E.append((2 * np.mean(u[1, 0, 0] * np.sin(k * x))) ** 2)
+        else:  # density and momentum parts of the wave together decay smoothly
+            rk = 2 * np.mean((r[0, 0] - 1) * np.sin(k * x))
+            jk = 2 * np.mean(r[0, 0] * u[0, 0, 0] * np.cos(k * x))
+            E.append(rk * rk + jk * jk / L.CS2)
+    t = np.arange(T)
+    return -np.polyfit(t[t0:], np.log(np.array(E)[t0:]), 1)[0] / 2, k
+
+
+@pytest.mark.parametrize("gs,gb", [(0.2, -0.5), (-0.3, 0.5)])
+def test_mrt_shear_wave_uses_gamma_s_only(gs, gb):
+    rate, k = _wave_rate(gs, gb, "shear")
+    nu, _ = L.mrt_viscosities(gs, gb)
+    assert abs(rate / (nu * k * k) - 1) < 2e-3
+
+
+def test_mrt_sound_attenuation_fixes_the_bulk_viscosity():
+    """A sound wave decays at (k^2/2)(4 nu/3 + nu_B) (three-dimensional
+    Navier-Stokes), with nu_B = (c_s^2/3)(1 + gamma_b)/(1 - gamma_b): the
+    trace split of d = 3.  The difference between two gamma_b isolates nu_B
+    (a d = 2 split would make it 3/2 as large)."""
+    rates = {}
+    for gb in (-0.5, 0.5):
+        rate, k = _wave_rate(0.2, gb, "sound")
+        nu, nuB = L.mrt_viscosities(0.2, gb)
+        assert abs(rate / (k * k / 2 * (4 * nu / 3 + nuB)) - 1) < 1e-2
+        rates[gb] = rate
+    dB = L.mrt_viscosities(0.2, 0.5)[1] - L.mrt_viscosities(0.2, -0.5)[1]
+    assert abs((rates[0.5] - rates[-0.5]) / (k * k / 2 * dB) - 1) < 3e-2
