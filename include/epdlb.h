@@ -476,6 +476,17 @@ int epdlb_lb3_set_populations(epdlb_lb3* c, const double* f);
 int epdlb_lb3_set_equilibrium(epdlb_lb3* c, const double* rho, const double* u);
 /* Body force density F (3 planes), held for every following step; NULL clears it. */
 int epdlb_lb3_set_force(epdlb_lb3* c, const double* F);
+/* Collision of the following steps.  mrt = 0 (the default): BGK at the
+ * context's tau.  mrt = 1: the paper's multi-relaxation collision (Sec. II,
+ * Eq. force_col) with the trace split of three dimensions, where the printed
+ * 2/3 and 1/3 apply: with A = Pi - rho/3 I, N = A - rho u u, t = tr(N)/3,
+ * the post-collision stress is rho u u + gamma_s (N - t I) + gamma_b t I
+ * + (1 + gamma_s)/2 [u F + F u - (2/3)(u.F) I] + (1 + gamma_b)/3 (u.F) I,
+ * the momentum j + F, and the non-hydrodynamic modes are scaled by gamma_g.
+ * Shear viscosity (1/6)(1 + gamma_s)/(1 - gamma_s), bulk viscosity
+ * (1/9)(1 + gamma_b)/(1 - gamma_b) (lattice units); equal factors 1 - 1/tau
+ * give the BGK collision at tau.  EINVAL for a factor outside (-1, 1). */
+int epdlb_lb3_set_collision(epdlb_lb3* c, int32_t mrt, double gamma_s, double gamma_b, double gamma_g);
 /* n steps, queued; the last one also stores rho and u.  Returns before the GPU finishes. */
 int epdlb_lb3_step(epdlb_lb3* c, int64_t n);
 /* n steps as epdlb_lb3_step (1 <= n <= 4096), each launch timed on the GPU

@@ -100,15 +100,19 @@ def step(fstar, F, tau):
     return collide(stream(fstar), F, tau)
 
 
-def site(fstar, F, tau, z, y, x):
+def site(fstar, F, tau, z, y, x, mrt=None):
     """The step at one site, from the pre-streaming populations: the 19
     post-collision values and (rho, u) there.  Gathers the neighbours by index
-    (not by rolling whole planes), for sampled checks of large lattices."""
+    (not by rolling whole planes), for sampled checks of large lattices.
+    mrt = (gamma_s, gamma_b, gamma_g) selects the multi-relaxation collision."""
     nz, ny, nx = fstar.shape[1:]
     f = np.array([fstar[i, (z - C19[i, 2]) % nz, (y - C19[i, 1]) % ny, (x - C19[i, 0]) % nx]
-                  for i in range(19)], dtype=np.float64)
-    Fs = np.array([F[a, z, y, x] for a in range(3)], dtype=np.float64)
-    out, rho, u = collide(f.reshape(19, 1, 1, 1), Fs.reshape(3, 1, 1, 1), tau)
+                  for i in range(19)], dtype=np.float64).reshape(19, 1, 1, 1)
+    Fs = np.array([F[a, z, y, x] for a in range(3)], dtype=np.float64).reshape(3, 1, 1, 1)
+    if mrt is None:
+        out, rho, u = collide(f, Fs, tau)
+    else:
+        out, rho, u = collide_mrt(f, Fs, *mrt)
     return out[:, 0, 0, 0], float(rho[0, 0, 0]), u[:, 0, 0, 0]
 
 

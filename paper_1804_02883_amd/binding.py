@@ -197,6 +197,8 @@ SIGNATURES = {
     "epdlb_lb3_set_populations": (ctypes.c_int, [_vp, _dp]),
     "epdlb_lb3_set_equilibrium": (ctypes.c_int, [_vp, _dp, _dp]),
     "epdlb_lb3_set_force": (ctypes.c_int, [_vp, _dp]),
+    "epdlb_lb3_set_collision": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_double]),
     "epdlb_lb3_step": (ctypes.c_int, [_vp, ctypes.c_int64]),
     "epdlb_lb3_profile": (ctypes.c_int, [_vp, ctypes.c_int32, _dp]),
     "epdlb_lb3_sync": (ctypes.c_int, [_vp]),
@@ -987,6 +989,11 @@ class Fluid3D:
     def set_force(self, F=None):
         a = None if F is None else _f64(F, 3 * self.n)
         _check(load_library().epdlb_lb3_set_force(self.ctx, None if a is None else _ptr(a)), "epdlb_lb3_set_force")
+
+    def set_collision(self, mrt, gamma_s=0.0, gamma_b=0.0, gamma_g=0.0):
+        """mrt = 0: BGK at tau; 1: the multi-relaxation collision with these factors."""
+        _check(load_library().epdlb_lb3_set_collision(self.ctx, mrt, gamma_s, gamma_b, gamma_g),
+               "epdlb_lb3_set_collision")
 
     def step(self, n=1):
         _check(load_library().epdlb_lb3_step(self.ctx, n), "epdlb_lb3_step")

@@ -18,6 +18,7 @@
 #include "obs.hpp"
 #include "cg.hpp"
 #include "lb3.hpp"
+#include "lb3_mrt.hpp"
 
 using namespace epdlb;
 
@@ -2806,6 +2807,8 @@ struct epdlb_lb3 {
   void* u = nullptr;
   int cur = 0;  // f[cur] holds the post-collision populations of the last step
   bool have_moments = false;
+  int mrt = 0;  // 0: BGK at tau; 1: multi-relaxation with the factors below
+  double gs = 0.0, gb = 0.0, gg = 0.0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::vector<hipEvent_t> ev;  // start/stop pairs of epdlb_lb3_profile
@@ -2837,6 +2840,20 @@ dim3 lb3_grid(const epdlb_lb3* c) { return dim3((c->ny + lb3::kRows - 1) / lb3::
 // One step from f[cur] into f[cur ^ 1]; the moments are stored when mom.
 template <typename T> int lb3_launch(epdlb_lb3* c, bool mom) {
   const auto a = lb3_args<T>(c, c->cur);
+  if (c->mrt) {
+    lb3::Lb3MrtArgs<T> m;
+    m.b = a;
+    m.gs = T(c->gs);
+    m.gb = T(c->gb);
+    m.gg = T(c->gg);
+    if (mom)
+      launch_k((lb3::k_lb3_mrt<T, true>), lb3_grid(c), dim3(lb3::kThreads), 0, c->stream, m);
+    else
+      launch_k((lb3::k_lb3_mrt<T, false>), lb3_grid(c), dim3(lb3::kThreads), 0, c->stream, m);
+    HIPCHK(hipGetLastError());
+    c->cur ^= 1;
+    return EPDLB_OK;
+  }
   if (mom)
     launch_k((lb3::k_lb3<T, true>), lb3_grid(c), dim3(lb3::kThreads), 0, c->stream, a);
   else
@@ -3004,6 +3021,20 @@ int epdlb_lb3_set_force(epdlb_lb3* c, const double* F) {
   }
   if (!all_finite(F, count)) return fail(EPDLB_EINVAL, "non-finite force");
   return lb3_upload(c, c->F, F, count, nullptr);
+}
+
+int epdlb_lb3_set_collision(epdlb_lb3* c, int32_t mrt, double gamma_s, double gamma_b, double gamma_g) {
+  if (!c) return fail(EPDLB_EINVAL, "NULL context");
+  if (mrt != 0 && mrt != 1) return fail(EPDLB_EINVAL, "mrt must be 0 or 1");
+  if (mrt) {
+    for (double g : {gamma_s, gamma_b, gamma_g})
+      if (!(g > -1.0 && g < 1.0)) return fail(EPDLB_EINVAL, "gamma_s, gamma_b, gamma_g must lie in (-1, 1)");
+    c->gs = gamma_s;
+    c->gb = gamma_b;
+    c->gg = gamma_g;
+  }
+  c->mrt = mrt;
+  return EPDLB_OK;
 }
 
 int epdlb_lb3_step(epdlb_lb3* c, int64_t n) {

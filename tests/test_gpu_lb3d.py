@@ -223,3 +223,126 @@ def test_reverse_poiseuille_channel_on_the_gpu(prec, tol):
     assert np.max(np.abs(u[0, 1, :, 7] - exact)) / np.max(np.abs(exact)) < 1.5e-3
     # no cross flow beyond the rounding of the stored populations
     assert np.max(np.abs(u[1:])) < (1e-14 if prec == 0 else 1e-9)
+
+
+# --- the multi-relaxation collision (epdlb_lb3_set_collision) ---
+
+GAMMAS = [(0.2, -0.5, 0.0), (-0.3, 0.6, 0.4)]
+
+
+@pytest.mark.parametrize("gam", GAMMAS)
+@pytest.mark.parametrize("prec,tol", [(0, 1e-13), (1, 5e-7)])
+@pytest.mark.parametrize("shape", [(6, 10, 40), (3, 5, 130), (1, 1, 1), (5, 4, 65)])
+def test_mrt_steps_vs_oracle(shape, prec, tol, gam):
+    nz, ny, nx = shape
+    say(f"[lb3 mrt] {nz}x{ny}x{nx} precision={prec} gammas={gam} 4 steps")
+    f, F = _state(shape, nx * 5 + ny + nz)
+    fl = _fluid(nx, ny, nz, 1.0, prec)
+    fl.set_collision(1, *gam)
+    fl.set_populations(f)
+    fl.set_force(F)
+    if prec == 1:
+        w = L.W19[:, None, None, None]
+        f = w + (f - w).astype(np.float32).astype(np.float64)
+        F = F.astype(np.float32).astype(np.float64)
+    fl.step(4)
+    for _ in range(4):
+        f, rho, u = L.step_mrt(f, F, *gam)
+    got = fl.populations()
+    grho, gu = fl.velocity()
+    err = np.max(np.abs(got - f))
+    say(f"  max |f - oracle| {err:.2e}")
+    assert err < tol
+    assert np.max(np.abs(grho - rho)) < tol and np.max(np.abs(gu - u)) < tol
+    fl.close()
+
+
+def test_mrt_equal_rates_match_bgk_kernel_and_errors():
+    """Factors 1 - 1/tau reproduce the BGK kernel at tau (FP64, to rounding);
+    factors outside (-1, 1) are rejected; mrt = 0 returns to BGK."""
+    from paper_1804_02883_amd import EpdlbError
+    shape = (4, 6, 70)
+    f, F = _state(shape, 99)
+    out = []
+    for mrt in (0, 1):
+        fl = _fluid(70, 6, 4, 0.8, 0)
+        if mrt:
+            fl.set_collision(1, 1 - 1 / 0.8, 1 - 1 / 0.8, 1 - 1 / 0.8)
+        fl.set_populations(f)
+        fl.set_force(F)
+        fl.step(3)
+        out.append(fl.populations())
+        for bad in [(1.0, 0.0, 0.0), (0.0, -1.0, 0.0), (0.0, 0.0, float("nan"))]:
+            with pytest.raises(EpdlbError):
+                fl.set_collision(1, *bad)
+        with pytest.raises(EpdlbError):
+            fl.set_collision(2)
+        fl.close()
+    assert np.max(np.abs(out[0] - out[1])) < 1e-15
+
+
+def test_mrt_full_size_sampled_step():
+    """256^3 FP32 with the multi-relaxation collision: one step at 2000 sampled
+    sites and the 8 corners against the oracle's per-site step."""
+    n = 256
+    shape = (n, n, n)
+    gam = (0.2, -0.5, 0.1)
+    rng = np.random.default_rng(2025)
+    w = L.W19[:, None, None, None]
+    dev = (0.01 * rng.standard_normal((19,) + shape, dtype=np.float32)) * w.astype(np.float32)
+    f = dev.astype(np.float64) + w
+    del dev
+    F = (1e-4 * rng.standard_normal((3,) + shape, dtype=np.float32)).astype(np.float64)
+    fl = _fluid(n, n, n, 1.0, 1)
+    fl.set_collision(1, *gam)
+    fl.set_populations(f)
+    fl.set_force(F)
+    ms = fl.profile(1)
+    say(f"  one multi-relaxation launch {ms[0]:.3f} ms")
+    got = fl.populations()
+    rho_g, u_g = fl.velocity()
+    fl.close()
+    sites = [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(2000)]
+    sites += [(z, y, x) for z in (0, n - 1) for y in (0, n - 1) for x in (0, n - 1)]
+    worst = 0.0
+    for (z, y, x) in sites:
+        o, r, v = L.site(f, F, 0.0, z, y, x, mrt=gam)
+        worst = max(worst, np.max(np.abs(got[:, z, y, x] - o)), abs(rho_g[z, y, x] - r),
+                    np.max(np.abs(u_g[:, z, y, x] - v)))
+    say(f"  sampled max error {worst:.2e}")
+    assert worst < 5e-7
+
+
+def test_mrt_channel_uses_the_shear_viscosity():
+    """The reverse-Poiseuille drive with the multi-relaxation collision
+    (gamma_s = 0.2, gamma_b = -0.5, gamma_g = 0), FP64, 4000 steps: equal to the
+    oracle's one-column channel, and Eq. flow_field with
+    nu = (1/6)(1 + gamma_s)/(1 - gamma_s) within 5e-3 (the oracle's own
+    discretisation error here is 3.9e-3)."""
+    from oracle import epdlb_oracle as O
+    nz, ny, nx, F0, steps = 2, 32, 64, 1e-6, 4000
+    gs, gb = 0.2, -0.5
+    Y = np.arange(ny) + 0.5
+    Fx = np.where(Y < ny / 2, -F0, F0)
+    F = np.zeros((3, nz, ny, nx))
+    F[0] = Fx[None, :, None]
+    fl = _fluid(nx, ny, nz, 1.0, 0)
+    fl.set_collision(1, gs, gb, 0.0)
+    fl.set_force(F)
+    fl.step(steps)
+    _, u = fl.velocity()
+    fl.close()
+    f = L.equilibrium(np.ones((1, ny, 1)), np.zeros((3, 1, ny, 1)))
+    F1 = np.zeros((3, 1, ny, 1))
+    F1[0, 0, :, 0] = Fx
+    for _ in range(steps):
+        f, _, u1 = L.step_mrt(f, F1, gs, gb, 0.0)
+    ref = u1[0, 0, :, 0]
+    peak = np.max(np.abs(ref))
+    err = np.max(np.abs(u[0] - ref[None, :, None])) / peak
+    nu = L.mrt_viscosities(gs, gb)[0]
+    exact = O.poiseuille_profile(ny, F0, 1.0, nu=nu)
+    err_ex = np.max(np.abs(u[0, 1, :, 5] - exact)) / np.max(np.abs(exact))
+    say(f"  |u - oracle| / peak {err:.2e}, |u - Eq. flow_field| / peak {err_ex:.2e}")
+    assert err < 1e-10
+    assert err_ex < 5e-3

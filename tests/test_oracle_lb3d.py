@@ -304,3 +304,12 @@ def test_mrt_sound_attenuation_fixes_the_bulk_viscosity():
         rates[gb] = rate
     dB = L.mrt_viscosities(0.2, 0.5)[1] - L.mrt_viscosities(0.2, -0.5)[1]
     assert abs((rates[0.5] - rates[-0.5]) / (k * k / 2 * dB) - 1) < 3e-2
+
+
+def test_site_mrt_matches_whole_lattice_step():
+    f, F = _random_state((3, 4, 5), 23)
+    out, rho, u = L.step_mrt(f, F, 0.2, -0.4, 0.3)
+    for z, y, x in [(0, 0, 0), (2, 3, 4), (1, 2, 0), (0, 3, 2)]:
+        o, r, v = L.site(f, F, 0.0, z, y, x, mrt=(0.2, -0.4, 0.3))
+        assert np.allclose(o, out[:, z, y, x], rtol=0, atol=1e-15)
+        assert abs(r - rho[z, y, x]) < 1e-15 and np.allclose(v, u[:, z, y, x], rtol=0, atol=1e-15)
