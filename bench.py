@@ -281,12 +281,31 @@ def plain_line(args, workload):
                 config=cfgd, roofline=roofline, breakdown=breakdown, shapes=shapes, Q_P=d["Q_P"])
 
 
-def fluid3d_line():
+def fluid3d_cpu_baseline(seconds=3.0, n=64):
+    """The FP64 NumPy oracle's BGK step on an n^3 box (elementwise NumPy: one
+    thread), for `seconds` of host time."""
+    import numpy as np
+    from oracle import lb3d_oracle as L3
+    rng = np.random.default_rng(3)
+    f = L3.equilibrium(np.ones((n, n, n)), 1e-3 * rng.standard_normal((3, n, n, n)))
+    F = 1e-5 * rng.standard_normal((3, n, n, n))
+    steps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        f, _, _ = L3.step(f, F, 0.8)
+        steps += 1
+    dt = time.perf_counter() - t0
+    return dict(value=steps * n ** 3 / dt, unit="site-updates/s", cores=1, kind="oracle",
+                sample=f"{steps} BGK steps of a {n}^3 box, FP64 NumPy oracle, single thread, {dt:.1f} s")
+
+
+def fluid3d_line(cpu=True):
     """The three-dimensional D3Q19 fluid on a 256^3 box (FP32), with the HBM
     roofline of its step kernel."""
     from paper_1804_02883_amd import fluid3d_timing
     r = fluid3d_timing.measure(256, 40, 1)
     r["roofline"]["traffic"] = measured_traffic("fluid3d_256", "lb3")
+    if cpu:
+        r["cpu_baseline"] = fluid3d_cpu_baseline()
     return r
 
 
@@ -328,7 +347,7 @@ def main():
             out["plain_full_scale"] = dict(workload=pl["config"]["workload"], value=pl["value"],
                                            ms_per_step=pl["ms_per_step"], roofline=pl["roofline"])
     if not args.no_secondary:
-        out["fluid3d"] = fluid3d_line()
+        out["fluid3d"] = fluid3d_line(cpu=not args.no_cpu_baseline)
     else:
         out = plain_line(args, args.workload)
         if not args.no_secondary and args.workload != "cfg4":

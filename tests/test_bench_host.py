@@ -49,3 +49,8 @@ def test_fluid3d_byte_model():
     from paper_1804_02883_amd import fluid3d_timing as ft
     assert ft.bytes_per_site(1) == 164 and ft.bytes_per_site(0) == 328
     assert bench.measured_traffic("fluid3d_256", "lb3") is not None
+
+
+def test_fluid3d_cpu_baseline_runs():
+    r = bench.fluid3d_cpu_baseline(seconds=0.2, n=16)
+    assert r["kind"] == "oracle" and r["value"] > 0 and r["cores"] == 1
