@@ -346,3 +346,59 @@ def test_mrt_channel_uses_the_shear_viscosity():
     say(f"  |u - oracle| / peak {err:.2e}, |u - Eq. flow_field| / peak {err_ex:.2e}")
     assert err < 1e-10
     assert err_ex < 5e-3
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 4096), (1, 4096, 1), (4096, 1, 1), (2, 3, 4096)])
+def test_maximum_side_vs_oracle(shape):
+    """A side at the 4096 limit: a wave walking 64 chunks of one row, a grid of
+    1024 row blocks, or 4096 z-planes (the grid's second dimension); FP64,
+    both collisions, 2 steps."""
+    nz, ny, nx = shape
+    say(f"[lb3] maximum side {nz}x{ny}x{nx}")
+    f0, F = _state(shape, 4096 + nx + 2 * ny)
+    for gam in (None, (0.2, -0.5, 0.3)):
+        fl = _fluid(nx, ny, nz, 0.9, 0)
+        if gam:
+            fl.set_collision(1, *gam)
+        fl.set_populations(f0)
+        fl.set_force(F)
+        fl.step(2)
+        f = f0
+        for _ in range(2):
+            f = (L.step(f, F, 0.9) if gam is None else L.step_mrt(f, F, *gam))[0]
+        assert np.max(np.abs(fl.populations() - f)) < 1e-13
+        fl.close()
+
+
+@pytest.mark.parametrize("mrt", [0, 1])
+def test_fp32_long_run_balances(mrt):
+    """48^3 FP32 under a zero-mean random force, 500 steps: no systematic mass
+    drift (below 1e-7 per site, against 500 steps of single-precision rounding
+    of deviations near 1e-3), and the momentum gain equals 500 times the total
+    force to the same order."""
+    n, steps = 48, 500
+    shape = (n, n, n)
+    rng = np.random.default_rng(48)
+    F = 1e-6 * rng.standard_normal((3,) + shape)
+    F -= F.mean(axis=(1, 2, 3), keepdims=True)
+    F = F.astype(np.float32).astype(np.float64)
+    fl = _fluid(n, n, n, 0.8, 1)
+    if mrt:
+        fl.set_collision(1, 1 - 1 / 0.8, 0.3, 0.0)
+    fl.set_equilibrium(1 + 1e-3 * rng.standard_normal(shape), 1e-3 * rng.standard_normal((3,) + shape))
+    c = L.C19.astype(np.float64)
+
+    def totals(a):
+        sums = [float(a[i].sum(dtype=np.float64)) for i in range(19)]
+        return sum(sums), np.array([sum(c[i, d] * sums[i] for i in range(19)) for d in range(3)])
+
+    m0, j0 = totals(fl.populations())
+    fl.step(steps)
+    m1, j1 = totals(fl.populations())
+    fl.close()
+    N = float(n ** 3)
+    drift = (m1 - m0) / N
+    dj = (j1 - j0 - steps * F.reshape(3, -1).sum(axis=1)) / N
+    say(f"  collision {'mrt' if mrt else 'bgk'}: mass drift per site {drift:.2e}, momentum {np.max(np.abs(dj)):.2e}")
+    assert abs(drift) < 1e-7
+    assert np.max(np.abs(dj)) < 1e-7
