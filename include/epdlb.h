@@ -500,6 +500,28 @@ int epdlb_lb3_read_populations(epdlb_lb3* c, double* f);
 int epdlb_lb3_read_velocity(epdlb_lb3* c, double* rho, double* u);
 void epdlb_lb3_destroy(epdlb_lb3* c);
 
+/* Chain propagators and densities on a three-dimensional periodic grid of
+ * nx*ny*nz sites (powers of two up to 512), the paper's Sec. II (the split
+ * step q_{j+1} = E_j K (E_j q_j), E_j = exp(-(w_j - c_j)/2), K = exp(R_G^2
+ * Laplacian ds) with |k|^2 = kx^2 + ky^2 + kz^2; the density integrals with
+ * trapezoid contour weights; Eq. phi_s), in three dimensions as the paper
+ * allows (end of Sec. II); volume element dx^3.  The gauge constants c are
+ * the site means of the fields.  FP64 (precision 0) or FP32 (1) planes, FP64
+ * sums.  Host arrays FP64, 3 planes [I][z][y][x] (x contiguous): omega in
+ * (wA, wB, wS), phi out (Phi_A, Phi_B, Phi_S).  The context owns its device
+ * memory (2 (N + 1) + 8 planes); work runs on its stream (the caller's, or
+ * its own when stream is NULL).  EINVAL for a bad size or parameter or a
+ * non-finite potential; ENONFINITE when Q_P or Q_S is not finite. */
+typedef struct epdlb_epd3 epdlb_epd3;
+int epdlb_epd3_create(int32_t nx, int32_t ny, int32_t nz, int32_t n_contour, double f_A, double phi_P,
+                      double R_G, double dx, int32_t precision, int device, void* stream, epdlb_epd3** out);
+/* Densities of omega; Q_P = dx^3 sum q_N, Q_S = dx^3 sum exp(-(wS - cS)) (either may be NULL).  Synchronous. */
+int epdlb_epd3_densities(epdlb_epd3* c, const double* omega, double* phi, double* Q_P, double* Q_S);
+/* reps evaluations of the potentials last passed in, timed with events on the
+ * stream; ms receives the mean GPU time per evaluation.  Synchronous. */
+int epdlb_epd3_time(epdlb_epd3* c, int32_t reps, double* ms);
+void epdlb_epd3_destroy(epdlb_epd3* c);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char* epdlb_last_error(void);
 

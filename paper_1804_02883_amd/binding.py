@@ -205,6 +205,12 @@ SIGNATURES = {
     "epdlb_lb3_read_populations": (ctypes.c_int, [_vp, _dp]),
     "epdlb_lb3_read_velocity": (ctypes.c_int, [_vp, _dp, _dp]),
     "epdlb_lb3_destroy": (None, [_vp]),
+    "epdlb_epd3_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_int32, ctypes.c_int, _vp, _P(_vp)]),
+    "epdlb_epd3_densities": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp]),
+    "epdlb_epd3_time": (ctypes.c_int, [_vp, ctypes.c_int32, _dp]),
+    "epdlb_epd3_destroy": (None, [_vp]),
     "epdlb_last_error": (ctypes.c_char_p, []),
 }
 
@@ -1016,3 +1022,47 @@ class Fluid3D:
         u = np.empty((3,) + self.shape)
         _check(load_library().epdlb_lb3_read_velocity(self.ctx, _ptr(rho), _ptr(u)), "epdlb_lb3_read_velocity")
         return rho, u
+
+
+class Densities3D:
+    """Chain propagators and densities on a periodic 3D grid (epdlb_epd3_* in
+    include/epdlb.h); host arrays FP64 with shape (3, nz, ny, nx)."""
+
+    def __init__(self, nx, ny, nz, n_contour, f_A, phi_P, R_G=1.0, dx=1.0 / 3.0, precision=1, device=0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("epdlb needs a ROCm GPU (gfx950); none is visible")
+        self.shape = (nz, ny, nx)
+        self.n = nx * ny * nz
+        self.stream = torch.cuda.current_stream(torch.device("cuda", device))
+        out = _vp()
+        _check(load_library().epdlb_epd3_create(nx, ny, nz, n_contour, f_A, phi_P, R_G, dx, precision, device,
+                                                _vp(self.stream.cuda_stream), ctypes.byref(out)),
+               "epdlb_epd3_create")
+        self.ctx = out
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            load_library().epdlb_epd3_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def densities(self, omega):
+        """(phi (3, nz, ny, nx), Q_P, Q_S) of the potentials omega."""
+        w = _f64(omega, 3 * self.n)
+        phi = np.empty((3,) + self.shape)
+        qp = ctypes.c_double()
+        qs = ctypes.c_double()
+        _check(load_library().epdlb_epd3_densities(self.ctx, _ptr(w), _ptr(phi), ctypes.byref(qp), ctypes.byref(qs)),
+               "epdlb_epd3_densities")
+        return phi, qp.value, qs.value
+
+    def time(self, reps):
+        ms = ctypes.c_double()
+        _check(load_library().epdlb_epd3_time(self.ctx, reps, ctypes.byref(ms)), "epdlb_epd3_time")
+        return ms.value

@@ -19,6 +19,7 @@
 #include "cg.hpp"
 #include "lb3.hpp"
 #include "lb3_mrt.hpp"
+#include "epd3.hpp"
 
 using namespace epdlb;
 
@@ -3092,6 +3093,275 @@ void epdlb_lb3_destroy(epdlb_lb3* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  if (c->mem) (void)hipFree(c->mem);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+// ---------------------------------------------------------------------------
+// Chain propagators and densities on a three-dimensional grid.
+// ---------------------------------------------------------------------------
+struct epdlb_epd3 {
+  int device = 0;
+  int nx = 0, ny = 0, nz = 0;
+  long n = 0;
+  int N = 0;
+  double f_A = 0.5, phi_P = 0.1, R_G = 1.0, dx = 1.0;
+  int precision = 0;
+  void* mem = nullptr;
+  void* w = nullptr;    // 3 planes
+  void* phi = nullptr;  // 3 planes
+  void* q = nullptr;    // N + 1 planes
+  void* qb = nullptr;   // N + 1 planes
+  void* C = nullptr;    // n complex
+  double* part = nullptr;
+  double* sums = nullptr;  // 16
+  double* nodes = nullptr; // wA_j, wB_j: 2 (N + 1)
+  std::vector<double> seg;  // A-content of each contour segment
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  size_t es() const { return precision ? sizeof(float) : sizeof(double); }
+};
+
+namespace {
+
+bool pow2_upto(int v, int m) { return v >= 1 && v <= m && (v & (v - 1)) == 0; }
+
+template <typename T> int p3_fft(epdlb_epd3* c, int axis, int mode) {
+  epd3::LineArgs A;
+  A.nx = c->nx;
+  A.ny = c->ny;
+  A.nz = c->nz;
+  A.mode = mode;
+  A.heat = c->R_G * c->R_G / c->N * (2.0 * M_PI / c->dx) * (2.0 * M_PI / c->dx);
+  if (axis == 0) {
+    A.L = c->nx; A.st = 1; A.count = long(c->ny) * c->nz; A.g = 1; A.gs = c->nx; A.gi = 0;
+  } else if (axis == 1) {
+    A.L = c->ny; A.st = c->nx; A.count = long(c->nx) * c->nz; A.g = c->nx; A.gs = long(c->nx) * c->ny; A.gi = 1;
+  } else {
+    A.L = c->nz; A.st = long(c->nx) * c->ny; A.count = long(c->nx) * c->ny; A.g = 1; A.gs = 1; A.gi = 0;
+  }
+  if (A.L == 1 && mode != 2) return EPDLB_OK;  // a transform of length 1 is the identity
+  const int TL = A.L > 1 ? A.L / 2 : 1;
+  const long lines = epd3::kThreads / TL;
+  const size_t lds = size_t(2) * lines * A.L * sizeof(epd3::Cx<T>);
+  const long blocks = (A.count + lines - 1) / lines;
+  launch_k((epd3::k_p3_fft<T>), dim3(unsigned(blocks)), dim3(epd3::kThreads), lds, c->stream,
+           static_cast<epd3::Cx<T>*>(c->C), A);
+  HIPCHK(hipGetLastError());
+  return EPDLB_OK;
+}
+
+template <typename T> int p3_sum(epdlb_epd3* c, const T* a, int expo, const double* shift_sum, double* out) {
+  launch_k((epd3::k_p3_sum<T>), dim3(epd3::kRedBlocks), dim3(epd3::kThreads), 0, c->stream, a, c->n, expo,
+           shift_sum, 1.0 / double(c->n), c->part);
+  HIPCHK(hipGetLastError());
+  launch_k(epd3::k_p3_finish, dim3(1), dim3(epd3::kThreads), 0, c->stream, static_cast<const double*>(c->part),
+           epd3::kRedBlocks, out);
+  HIPCHK(hipGetLastError());
+  return EPDLB_OK;
+}
+
+template <typename T> int p3_densities(epdlb_epd3* c) {
+  const long n = c->n;
+  const T* w = static_cast<const T*>(c->w);
+  const T *wA = w, *wB = w + n, *wS = w + 2 * n;
+  const double inv_n = 1.0 / double(n);
+  const dim3 eg(unsigned(std::min<long>((n + epd3::kThreads - 1) / epd3::kThreads, 4096)));
+  CHK(p3_sum<T>(c, wA, 0, nullptr, c->sums + 0));
+  CHK(p3_sum<T>(c, wB, 0, nullptr, c->sums + 2));
+  CHK(p3_sum<T>(c, wS, 0, nullptr, c->sums + 4));
+  for (int chain = 0; chain < 2; ++chain) {
+    T* q = static_cast<T*>(chain ? c->qb : c->q);
+    launch_k((epd3::k_p3_fill<T>), eg, dim3(epd3::kThreads), 0, c->stream, q, T(1), n);
+    HIPCHK(hipGetLastError());
+    for (int j = 0; j < c->N; ++j) {
+      const int seg = chain ? c->N - 1 - j : j;
+      const T a = T(c->seg[seg]);
+      launch_k((epd3::k_p3_pre<T>), eg, dim3(epd3::kThreads), 0, c->stream, wA, wB,
+               static_cast<const double*>(c->sums), inv_n, a, static_cast<const T*>(q + long(j) * n),
+               static_cast<epd3::Cx<T>*>(c->C), n);
+      HIPCHK(hipGetLastError());
+      CHK(p3_fft<T>(c, 0, -1));
+      CHK(p3_fft<T>(c, 1, -1));
+      CHK(p3_fft<T>(c, 2, 2));
+      CHK(p3_fft<T>(c, 1, 1));
+      CHK(p3_fft<T>(c, 0, 1));
+      launch_k((epd3::k_p3_post<T>), eg, dim3(epd3::kThreads), 0, c->stream, wA, wB,
+               static_cast<const double*>(c->sums), inv_n, a, static_cast<const epd3::Cx<T>*>(c->C),
+               q + long(j + 1) * n, n);
+      HIPCHK(hipGetLastError());
+    }
+  }
+  CHK(p3_sum<T>(c, static_cast<const T*>(c->q) + long(c->N) * n, 0, nullptr, c->sums + 6));
+  CHK(p3_sum<T>(c, wS, 1, c->sums + 4, c->sums + 8));
+  epd3::DensArgs D;
+  D.N = c->N;
+  D.n = n;
+  D.V_over_dV = double(n);
+  D.phiP = c->phi_P;
+  D.wAn = c->nodes;
+  D.wBn = c->nodes + (c->N + 1);
+  D.sums = c->sums;
+  D.inv_n = inv_n;
+  launch_k((epd3::k_p3_density<T>), eg, dim3(epd3::kThreads), 0, c->stream, static_cast<const T*>(c->q),
+           static_cast<const T*>(c->qb), wS, static_cast<T*>(c->phi), D);
+  HIPCHK(hipGetLastError());
+  return EPDLB_OK;
+}
+
+}  // namespace
+
+int epdlb_epd3_create(int32_t nx, int32_t ny, int32_t nz, int32_t n_contour, double f_A, double phi_P, double R_G,
+                      double dx, int32_t precision, int device, void* stream, epdlb_epd3** out) {
+  if (!out) return fail(EPDLB_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!pow2_upto(nx, epd3::kMaxLen) || !pow2_upto(ny, epd3::kMaxLen) || !pow2_upto(nz, epd3::kMaxLen))
+    return fail(EPDLB_EINVAL, "nx, ny, nz must be powers of two in [1, 512]");
+  if (n_contour < 2 || n_contour > 256) return fail(EPDLB_EINVAL, "n_contour must be in [2, 256]");
+  if (!(f_A > 0.0 && f_A < 1.0) || !(phi_P > 0.0 && phi_P < 1.0))
+    return fail(EPDLB_EINVAL, "f_A and phi_P must lie in (0, 1)");
+  if (!(R_G > 0.0) || !(dx > 0.0) || !std::isfinite(R_G) || !std::isfinite(dx))
+    return fail(EPDLB_EINVAL, "R_G and dx must be finite and > 0");
+  if (precision != 0 && precision != 1) return fail(EPDLB_EINVAL, "precision must be 0 or 1");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= device || device < 0)
+    return fail(EPDLB_ENODEV, "no HIP device with that index");
+  HIPCHK(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(EPDLB_ENODEV, std::string("library built for gfx950, device is ") + prop.gcnArchName);
+  epdlb_epd3* c = new (std::nothrow) epdlb_epd3();
+  if (!c) return fail(EPDLB_ENOMEM, "host allocation failed");
+  c->device = device;
+  c->nx = nx;
+  c->ny = ny;
+  c->nz = nz;
+  c->n = long(nx) * ny * nz;
+  c->N = n_contour;
+  c->f_A = f_A;
+  c->phi_P = phi_P;
+  c->R_G = R_G;
+  c->dx = dx;
+  c->precision = precision;
+  // contour tables: A-content of each segment and trapezoid node weights over the A and B parts
+  const int N = n_contour;
+  const double ds = 1.0 / N;
+  c->seg.resize(N);
+  for (int j = 0; j < N; ++j) c->seg[j] = std::min(1.0, std::max(0.0, f_A * N - j));
+  std::vector<double> nodes(2 * size_t(N + 1), 0.0);
+  for (int j = 0; j <= N; ++j) {
+    if (j >= 1) {
+      nodes[j] += 0.5 * ds * c->seg[j - 1];
+      nodes[N + 1 + j] += 0.5 * ds * (1.0 - c->seg[j - 1]);
+    }
+    if (j <= N - 1) {
+      nodes[j] += 0.5 * ds * c->seg[j];
+      nodes[N + 1 + j] += 0.5 * ds * (1.0 - c->seg[j]);
+    }
+  }
+  const size_t plane = align256(size_t(c->n) * c->es());
+  const size_t cbytes = align256(size_t(c->n) * 2 * c->es());
+  const size_t total = 3 * plane + 3 * plane + 2 * size_t(N + 1) * plane + cbytes +
+                       align256(epd3::kRedBlocks * sizeof(double)) + align256(16 * sizeof(double)) +
+                       align256(nodes.size() * sizeof(double));
+  if (hipMalloc(&c->mem, total) != hipSuccess) {
+    delete c;
+    return fail(EPDLB_ENOMEM, "hipMalloc of the propagator planes failed");
+  }
+  unsigned char* b = static_cast<unsigned char*>(c->mem);
+  c->w = b;
+  b += 3 * plane;
+  c->phi = b;
+  b += 3 * plane;
+  c->q = b;
+  b += size_t(N + 1) * plane;
+  c->qb = b;
+  b += size_t(N + 1) * plane;
+  c->C = b;
+  b += cbytes;
+  c->part = reinterpret_cast<double*>(b);
+  b += align256(epd3::kRedBlocks * sizeof(double));
+  c->sums = reinterpret_cast<double*>(b);
+  b += align256(16 * sizeof(double));
+  c->nodes = reinterpret_cast<double*>(b);
+  if (stream) {
+    c->stream = reinterpret_cast<hipStream_t>(stream);
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      epdlb_epd3_destroy(c);
+      return fail(EPDLB_EHIP, "hipStreamCreate failed");
+    }
+    c->own_stream = true;
+  }
+  if (hipMemcpyAsync(c->nodes, nodes.data(), nodes.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    epdlb_epd3_destroy(c);
+    return fail(EPDLB_EHIP, "uploading the contour weights failed");
+  }
+  *out = c;
+  return EPDLB_OK;
+}
+
+int epdlb_epd3_densities(epdlb_epd3* c, const double* omega, double* phi, double* Q_P, double* Q_S) {
+  if (!c || !omega || !phi) return fail(EPDLB_EINVAL, "NULL argument");
+  const size_t n = size_t(c->n);
+  if (!all_finite(omega, 3 * n)) return fail(EPDLB_EINVAL, "non-finite potential");
+  HIPCHK(hipSetDevice(c->device));
+  if (c->precision) {
+    std::vector<float> h(3 * n);
+    for (size_t i = 0; i < 3 * n; ++i) h[i] = float(omega[i]);
+    HIPCHK(hipMemcpyAsync(c->w, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    CHK(p3_densities<float>(c));
+    HIPCHK(hipMemcpyAsync(h.data(), c->phi, h.size() * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < 3 * n; ++i) phi[i] = h[i];
+  } else {
+    HIPCHK(hipMemcpyAsync(c->w, omega, 3 * n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    CHK(p3_densities<double>(c));
+    HIPCHK(hipMemcpyAsync(phi, c->phi, 3 * n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  double s[16];
+  HIPCHK(hipMemcpyAsync(s, c->sums, sizeof(s), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const double dV = c->dx * c->dx * c->dx;
+  if (Q_P) *Q_P = dV * s[6];
+  if (Q_S) *Q_S = dV * s[8];
+  if (!std::isfinite(s[6]) || !std::isfinite(s[8]) || !(s[6] > 0.0))
+    return fail(EPDLB_ENONFINITE, "a partition function is not finite and positive");
+  return EPDLB_OK;
+}
+
+int epdlb_epd3_time(epdlb_epd3* c, int32_t reps, double* ms) {
+  if (!c || !ms) return fail(EPDLB_EINVAL, "NULL argument");
+  if (reps < 1 || reps > 1000) return fail(EPDLB_EINVAL, "reps must lie in [1, 1000]");
+  HIPCHK(hipSetDevice(c->device));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(EPDLB_EHIP, "hipEventCreate failed");
+  }
+  int r = hipEventRecord(e0, c->stream) == hipSuccess ? EPDLB_OK : EPDLB_EHIP;
+  for (int k = 0; k < reps && r == EPDLB_OK; ++k) r = c->precision ? p3_densities<float>(c) : p3_densities<double>(c);
+  float t = 0.f;
+  if (r == EPDLB_OK && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+    r = fail(EPDLB_EHIP, "timing events failed");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  CHK(r);
+  *ms = double(t) / reps;
+  return EPDLB_OK;
+}
+
+void epdlb_epd3_destroy(epdlb_epd3* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->mem) (void)hipFree(c->mem);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
