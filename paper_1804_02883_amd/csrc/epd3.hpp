@@ -67,22 +67,25 @@ struct LineArgs {
   long g;        // base(l) = (l / g) * gs + (l % g) * gi
   long gs, gi;
   int mode;      // -1 forward, +1 inverse, 2 forward, heat multiplier, inverse
+  int lb;        // lines per block; > 0: lines interleaved across lanes (strided passes)
   int nx, ny, nz;
   double heat;   // R_G^2 ds (2 pi / dx)^2: |k|^2 R_G^2 ds = heat (mx^2/nx^2 + my^2/ny^2 + mz^2/nz^2)
 };
 
 // Radix-2 Stockham pass over the lines held in LDS: src -> dst; dir -1 or +1.
+// tw[m] = (cos, sin)(pi m / (L/2)), m < L/2: the stage of sub-length Ns takes
+// the angle dir pi k / Ns from entry k L / (2 Ns).
 template <typename T>
-__device__ __forceinline__ void stockham(Cx<T>* buf0, Cx<T>* buf1, int L, int t, int TL, bool active, int dir,
-                                         Cx<T>** out) {
+__device__ __forceinline__ void stockham(Cx<T>* buf0, Cx<T>* buf1, const Cx<T>* tw, int L, int t, int TL,
+                                         bool active, int dir, Cx<T>** out) {
   Cx<T>* src = buf0;
   Cx<T>* dst = buf1;
   for (int Ns = 1; Ns < L; Ns *= 2) {
     if (active) {
       for (int j = t; j < L / 2; j += TL) {
         const int k = j % Ns;
-        T s, c;
-        sin_cos_pi(T(dir) * T(k) / T(Ns), &s, &c);
+        const Cx<T> w = tw[k * (L / (2 * Ns))];
+        const T c = w.re, s = dir > 0 ? w.im : -w.im;
         const Cx<T> u = src[j];
         const Cx<T> v0 = src[j + L / 2];
         Cx<T> v;
@@ -103,42 +106,57 @@ __device__ __forceinline__ void stockham(Cx<T>* buf0, Cx<T>* buf1, int L, int t,
   *out = src;
 }
 
-// Transform every line of C in place.  Block: kThreads threads, TL = max(L/2, 1)
-// per line, kThreads / TL lines; dynamic LDS 2 * lines * L complex values.
+// Transform every line of C in place.  Contiguous lines (A.lb == 0): TL =
+// max(L/2, 1) consecutive threads per line, kThreads / TL lines per block.
+// Strided lines (A.lb > 0): A.lb lines per block, interleaved across lanes
+// (lane % lb picks the line), so that the lanes of one load instruction read
+// neighbouring lines' elements: consecutive addresses.  Dynamic LDS
+// lines * (2 L + 2) complex values (the 2 pad the lines across banks), then
+// the L/2 twiddles.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_p3_fft(Cx<T>* __restrict__ C, LineArgs A) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int L = A.L;
-  const int TL = L > 1 ? L / 2 : 1;
-  const int lines = kThreads / TL;
-  const int sub = threadIdx.x / TL, t = threadIdx.x % TL;
+  const int lines = A.lb > 0 ? A.lb : kThreads / (L > 1 ? L / 2 : 1);
+  const int TL = kThreads / lines;
+  const int sub = A.lb > 0 ? int(threadIdx.x) % lines : int(threadIdx.x) / TL;
+  const int t = A.lb > 0 ? int(threadIdx.x) / lines : int(threadIdx.x) % TL;
   const long l = long(blockIdx.x) * lines + sub;
   const bool active = l < A.count;
   Cx<T>* base_lds = reinterpret_cast<Cx<T>*>(lds_raw);
-  Cx<T>* b0 = base_lds + long(sub) * 2 * L;
+  Cx<T>* b0 = base_lds + long(sub) * (2 * L + 2);
   Cx<T>* b1 = b0 + L;
+  Cx<T>* tw = base_lds + long(lines) * (2 * L + 2);
+  for (int m = threadIdx.x; m < L / 2; m += kThreads) {
+    T sv, cv;
+    sin_cos_pi(T(m) / T(L / 2), &sv, &cv);
+    tw[m].re = cv;
+    tw[m].im = sv;
+  }
   const long base = active ? (l / A.g) * A.gs + (l % A.g) * A.gi : 0;
   if (active)
     for (int e = t; e < L; e += TL) b0[e] = C[base + e * A.st];
   __syncthreads();
   Cx<T>* res;
-  stockham(b0, b1, L, t, TL, active, A.mode == 1 ? 1 : -1, &res);
+  stockham(b0, b1, tw, L, t, TL, active, A.mode == 1 ? 1 : -1, &res);
   if (A.mode == 2) {
     // heat multiplier at (mx, my, mz); this pass runs along z
     if (active) {
       const int x = int(base % A.nx), y = int(base / A.nx);
       const int mx = x < (A.nx + 1) / 2 ? x : x - A.nx, my = y < (A.ny + 1) / 2 ? y : y - A.ny;
       const double kxy = double(mx) * mx / (double(A.nx) * A.nx) + double(my) * my / (double(A.ny) * A.ny);
+      const T fxy = T(exp(-A.heat * kxy));  // the factor separates: exp(-h kxy) exp(-h kz)
+      const T hz = T(A.heat / (double(L) * L));
       for (int e = t; e < L; e += TL) {
         const int mz = e < (L + 1) / 2 ? e : e - L;
-        const T f = T(exp(-A.heat * (kxy + double(mz) * mz / (double(L) * L))));
+        const T f = fxy * exp(-hz * T(mz * mz));
         res[e].re *= f;
         res[e].im *= f;
       }
     }
     __syncthreads();
     Cx<T>* other = res == b0 ? b1 : b0;
-    stockham(res, other, L, t, TL, active, 1, &res);
+    stockham(res, other, tw, L, t, TL, active, 1, &res);
   }
   if (active)
     for (int e = t; e < L; e += TL) C[base + e * A.st] = res[e];

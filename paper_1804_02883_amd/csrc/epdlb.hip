@@ -3142,10 +3142,19 @@ template <typename T> int p3_fft(epdlb_epd3* c, int axis, int mode) {
     A.L = c->nz; A.st = long(c->nx) * c->ny; A.count = long(c->nx) * c->ny; A.g = 1; A.gs = 1; A.gi = 0;
   }
   if (A.L == 1 && mode != 2) return EPDLB_OK;  // a transform of length 1 is the identity
-  const int TL = A.L > 1 ? A.L / 2 : 1;
-  const long lines = epd3::kThreads / TL;
-  const size_t lds = size_t(2) * lines * A.L * sizeof(epd3::Cx<T>);
+  // strided lines (y, z): up to 16 neighbouring lines per block, interleaved
+  // across lanes, with the LDS held to 96 KB; contiguous lines (x): half a
+  // line's length of threads per line
+  A.lb = 0;
+  if (axis > 0) {
+    long lb = 16;
+    while (lb > 1 && (size_t(lb) * (2 * A.L + 2) + A.L / 2) * sizeof(epd3::Cx<T>) > 98304) lb /= 2;
+    A.lb = int(lb);
+  }
+  const long lines = A.lb > 0 ? A.lb : epd3::kThreads / (A.L > 1 ? A.L / 2 : 1);
+  const size_t lds = (size_t(lines) * (2 * A.L + 2) + A.L / 2) * sizeof(epd3::Cx<T>);
   const long blocks = (A.count + lines - 1) / lines;
+  HIPCHK(prep_lds(epd3::k_p3_fft<T>, lds));
   launch_k((epd3::k_p3_fft<T>), dim3(unsigned(blocks)), dim3(epd3::kThreads), lds, c->stream,
            static_cast<epd3::Cx<T>*>(c->C), A);
   HIPCHK(hipGetLastError());
