@@ -3,9 +3,9 @@
 // heat kernel exp(-R_G^2 |k|^2 ds) of three dimensions).
 //
 // One contour step q -> E K (E q), E = exp(-(w_j - c_j)/2), runs as
-//   k_p3_pre  (C = E q, complex) -> FFT along x -> FFT along y ->
-//   FFT along z, heat multiplier, inverse FFT along z -> inverse FFT along y
-//   -> inverse FFT along x -> k_p3_post (q' = E Re C / n).
+//   FFT along x of E q (the factor applied as the lines load) -> FFT along y
+//   -> FFT along z, heat multiplier, inverse FFT along z -> inverse FFT along
+//   y -> inverse FFT along x, storing q' = E Re / n.
 // The FFT kernel transforms whole lines in LDS with the radix-2 Stockham
 // formulation (natural order in and out, a ping-pong pair of buffers per
 // line): every line is read and written once per pass.  Lines along x are
@@ -37,29 +37,6 @@ __device__ __forceinline__ T half_step_factor(T wa, T wb, T a, const double* sum
   return exp(-(a * (wa - cA) + (T(1) - a) * (wb - cB)) * T(0.5));
 }
 
-// C = E q (q == nullptr: q = 1).
-template <typename T>
-__global__ void __launch_bounds__(kThreads) k_p3_pre(const T* __restrict__ wA, const T* __restrict__ wB,
-                                                     const double* __restrict__ sums, double inv_n, T a,
-                                                     const T* __restrict__ q, Cx<T>* __restrict__ C, long n) {
-  for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += long(gridDim.x) * blockDim.x) {
-    const T e = half_step_factor(wA[i], wB[i], a, sums, inv_n);
-    Cx<T> v;
-    v.re = q ? e * q[i] : e;
-    v.im = T(0);
-    C[i] = v;
-  }
-}
-
-// q' = E Re(C) / n (the inverse transforms are unnormalised).
-template <typename T>
-__global__ void __launch_bounds__(kThreads) k_p3_post(const T* __restrict__ wA, const T* __restrict__ wB,
-                                                      const double* __restrict__ sums, double inv_n, T a,
-                                                      const Cx<T>* __restrict__ C, T* __restrict__ qn, long n) {
-  for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += long(gridDim.x) * blockDim.x)
-    qn[i] = half_step_factor(wA[i], wB[i], a, sums, inv_n) * C[i].re * T(inv_n);
-}
-
 struct LineArgs {
   int L;         // line length (power of two, <= kMaxLen)
   long st;       // element stride along the line
@@ -70,6 +47,16 @@ struct LineArgs {
   int lb;        // lines per block; > 0: lines interleaved across lanes (strided passes)
   int nx, ny, nz;
   double heat;   // R_G^2 ds (2 pi / dx)^2: |k|^2 R_G^2 ds = heat (mx^2/nx^2 + my^2/ny^2 + mz^2/nz^2)
+  // x passes only: fuse = 1 loads E q (q == nullptr: E) instead of C; fuse = 2
+  // stores q' = E Re(.) / n instead of C (E from wA, wB, a and the field sums)
+  int fuse;
+  const void* wA;
+  const void* wB;
+  const void* q;
+  void* qn;
+  const double* sums;
+  double inv_n;
+  double a;
 };
 
 // Radix-2 Stockham pass over the lines held in LDS: src -> dst; dir -1 or +1.
@@ -134,8 +121,21 @@ __global__ void __launch_bounds__(kThreads) k_p3_fft(Cx<T>* __restrict__ C, Line
     tw[m].im = sv;
   }
   const long base = active ? (l / A.g) * A.gs + (l % A.g) * A.gi : 0;
-  if (active)
-    for (int e = t; e < L; e += TL) b0[e] = C[base + e * A.st];
+  const T* wA = static_cast<const T*>(A.wA);
+  const T* wB = static_cast<const T*>(A.wB);
+  if (active) {
+    if (A.fuse == 1) {
+      const T* q = static_cast<const T*>(A.q);
+      for (int e = t; e < L; e += TL) {
+        const long i = base + e * A.st;
+        const T f = half_step_factor(wA[i], wB[i], T(A.a), A.sums, A.inv_n);
+        b0[e].re = q ? f * q[i] : f;
+        b0[e].im = T(0);
+      }
+    } else {
+      for (int e = t; e < L; e += TL) b0[e] = C[base + e * A.st];
+    }
+  }
   __syncthreads();
   Cx<T>* res;
   stockham(b0, b1, tw, L, t, TL, active, A.mode == 1 ? 1 : -1, &res);
@@ -158,8 +158,17 @@ __global__ void __launch_bounds__(kThreads) k_p3_fft(Cx<T>* __restrict__ C, Line
     Cx<T>* other = res == b0 ? b1 : b0;
     stockham(res, other, tw, L, t, TL, active, 1, &res);
   }
-  if (active)
-    for (int e = t; e < L; e += TL) C[base + e * A.st] = res[e];
+  if (active) {
+    if (A.fuse == 2) {
+      T* qn = static_cast<T*>(A.qn);
+      for (int e = t; e < L; e += TL) {
+        const long i = base + e * A.st;
+        qn[i] = half_step_factor(wA[i], wB[i], T(A.a), A.sums, A.inv_n) * res[e].re * T(A.inv_n);
+      }
+    } else {
+      for (int e = t; e < L; e += TL) C[base + e * A.st] = res[e];
+    }
+  }
 }
 
 // part[block] = sum over the block's grid-stride elements of a (exp_shift:

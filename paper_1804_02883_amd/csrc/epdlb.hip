@@ -3127,8 +3127,18 @@ namespace {
 
 bool pow2_upto(int v, int m) { return v >= 1 && v <= m && (v & (v - 1)) == 0; }
 
-template <typename T> int p3_fft(epdlb_epd3* c, int axis, int mode) {
+template <typename T>
+int p3_fft(epdlb_epd3* c, int axis, int mode, int fuse = 0, const T* q = nullptr, T* qn = nullptr, T a = T(0)) {
   epd3::LineArgs A;
+  const long n = c->n;
+  A.fuse = fuse;
+  A.wA = c->w;
+  A.wB = static_cast<const T*>(c->w) + n;
+  A.q = q;
+  A.qn = qn;
+  A.sums = c->sums;
+  A.inv_n = 1.0 / double(n);
+  A.a = double(a);
   A.nx = c->nx;
   A.ny = c->ny;
   A.nz = c->nz;
@@ -3141,7 +3151,7 @@ template <typename T> int p3_fft(epdlb_epd3* c, int axis, int mode) {
   } else {
     A.L = c->nz; A.st = long(c->nx) * c->ny; A.count = long(c->nx) * c->ny; A.g = 1; A.gs = 1; A.gi = 0;
   }
-  if (A.L == 1 && mode != 2) return EPDLB_OK;  // a transform of length 1 is the identity
+  if (A.L == 1 && mode != 2 && fuse == 0) return EPDLB_OK;  // a transform of length 1 is the identity
   // strided lines (y, z): up to 16 neighbouring lines per block, interleaved
   // across lanes, with the LDS held to 96 KB; contiguous lines (x): half a
   // line's length of threads per line
@@ -3187,19 +3197,12 @@ template <typename T> int p3_densities(epdlb_epd3* c) {
     for (int j = 0; j < c->N; ++j) {
       const int seg = chain ? c->N - 1 - j : j;
       const T a = T(c->seg[seg]);
-      launch_k((epd3::k_p3_pre<T>), eg, dim3(epd3::kThreads), 0, c->stream, wA, wB,
-               static_cast<const double*>(c->sums), inv_n, a, static_cast<const T*>(q + long(j) * n),
-               static_cast<epd3::Cx<T>*>(c->C), n);
-      HIPCHK(hipGetLastError());
-      CHK(p3_fft<T>(c, 0, -1));
+      // the half-step factors ride on the x passes: E q as the lines load, E Re / n as they store
+      CHK(p3_fft<T>(c, 0, -1, 1, static_cast<const T*>(q + long(j) * n), nullptr, a));
       CHK(p3_fft<T>(c, 1, -1));
       CHK(p3_fft<T>(c, 2, 2));
       CHK(p3_fft<T>(c, 1, 1));
-      CHK(p3_fft<T>(c, 0, 1));
-      launch_k((epd3::k_p3_post<T>), eg, dim3(epd3::kThreads), 0, c->stream, wA, wB,
-               static_cast<const double*>(c->sums), inv_n, a, static_cast<const epd3::Cx<T>*>(c->C),
-               q + long(j + 1) * n, n);
-      HIPCHK(hipGetLastError());
+      CHK(p3_fft<T>(c, 0, 1, 2, nullptr, q + long(j + 1) * n, a));
     }
   }
   CHK(p3_sum<T>(c, static_cast<const T*>(c->q) + long(c->N) * n, 0, nullptr, c->sums + 6));

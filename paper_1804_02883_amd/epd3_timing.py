@@ -4,8 +4,8 @@
 
 Box n^3, FP32 planes (FP64 sums), f_A = 0.3, phibar_P = 0.15, seeded
 potentials 0.2 xi.  An evaluation runs both chains over N contour steps, each
-step 7 launches (the half-step factor, 5 FFT passes, the second factor),
-plus the gauge and partition-function sums and the density kernel.  Prints
+step 5 FFT launches (the half-step factors ride on the two x passes), plus
+the gauge and partition-function sums and the density kernel.  Prints
 one JSON line: ms per evaluation (events on the stream around `reps`
 evaluations) and site contour steps per second (n^3 sites x 2N steps).
 """
@@ -27,7 +27,7 @@ def measure(n=128, N=32, reps=5, precision=1):
     d.close()
     sites = n ** 3
     return dict(workload=f"densities3d_{n}^3_N{N}", precision="f32" if precision else "f64", ms_per_eval=ms,
-                site_contour_steps_per_s=sites * 2 * N / (ms * 1e-3), launches_per_eval=2 * N * 7 + 2 + 5 * 2 + 1)
+                site_contour_steps_per_s=sites * 2 * N / (ms * 1e-3), launches_per_eval=2 * N * 5 + 2 + 5 * 2 + 1)
 
 
 def main(argv=None):
