@@ -59,15 +59,19 @@ struct LineArgs {
   double a;
 };
 
-// Radix-2 Stockham pass over the lines held in LDS: src -> dst; dir -1 or +1.
-// tw[m] = (cos, sin)(pi m / (L/2)), m < L/2: the stage of sub-length Ns takes
-// the angle dir pi k / Ns from entry k L / (2 Ns).
+// Stockham transform of the lines held in LDS (natural order in and out):
+// one radix-2 stage when log2 L is odd, then radix-4 stages; src and dst
+// alternate, *out receives the buffer that holds the result.  dir -1 or +1.
+// tw[m] = (cos, sin)(pi m / (L/2)), m < L: the stage of sub-length Ns takes
+// the angle dir pi r k / (2 Ns) (radix 4, r < 4) from entry r k L / (4 Ns),
+// and dir pi k / Ns (radix 2) from entry k L / (2 Ns).
 template <typename T>
 __device__ __forceinline__ void stockham(Cx<T>* buf0, Cx<T>* buf1, const Cx<T>* tw, int L, int t, int TL,
                                          bool active, int dir, Cx<T>** out) {
   Cx<T>* src = buf0;
   Cx<T>* dst = buf1;
-  for (int Ns = 1; Ns < L; Ns *= 2) {
+  int Ns = 1;
+  if (L > 1 && (__builtin_ctz(unsigned(L)) & 1)) {
     if (active) {
       for (int j = t; j < L / 2; j += TL) {
         const int k = j % Ns;
@@ -75,14 +79,47 @@ __device__ __forceinline__ void stockham(Cx<T>* buf0, Cx<T>* buf1, const Cx<T>* 
         const T c = w.re, s = dir > 0 ? w.im : -w.im;
         const Cx<T> u = src[j];
         const Cx<T> v0 = src[j + L / 2];
-        Cx<T> v;
-        v.re = v0.re * c - v0.im * s;
-        v.im = v0.re * s + v0.im * c;
+        const T vr = v0.re * c - v0.im * s, vi = v0.re * s + v0.im * c;
         const int d = (j / Ns) * Ns * 2 + k;
-        dst[d].re = u.re + v.re;
-        dst[d].im = u.im + v.im;
-        dst[d + Ns].re = u.re - v.re;
-        dst[d + Ns].im = u.im - v.im;
+        dst[d].re = u.re + vr;
+        dst[d].im = u.im + vi;
+        dst[d + Ns].re = u.re - vr;
+        dst[d + Ns].im = u.im - vi;
+      }
+    }
+    __syncthreads();
+    Cx<T>* tmp = src;
+    src = dst;
+    dst = tmp;
+    Ns = 2;
+  }
+  for (; Ns < L; Ns *= 4) {
+    if (active) {
+      for (int j = t; j < L / 4; j += TL) {
+        const int k = j % Ns;
+        const int step = k * (L / (4 * Ns));
+        T vr[4], vi[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const Cx<T> a = src[j + r * (L / 4)];
+          const Cx<T> w = tw[r * step];
+          const T c = w.re, s = dir > 0 ? w.im : -w.im;
+          vr[r] = a.re * c - a.im * s;
+          vi[r] = a.re * s + a.im * c;
+        }
+        // 4-point DFT with i^dir: (dir i) v = (-dir vi, dir vr)
+        const T dr = T(dir);
+        const T s02r = vr[0] + vr[2], s02i = vi[0] + vi[2], d02r = vr[0] - vr[2], d02i = vi[0] - vi[2];
+        const T s13r = vr[1] + vr[3], s13i = vi[1] + vi[3], d13r = vr[1] - vr[3], d13i = vi[1] - vi[3];
+        const int d = (j / Ns) * Ns * 4 + k;
+        dst[d].re = s02r + s13r;
+        dst[d].im = s02i + s13i;
+        dst[d + Ns].re = d02r - dr * d13i;
+        dst[d + Ns].im = d02i + dr * d13r;
+        dst[d + 2 * Ns].re = s02r - s13r;
+        dst[d + 2 * Ns].im = s02i - s13i;
+        dst[d + 3 * Ns].re = d02r + dr * d13i;
+        dst[d + 3 * Ns].im = d02i - dr * d13r;
       }
     }
     __syncthreads();
@@ -99,7 +136,7 @@ __device__ __forceinline__ void stockham(Cx<T>* buf0, Cx<T>* buf1, const Cx<T>* 
 // (lane % lb picks the line), so that the lanes of one load instruction read
 // neighbouring lines' elements: consecutive addresses.  Dynamic LDS
 // lines * (2 L + 2) complex values (the 2 pad the lines across banks), then
-// the L/2 twiddles.
+// the L twiddles.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_p3_fft(Cx<T>* __restrict__ C, LineArgs A) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -114,9 +151,9 @@ __global__ void __launch_bounds__(kThreads) k_p3_fft(Cx<T>* __restrict__ C, Line
   Cx<T>* b0 = base_lds + long(sub) * (2 * L + 2);
   Cx<T>* b1 = b0 + L;
   Cx<T>* tw = base_lds + long(lines) * (2 * L + 2);
-  for (int m = threadIdx.x; m < L / 2; m += kThreads) {
+  for (int m = threadIdx.x; m < L; m += kThreads) {
     T sv, cv;
-    sin_cos_pi(T(m) / T(L / 2), &sv, &cv);
+    sin_cos_pi(L > 1 ? T(2 * m) / T(L) : T(0), &sv, &cv);
     tw[m].re = cv;
     tw[m].im = sv;
   }

@@ -3158,11 +3158,11 @@ int p3_fft(epdlb_epd3* c, int axis, int mode, int fuse = 0, const T* q = nullptr
   A.lb = 0;
   if (axis > 0) {
     long lb = 16;
-    while (lb > 1 && (size_t(lb) * (2 * A.L + 2) + A.L / 2) * sizeof(epd3::Cx<T>) > 98304) lb /= 2;
+    while (lb > 1 && (size_t(lb) * (2 * A.L + 2) + A.L) * sizeof(epd3::Cx<T>) > 98304) lb /= 2;
     A.lb = int(lb);
   }
   const long lines = A.lb > 0 ? A.lb : epd3::kThreads / (A.L > 1 ? A.L / 2 : 1);
-  const size_t lds = (size_t(lines) * (2 * A.L + 2) + A.L / 2) * sizeof(epd3::Cx<T>);
+  const size_t lds = (size_t(lines) * (2 * A.L + 2) + A.L) * sizeof(epd3::Cx<T>);
   const long blocks = (A.count + lines - 1) / lines;
   HIPCHK(prep_lds(epd3::k_p3_fft<T>, lds));
   launch_k((epd3::k_p3_fft<T>), dim3(unsigned(blocks)), dim3(epd3::kThreads), lds, c->stream,
