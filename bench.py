@@ -14,7 +14,9 @@ at an exact step that ended surrogate steps.  `roofline` is the MFMA
 roofline of the 64 -> 64 convolution.  `plain_full_scale` adds the plain
 path on 1024 x 512, N = 64 with its HBM roofline, and `fluid3d` the
 three-dimensional D3Q19 fluid on a 256^3 box (FP32) with the HBM roofline of
-its step kernel (paper_1804_02883_amd/fluid3d_timing.py).
+its step kernel (paper_1804_02883_amd/fluid3d_timing.py), and `densities3d`
+the propagators and densities on a 256^3 grid (FP32, N = 32) with the HBM
+roofline of its FFT kernel (paper_1804_02883_amd/epd3_timing.py).
 
 `--workload cfg3` (or cfg2, cfg5, cfg4) reports a plain line instead.
 
@@ -309,6 +311,32 @@ def fluid3d_line(cpu=True):
     return r
 
 
+def densities3d_cpu_baseline(seconds=3.0, n=32, N=16):
+    """The FP64 NumPy oracle's density evaluation on an n^3 grid (numpy.fft)."""
+    import numpy as np
+    from oracle import epd3d_oracle as E3
+    from seeded_inputs import preset
+    p = preset("cfg1", n_contour=N, f_A=0.3, phi_P=0.15)
+    w = 0.2 * np.random.default_rng(5).standard_normal((3, n, n, n))
+    evals, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        E3.densities3(w, p)
+        evals += 1
+    dt = time.perf_counter() - t0
+    return dict(value=evals * n ** 3 * 2 * N / dt, unit="site contour steps/s", cores=1, kind="oracle",
+                sample=f"{evals} density evaluations of a {n}^3 grid, N = {N}, FP64 NumPy oracle, {dt:.1f} s")
+
+
+def densities3d_line(cpu=True):
+    """Propagators and densities on a 256^3 grid (FP32, N = 32), with the HBM
+    roofline of the FFT kernel."""
+    from paper_1804_02883_amd import epd3_timing
+    r = epd3_timing.measure(256, 32, 3, 1)
+    if cpu:
+        r["cpu_baseline"] = densities3d_cpu_baseline()
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -348,6 +376,7 @@ def main():
                                            ms_per_step=pl["ms_per_step"], roofline=pl["roofline"])
     if not args.no_secondary:
         out["fluid3d"] = fluid3d_line(cpu=not args.no_cpu_baseline)
+        out["densities3d"] = densities3d_line(cpu=not args.no_cpu_baseline)
     else:
         out = plain_line(args, args.workload)
         if not args.no_secondary and args.workload != "cfg4":

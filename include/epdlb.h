@@ -520,6 +520,11 @@ int epdlb_epd3_densities(epdlb_epd3* c, const double* omega, double* phi, double
 /* reps evaluations of the potentials last passed in, timed with events on the
  * stream; ms receives the mean GPU time per evaluation.  Synchronous. */
 int epdlb_epd3_time(epdlb_epd3* c, int32_t reps, double* ms);
+/* One evaluation of the potentials last passed in with every FFT launch
+ * timed on the GPU from its own start to its end: *fft_ms receives the sum of
+ * their durations and *fft_launches their number (10 N at sides > 1).
+ * Synchronous. */
+int epdlb_epd3_profile(epdlb_epd3* c, double* fft_ms, int32_t* fft_launches);
 void epdlb_epd3_destroy(epdlb_epd3* c);
 
 /* Message for the last failing call on this thread ("" if none). */

@@ -210,6 +210,7 @@ SIGNATURES = {
                                          ctypes.c_int32, ctypes.c_int, _vp, _P(_vp)]),
     "epdlb_epd3_densities": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp]),
     "epdlb_epd3_time": (ctypes.c_int, [_vp, ctypes.c_int32, _dp]),
+    "epdlb_epd3_profile": (ctypes.c_int, [_vp, _dp, _P(ctypes.c_int32)]),
     "epdlb_epd3_destroy": (None, [_vp]),
     "epdlb_last_error": (ctypes.c_char_p, []),
 }
@@ -1066,3 +1067,10 @@ class Densities3D:
         ms = ctypes.c_double()
         _check(load_library().epdlb_epd3_time(self.ctx, reps, ctypes.byref(ms)), "epdlb_epd3_time")
         return ms.value
+
+    def profile(self):
+        """(summed kernel ms of the FFT launches of one evaluation, their number)."""
+        ms = ctypes.c_double()
+        k = ctypes.c_int32()
+        _check(load_library().epdlb_epd3_profile(self.ctx, ctypes.byref(ms), ctypes.byref(k)), "epdlb_epd3_profile")
+        return ms.value, k.value

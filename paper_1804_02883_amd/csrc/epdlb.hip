@@ -3118,6 +3118,9 @@ struct epdlb_epd3 {
   double* sums = nullptr;  // 16
   double* nodes = nullptr; // wA_j, wB_j: 2 (N + 1)
   std::vector<double> seg;  // A-content of each contour segment
+  std::vector<hipEvent_t> ev;  // start/stop pairs of the timed FFT launches (epdlb_epd3_profile)
+  size_t ev_used = 0;          // pairs armed in the current evaluation; 0 when not profiling
+  bool profiling = false;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   size_t es() const { return precision ? sizeof(float) : sizeof(double); }
@@ -3165,6 +3168,11 @@ int p3_fft(epdlb_epd3* c, int axis, int mode, int fuse = 0, const T* q = nullptr
   const size_t lds = (size_t(lines) * (2 * A.L + 2) + A.L) * sizeof(epd3::Cx<T>);
   const long blocks = (A.count + lines - 1) / lines;
   HIPCHK(prep_lds(epd3::k_p3_fft<T>, lds));
+  if (c->profiling && 2 * c->ev_used + 1 < c->ev.size()) {
+    tl_ev_start = c->ev[2 * c->ev_used];
+    tl_ev_stop = c->ev[2 * c->ev_used + 1];
+    ++c->ev_used;
+  }
   launch_k((epd3::k_p3_fft<T>), dim3(unsigned(blocks)), dim3(epd3::kThreads), lds, c->stream,
            static_cast<epd3::Cx<T>*>(c->C), A);
   HIPCHK(hipGetLastError());
@@ -3371,9 +3379,37 @@ int epdlb_epd3_time(epdlb_epd3* c, int32_t reps, double* ms) {
   return EPDLB_OK;
 }
 
+int epdlb_epd3_profile(epdlb_epd3* c, double* fft_ms, int32_t* fft_launches) {
+  if (!c || !fft_ms || !fft_launches) return fail(EPDLB_EINVAL, "NULL argument");
+  HIPCHK(hipSetDevice(c->device));
+  const size_t need = 2 * size_t(10 * c->N + 2);
+  while (c->ev.size() < need) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    c->ev.push_back(e);
+  }
+  c->profiling = true;
+  c->ev_used = 0;
+  const int r = c->precision ? p3_densities<float>(c) : p3_densities<double>(c);
+  c->profiling = false;
+  tl_ev_start = tl_ev_stop = nullptr;
+  CHK(r);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double total = 0.0;
+  for (size_t k = 0; k < c->ev_used; ++k) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, c->ev[2 * k], c->ev[2 * k + 1]));
+    total += t;
+  }
+  *fft_ms = total;
+  *fft_launches = int32_t(c->ev_used);
+  return EPDLB_OK;
+}
+
 void epdlb_epd3_destroy(epdlb_epd3* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   if (c->mem) (void)hipFree(c->mem);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;

@@ -7,7 +7,10 @@ potentials 0.2 xi.  An evaluation runs both chains over N contour steps, each
 step 5 FFT launches (the half-step factors ride on the two x passes), plus
 the gauge and partition-function sums and the density kernel.  Prints
 one JSON line: ms per evaluation (events on the stream around `reps`
-evaluations) and site contour steps per second (n^3 sites x 2N steps).
+evaluations), `value` in site contour steps per second (n^3 sites x 2N
+steps), and the HBM roofline of the FFT kernel: the mean algorithmic bytes
+of its launches over their mean duration, each launch timed from its own
+start to its end in one further evaluation.
 """
 import argparse
 import json
@@ -24,10 +27,22 @@ def measure(n=128, N=32, reps=5, precision=1):
     w = 0.2 * np.random.default_rng(5).standard_normal((3, n, n, n))
     d.densities(w)  # uploads the potentials and warms up
     ms = d.time(reps)
+    fft_ms, fft_launches = d.profile()
     d.close()
     sites = n ** 3
+    es = 4 if precision else 8
+    # per FFT launch: the complex plane in and out (16 B per site in FP32); the two
+    # x passes of a contour step read or write q, wA, wB (12 B) in place of one
+    # complex plane, so a step's 5 launches move 2 * 20 + 3 * 16 B per site (FP32)
+    alg = sites * es * (2 * 5 + 3 * 4) / 5
+    avg = fft_ms / fft_launches
+    achieved = alg / (avg * 1e-3) / 1e9
     return dict(workload=f"densities3d_{n}^3_N{N}", precision="f32" if precision else "f64", ms_per_eval=ms,
-                site_contour_steps_per_s=sites * 2 * N / (ms * 1e-3), launches_per_eval=2 * N * 5 + 2 + 5 * 2 + 1)
+                value=sites * 2 * N / (ms * 1e-3), unit="site contour steps/s",
+                launches_per_eval=2 * N * 5 + 2 + 5 * 2 + 1,
+                roofline=dict(bound="hbm", kernel="p3_fft", achieved=achieved, peak=8000.0, unit="GB/s",
+                              frac=achieved / 8000.0, algorithmic_bytes_per_launch=alg, avg_launch_us=avg * 1e3,
+                              traffic=None))
 
 
 def main(argv=None):

@@ -54,3 +54,8 @@ def test_fluid3d_byte_model():
 def test_fluid3d_cpu_baseline_runs():
     r = bench.fluid3d_cpu_baseline(seconds=0.2, n=16)
     assert r["kind"] == "oracle" and r["value"] > 0 and r["cores"] == 1
+
+
+def test_densities3d_cpu_baseline_runs():
+    r = bench.densities3d_cpu_baseline(seconds=0.1, n=8, N=4)
+    assert r["kind"] == "oracle" and r["value"] > 0
