@@ -55,6 +55,9 @@ MEASURED_TRAFFIC = {
     ("cfg5q", "nn_conv"): dict(bytes_per_launch=63970359, files=_NN_FILES,
                                source_sha256="4f00c90da1997534e3811f0beb2591c36ceaec6e5898195cfffe087c312feb2d"),
     # profiles/lb3_fluid3d_256_traffic.md: the step kernel without moment stores
+    # profiles/epd3_densities_256_traffic.md: mean over the five FFT passes of a contour step
+    ("densities3d_256_N32", "p3_fft"): dict(bytes_per_launch=295385359, files=("epd3.hpp",),
+                                            source_sha256="0f8cbbb975abf58193e39b668c073a1b5acfb5f18cfb18bb1665b18b037520b1"),
     ("fluid3d_256", "lb3"): dict(bytes_per_launch=2873793431, files=("lb3.hpp",),
                                  source_sha256="e7e59f031e128b313dda272b0a26b0ab5c5fe413ad9252a506d9b009c091450e"),
 }
@@ -332,6 +335,7 @@ def densities3d_line(cpu=True):
     roofline of the FFT kernel."""
     from paper_1804_02883_amd import epd3_timing
     r = epd3_timing.measure(256, 32, 3, 1)
+    r["roofline"]["traffic"] = measured_traffic("densities3d_256_N32", "p3_fft")
     if cpu:
         r["cpu_baseline"] = densities3d_cpu_baseline()
     return r
