@@ -42,7 +42,8 @@ enum {
   EPDLB_EINVAL = -1,     /* bad argument, shape or parameter */
   EPDLB_ENOMEM = -2,     /* device allocation failed or workspace too small */
   EPDLB_EHIP = -3,       /* a HIP runtime call failed */
-  EPDLB_ENONFINITE = -4, /* a partition function or field became non-finite */
+  EPDLB_ENONFINITE = -4, /* a partition function, field mean, LB density or velocity became non-finite */
+  EPDLB_EUNSTABLE = -5,  /* the LB flow left its stable range: |u| > mach_max c_s, or a negative population */
   EPDLB_ESTATE = -6,     /* call out of order (e.g. step before seed) */
   EPDLB_ENODEV = -7      /* no usable gfx950 device */
 };
@@ -117,6 +118,15 @@ typedef struct {
    * current iterate, factor (s.z)_new / (s.z)_old.  Same solution and
    * stopping test, fewer iterations; 0 (default): the paper's plain iteration. */
   int32_t cg_precond;
+  /* Flow guard of the LB step (Sec. II: the lattice speed of sound
+   * c_s = dx/(dt sqrt 3), 1/sqrt 3 in lattice units).  Every LB launch checks
+   * each site; the next epdlb_sync (epdlb_batch_sync) returns EPDLB_EUNSTABLE
+   * once some step produced |u| > mach_max c_s or a negative post-collision
+   * population, and EPDLB_ENONFINITE once it produced a density or velocity
+   * that is not finite.  The flags stay raised until the state is replaced
+   * (seed, set_fields, set_state).  Default 0.5; 0 disables the speed test
+   * (the other two tests stay on). */
+  double mach_max;
 } epdlb_params;
 
 /* Observables of the current densities (Sec. III and IV).  Phi_P = Phi_A +
@@ -181,6 +191,19 @@ int epdlb_params_default(epdlb_params* p);
 /* Check *p without touching a GPU.  Host only. */
 int epdlb_validate(const epdlb_params* p);
 
+/* Relaxation factors of the multi-relaxation collision from the shear and
+ * bulk viscosities (Sec. II viscosity relations, with the lattice speed of
+ * sound c_s^2 = dx^2/(3 dt^2)):
+ *   eta   = (dt rho c_s^2 / 2) (1 + gamma_s)/(1 - gamma_s),
+ *   eta_B = (dt rho c_s^2 / d) (1 + gamma_b)/(1 - gamma_b),
+ * d = dim (2 for epdlb_params.lb_gamma_s/_b, 3 for epdlb_lb3_set_collision).
+ * The paper's eta = eta_B = 1 R_G^2 rho/tau at dx = R_G/3, dt = 0.002 tau
+ * gives gamma_s = gamma_b = -0.8050541516245486 in two dimensions.
+ * EINVAL for a non-positive or non-finite argument, dim other than 2 or 3,
+ * or a NULL output.  Host only. */
+int epdlb_mrt_gammas(double eta, double eta_B, double rho, double dx, double dt, int32_t dim,
+                     double* gamma_s, double* gamma_b);
+
 /* Device bytes a context for *p needs when the caller supplies the workspace.  Host only. */
 int epdlb_workspace_bytes(const epdlb_params* p, size_t* bytes);
 
@@ -235,7 +258,10 @@ int epdlb_step(epdlb_ctx* ctx, int64_t n);
 /* Queue one stage of a step (EPDLB_STAGE_*), for per-stage checks. */
 int epdlb_run_stage(epdlb_ctx* ctx, int32_t stage);
 
-/* Wait for queued work; reports non-finite partition functions. */
+/* Wait for queued work.  Returns EPDLB_ENONFINITE when a partition function,
+ * a field mean, or an LB density or velocity became non-finite, and
+ * EPDLB_EUNSTABLE when the flow guard (epdlb_params.mach_max) tripped, in
+ * any step since the state was last replaced. */
 int epdlb_sync(epdlb_ctx* ctx);
 
 /* Copy current fields to host (FP64, nx*ny each). */

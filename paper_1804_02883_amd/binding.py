@@ -3,8 +3,9 @@ plus a small `Simulation` convenience wrapper.
 
 Argument marshalling only: every step of the simulation runs in the HIP
 kernels of the library.  PyTorch supplies device memory (the context's
-workspace is a torch uint8 tensor) and the stream (torch's current stream), so
-torch's allocator and events see the library's work.  Without a GPU the host
+workspace is a torch uint8 tensor) and the stream (`work_stream`: torch's
+current stream, or a torch stream of its own when that is the legacy default
+stream), so torch's allocator and events see the library's work.  Without a GPU the host
 entry points (params, validation, workspace size, noise) still work.
 """
 import ctypes
@@ -21,6 +22,7 @@ EPDLB_EINVAL = -1
 EPDLB_ENOMEM = -2
 EPDLB_EHIP = -3
 EPDLB_ENONFINITE = -4
+EPDLB_EUNSTABLE = -5
 EPDLB_ESTATE = -6
 EPDLB_ENODEV = -7
 
@@ -56,6 +58,7 @@ class epdlb_params(ctypes.Structure):
         ("lb_gamma_s", ctypes.c_double), ("lb_gamma_b", ctypes.c_double), ("lb_gamma_g", ctypes.c_double),
         ("cg_invert", ctypes.c_int32), ("cg_max_iter", ctypes.c_int32), ("cg_tol", ctypes.c_double),
         ("cg_precond", ctypes.c_int32),
+        ("mach_max", ctypes.c_double),
     ]
 
 
@@ -125,6 +128,8 @@ _vp = ctypes.c_void_p
 SIGNATURES = {
     "epdlb_params_default": (ctypes.c_int, [_P(epdlb_params)]),
     "epdlb_validate": (ctypes.c_int, [_P(epdlb_params)]),
+    "epdlb_mrt_gammas": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_int32, _dp, _dp]),
     "epdlb_workspace_bytes": (ctypes.c_int, [_P(epdlb_params), _P(ctypes.c_size_t)]),
     "epdlb_noise_fill": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_double, ctypes.c_int32,
                                         ctypes.c_int32, _dp]),
@@ -253,6 +258,21 @@ def _f64(a, count):
     return a
 
 
+
+def work_stream(device):
+    """The stream a context queues its work on: torch's current stream of
+    `device`, or a new torch stream (default priority) when the current one is
+    the legacy default stream, whose null handle the library would read as "no
+    stream" and answer with a private stream that torch events cannot see.
+    Events that time a context's work are recorded on this stream."""
+    import torch
+    dev = torch.device("cuda", device) if isinstance(device, int) else device
+    s = torch.cuda.current_stream(dev)
+    if s.cuda_stream == 0:
+        s = torch.cuda.Stream(dev)
+    return s
+
+
 def make_params(d=None, **kw):
     """epdlb_params from the library defaults, updated by a dict and keywords."""
     p = epdlb_params()
@@ -264,15 +284,17 @@ def make_params(d=None, **kw):
     return p
 
 
+def epdlb_mrt_gammas(eta, eta_B, rho, dx, dt, dim):
+    gs, gb = ctypes.c_double(), ctypes.c_double()
+    _check(load_library().epdlb_mrt_gammas(eta, eta_B, rho, dx, dt, dim, ctypes.byref(gs), ctypes.byref(gb)),
+           "epdlb_mrt_gammas")
+    return gs.value, gb.value
+
+
 def mrt_gammas(eta, eta_B, rho=1.0, dx=1.0 / 3.0, dt=0.002, d=2):
     """(gamma_s, gamma_b) of the multi-relaxation LB from the shear and bulk
-    viscosities (Sec. II): eta = (dt rho c_s^2/2)(1 + gamma_s)/(1 - gamma_s),
-    eta_B = (dt rho c_s^2/d)(1 + gamma_b)/(1 - gamma_b), c_s^2 = dx^2/(3 dt^2).
-    Host arithmetic only."""
-    cs2 = dx * dx / (3.0 * dt * dt)
-    a = 2.0 * eta / (dt * rho * cs2)
-    b = d * eta_B / (dt * rho * cs2)
-    return (a - 1.0) / (a + 1.0), (b - 1.0) / (b + 1.0)
+    viscosities (epdlb_mrt_gammas, Sec. II viscosity relations)."""
+    return epdlb_mrt_gammas(eta, eta_B, rho, dx, dt, d)
 
 
 # ---- functions with the C ABI's names --------------------------------------------------
@@ -528,7 +550,7 @@ def epdlb_last_error():
 
 class Simulation:
     """One replica on one GPU.  Device memory comes from torch's caching
-    allocator and work is queued on torch's current stream of `device`."""
+    allocator and work is queued on `work_stream(device)`."""
 
     def __init__(self, params, device=0, use_torch=True):
         import torch
@@ -543,10 +565,13 @@ class Simulation:
         ws_ptr, ws_bytes = None, 0
         if use_torch:
             dev = torch.device("cuda", device)
-            self.stream = torch.cuda.current_stream(dev)
+            self.stream = work_stream(dev)
             stream = _vp(self.stream.cuda_stream)
             ws_bytes = epdlb_workspace_bytes(self.p)
             self._ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
+            # the workspace is used on the context's stream: the caching
+            # allocator must not hand it out again before that work is done
+            self._ws.record_stream(self.stream)
             base = self._ws.data_ptr()
             ws_ptr = _vp((base + 255) & ~255)
         self.ctx = epdlb_create(self.p, device, stream, ws_ptr, ws_bytes)
@@ -747,7 +772,7 @@ def epdlb_nn_destroy(nn):
 
 class Trainer:
     """Device dataset of (potentials -> densities) pairs and the surrogate's
-    training kernels; work is queued on torch's current stream."""
+    training kernels; work is queued on `work_stream(device)`."""
 
     def __init__(self, nx, ny, capacity, max_batch, device=0):
         import torch
@@ -756,7 +781,7 @@ class Trainer:
         self.shape = (ny, nx)
         self.n = nx * ny
         self.capacity = capacity
-        self.stream = torch.cuda.current_stream(torch.device("cuda", device))
+        self.stream = work_stream(device)
         self.nn = epdlb_nn_create(nx, ny, capacity, max_batch, device, _vp(self.stream.cuda_stream))
 
     def close(self):
@@ -881,7 +906,7 @@ def epdlb_batch_destroy(b):
 
 class Batch:
     """Many replicas (uneven grids, own drive, A fraction and seed) advanced
-    together on one GPU; work is queued on torch's current stream."""
+    together on one GPU; work is queued on `work_stream(device)`."""
 
     def __init__(self, params_list, device=0):
         import torch
@@ -889,7 +914,7 @@ class Batch:
             raise RuntimeError("epdlb needs a ROCm GPU (gfx950); none is visible")
         self.params = [p if isinstance(p, epdlb_params) else make_params(p) for p in params_list]
         self.shapes = [(p.ny, p.nx) for p in self.params]
-        self.stream = torch.cuda.current_stream(torch.device("cuda", device))
+        self.stream = work_stream(device)
         self.b = epdlb_batch_create(self.params, device, _vp(self.stream.cuda_stream))
 
     def close(self):
@@ -955,9 +980,8 @@ class Batch:
 
 class Fluid3D:
     """Periodic D3Q19 fluid box (epdlb_lb3_* in include/epdlb.h): host arrays
-    are FP64 with shape (planes, nz, ny, nx); work is queued on torch's
-    current stream, or on a stream of the library's own when that is the
-    null stream."""
+    are FP64 with shape (planes, nz, ny, nx); work is queued on
+    `work_stream(device)`."""
 
     def __init__(self, nx, ny, nz, tau, precision=1, device=0):
         import torch
@@ -965,7 +989,7 @@ class Fluid3D:
             raise RuntimeError("epdlb needs a ROCm GPU (gfx950); none is visible")
         self.shape = (nz, ny, nx)
         self.n = nx * ny * nz
-        self.stream = torch.cuda.current_stream(torch.device("cuda", device))
+        self.stream = work_stream(device)
         out = _vp()
         _check(load_library().epdlb_lb3_create(nx, ny, nz, tau, precision, device, _vp(self.stream.cuda_stream),
                                                ctypes.byref(out)), "epdlb_lb3_create")
@@ -1035,7 +1059,7 @@ class Densities3D:
             raise RuntimeError("epdlb needs a ROCm GPU (gfx950); none is visible")
         self.shape = (nz, ny, nx)
         self.n = nx * ny * nz
-        self.stream = torch.cuda.current_stream(torch.device("cuda", device))
+        self.stream = work_stream(device)
         out = _vp()
         _check(load_library().epdlb_epd3_create(nx, ny, nz, n_contour, f_A, phi_P, R_G, dx, precision, device,
                                                 _vp(self.stream.cuda_stream), ctypes.byref(out)),

@@ -285,6 +285,7 @@ int validate(const epdlb_params* p) {
     if (p->precision == 1 && p->cg_tol < 1e-6)
       return fail(EPDLB_EINVAL, "cg_tol below 1e-6 needs FP64 fields (precision 0)");
   }
+  if (!(p->mach_max >= 0.0) || !std::isfinite(p->mach_max)) return fail(EPDLB_EINVAL, "mach_max must be >= 0");
   return EPDLB_OK;
 }
 
@@ -727,6 +728,9 @@ int stage_lb(epdlb_ctx* c) {
   a.gs = T(p.lb_gamma_s);
   a.gb = T(p.lb_gamma_b);
   a.gg = T(p.lb_gamma_g);
+  // |u| > mach_max c_s, c_s^2 = 1/3 in lattice units; 0 disables the speed test
+  a.umax2 = p.mach_max > 0.0 ? T(p.mach_max * p.mach_max / 3.0) : T(INFINITY);
+  a.guard = c->ptr<unsigned>(c->L.counters);
   a.nrep = c->nrep;
   a.rs = long(c->rstride);
   {
@@ -1079,7 +1083,10 @@ size_t elem(const epdlb_ctx* c) { return c->p.precision == 0 ? 8 : 4; }
 int reset_scal(epdlb_ctx* c, int r) {
   double sc[kNumScal] = {0};
   sc[kGext] = g_lattice(c->rp[r]);
+  const unsigned guard[16] = {0};
   HIPCHK(hipMemcpyAsync(c->base + c->roff(r) + c->L.scal, sc, sizeof(sc), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->base + c->roff(r) + c->L.counters, guard, sizeof(guard), hipMemcpyHostToDevice,
+                        c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return EPDLB_OK;
 }
@@ -1270,10 +1277,16 @@ void default_shapes(epdlb_ctx* c) {
 int check_finite(epdlb_ctx* c) {
   for (int r = 0; r < c->nrep; ++r) {
     double s[kNumScal];
+    unsigned g[kNumGuard];
     HIPCHK(hipMemcpyAsync(s, c->base + c->roff(r) + c->L.scal, sizeof(s), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(g, c->base + c->roff(r) + c->L.counters, sizeof(g), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    const std::string who = c->nrep > 1 ? " (replica " + std::to_string(r) + " of its group)" : "";
     for (int i = 0; i < kNumScal; ++i)
-      if (!std::isfinite(s[i])) return fail(EPDLB_ENONFINITE, "non-finite partition function or field mean");
+      if (!std::isfinite(s[i])) return fail(EPDLB_ENONFINITE, "non-finite partition function or field mean" + who);
+    if (g[kGuardNonFinite]) return fail(EPDLB_ENONFINITE, "non-finite LB density or velocity" + who);
+    if (g[kGuardMach]) return fail(EPDLB_EUNSTABLE, "LB flow speed above mach_max times the speed of sound" + who);
+    if (g[kGuardNegative]) return fail(EPDLB_EUNSTABLE, "negative LB population" + who);
   }
   return EPDLB_OK;
 }
@@ -1315,7 +1328,8 @@ bool same_model(const epdlb_params& a, const epdlb_params& b) {
          a.D_B == b.D_B && a.R_G == b.R_G && a.dx == b.dx && a.dt == b.dt && a.kT_over_v == b.kT_over_v &&
          a.lb_tau == b.lb_tau && a.g_units == b.g_units && a.precision == b.precision &&
          a.init_flow == b.init_flow && a.couple_lb == b.couple_lb && a.lb_mrt == b.lb_mrt &&
-         a.lb_gamma_s == b.lb_gamma_s && a.lb_gamma_b == b.lb_gamma_b && a.lb_gamma_g == b.lb_gamma_g;
+         a.lb_gamma_s == b.lb_gamma_s && a.lb_gamma_b == b.lb_gamma_b && a.lb_gamma_g == b.lb_gamma_g &&
+         a.mach_max == b.mach_max;
 }
 
 // A group context over `rp` (same grid shape), arena allocated here.
@@ -1468,10 +1482,27 @@ int epdlb_params_default(epdlb_params* p) {
   p->cg_max_iter = 1000;
   p->cg_tol = 1e-8;
   p->cg_precond = 0;
+  p->mach_max = 0.5;
   return EPDLB_OK;
 }
 
 int epdlb_validate(const epdlb_params* p) { return validate(p); }
+
+int epdlb_mrt_gammas(double eta, double eta_B, double rho, double dx, double dt, int32_t dim,
+                     double* gamma_s, double* gamma_b) {
+  if (!gamma_s || !gamma_b) return fail(EPDLB_EINVAL, "NULL output");
+  if (dim != 2 && dim != 3) return fail(EPDLB_EINVAL, "dim must be 2 or 3");
+  const double v[5] = {eta, eta_B, rho, dx, dt};
+  for (double x : v)
+    if (!(x > 0.0) || !std::isfinite(x)) return fail(EPDLB_EINVAL, "eta, eta_B, rho, dx, dt must be finite and > 0");
+  // eta = (dt rho cs2 / 2) (1 + g)/(1 - g)  <=>  g = (a - 1)/(a + 1), a = 2 eta/(dt rho cs2)
+  const double cs2 = dx * dx / (3.0 * dt * dt);
+  const double a = 2.0 * eta / (dt * rho * cs2);
+  const double b = double(dim) * eta_B / (dt * rho * cs2);
+  *gamma_s = (a - 1.0) / (a + 1.0);
+  *gamma_b = (b - 1.0) / (b + 1.0);
+  return EPDLB_OK;
+}
 
 int epdlb_workspace_bytes(const epdlb_params* p, size_t* bytes) {
   CHK(validate(p));

@@ -861,12 +861,31 @@ template <typename T> struct LbArgs {
   T omega;         // BGK: 1/tau
   T fpre;          // BGK: 1 - 1/(2 tau)
   T gs, gb, gg;    // multi-relaxation: shear, bulk and non-hydrodynamic factors
+  T umax2;         // flow-speed guard: |u|^2 above this sets guard[kGuardMach]
+  unsigned* guard; // kNumGuard flags of the replica, set (never cleared) by the kernel
   int nrep;
   long rs;
   __device__ void shift(long o) {
     fin = sh(fin, o), fout = sh(fout, o), F = sh(F, o), rho = sh(rho, o), u = sh(u, o);
+    guard = sh(guard, o);
   }
 };
+
+// Stability flags of one replica, raised by the LB kernel and reported by the
+// host at the next synchronisation: the flow speed above the guard, a
+// negative post-collision population, a density or velocity that is not finite.
+enum Guard : int { kGuardMach = 0, kGuardNegative = 1, kGuardNonFinite = 2, kNumGuard = 3 };
+
+// Raises the flags some lane of the wave found (one store per flag and wave).
+template <typename T>
+__device__ __forceinline__ void lb_guard(unsigned* guard, T rho, T usq, T umax2, T fmin) {
+  const bool nonfinite = !isfinite(rho) || !isfinite(usq);
+  const bool fast = !nonfinite && usq > umax2;
+  const bool neg = !nonfinite && fmin < T(0);
+  if (__any(nonfinite) && nonfinite) guard[kGuardNonFinite] = 1u;
+  if (__any(fast) && fast) guard[kGuardMach] = 1u;
+  if (__any(neg) && neg) guard[kGuardNegative] = 1u;
+}
 
 // MRT = false: BGK collision with relaxation time tau and the second-order
 // force term.  MRT = true: the multi-relaxation collision in moment space
@@ -943,13 +962,19 @@ __global__ void __launch_bounds__(256) k_lb(LbArgs<T> P) {
       o[k] = hpost + P.gg * (g[k] - hpre);
     }
     o[0] = drho - (((o[1] + o[2]) + (o[3] + o[4])) + ((o[5] + o[6]) + (o[7] + o[8])));
+    T fmin = o[0] + T(4.0 / 9.0);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) P.fout[k * P.n + i] = o[k];
+    for (int k = 0; k < 9; ++k) {
+      P.fout[k * P.n + i] = o[k];
+      fmin = min(fmin, o[k] + (k == 0 ? T(4.0 / 9.0) : (k < 5 ? T(1.0 / 9.0) : T(1.0 / 36.0))));
+    }
+    lb_guard(P.guard, rho, usq, P.umax2, fmin);
     P.rho[i] = rho;
     P.u[i] = ux;
     P.u[P.n + i] = uy;
     return;
   }
+  T fmin = T(1);
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
     const T w = k == 0 ? T(4.0 / 9.0) : (k < 5 ? T(1.0 / 9.0) : T(1.0 / 36.0));
@@ -959,8 +984,11 @@ __global__ void __launch_bounds__(256) k_lb(LbArgs<T> P) {
     const T cF = T(cx[k]) * Fx + T(cy[k]) * Fy;
     const T cmuF = (T(cx[k]) - ux) * Fx + (T(cy[k]) - uy) * Fy;
     const T src = w * (T(3) * cmuF + T(9) * cu * cF);
-    P.fout[k * P.n + i] = g[k] - (g[k] - geq) * P.omega + P.fpre * src;
+    const T o = g[k] - (g[k] - geq) * P.omega + P.fpre * src;
+    P.fout[k * P.n + i] = o;
+    fmin = min(fmin, o + w);
   }
+  lb_guard(P.guard, rho, usq, P.umax2, fmin);
   P.rho[i] = rho;
   P.u[i] = ux;
   P.u[P.n + i] = uy;

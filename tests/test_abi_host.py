@@ -58,6 +58,7 @@ def test_defaults_and_validation():
     assert abs(gs + 0.8050541516245486) < 1e-15 and gs == gb
     assert B.epdlb_validate(B.make_params(lb_mrt=1, lb_gamma_s=gs, lb_gamma_b=gb, lb_gamma_g=0.5)) == 0
     assert (p.cg_invert, p.cg_max_iter, p.cg_tol, p.cg_precond) == (0, 1000, 1e-8, 0)
+    assert p.mach_max == 0.5 and B.epdlb_validate(B.make_params(mach_max=0.0)) == 0
     assert B.epdlb_validate(B.make_params(cg_invert=1)) == 0
     assert B.epdlb_validate(B.make_params(cg_invert=1, precision=1, cg_tol=1e-6)) == 0
     for bad in [dict(nx=48), dict(nx=16), dict(ny=8), dict(n_contour=1), dict(f_A=1.0),
@@ -68,10 +69,28 @@ def test_defaults_and_validation():
                 dict(lb_mrt=1, lb_gamma_b=-1.0), dict(lb_mrt=1, lb_gamma_g=float("nan")),
                 dict(cg_invert=2), dict(cg_invert=1, density_mode=1), dict(cg_invert=1, cg_tol=0.0),
                 dict(cg_invert=1, cg_max_iter=-1), dict(cg_invert=1, cg_tol=float("inf")),
-                dict(cg_invert=1, precision=1), dict(cg_precond=2)]:
+                dict(cg_invert=1, precision=1), dict(cg_precond=2), dict(mach_max=-0.1),
+                dict(mach_max=float("nan"))]:
         q = B.make_params(**bad)
         assert B.epdlb_validate(q) == B.EPDLB_EINVAL, bad
         assert B.epdlb_last_error() != ""
+
+
+def test_mrt_gammas_from_the_library_match_the_oracle():
+    """The viscosity relations of Sec. II are computed in the library
+    (epdlb_mrt_gammas); they agree with the pinned oracle relation in two and
+    three dimensions, and bad arguments are refused."""
+    from oracle import epdlb_oracle as O
+    for d in (2, 3):
+        for eta, eta_B, rho, dx, dt in ((1.0, 1.0, 1.0, 1 / 3, 0.002), (0.7, 2.5, 1.3, 0.25, 0.004)):
+            got = B.epdlb_mrt_gammas(eta, eta_B, rho, dx, dt, d)
+            ref = O.mrt_gammas(eta, eta_B, rho, dx, dt, d=d)
+            assert max(abs(got[0] - ref[0]), abs(got[1] - ref[1])) < 1e-15, (d, eta, eta_B)
+    for bad in [(0.0, 1.0, 1.0, 0.3, 0.002, 2), (1.0, -1.0, 1.0, 0.3, 0.002, 2), (1.0, 1.0, 1.0, 0.3, 0.0, 2),
+                (1.0, 1.0, float("nan"), 0.3, 0.002, 2), (1.0, 1.0, 1.0, 0.3, 0.002, 4)]:
+        with pytest.raises(B.EpdlbError) as e:
+            B.epdlb_mrt_gammas(*bad)
+        assert e.value.code == B.EPDLB_EINVAL
 
 
 def test_workspace_bytes_scale():

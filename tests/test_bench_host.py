@@ -31,6 +31,38 @@ def test_measured_traffic_entries_match_sources():
     assert bench.measured_traffic("cfg3", "lb") is None
 
 
+def test_window_starts_at_an_exact_step_inside_the_run():
+    """The timed window holds exactly K steps, starts on a fallback step at least W
+    steps into the run, and ends inside the 2e4-step run whenever it fits."""
+    for K, W in ((20, 5), (2000, 50), (1, 0), (50, 0), (19990, 5), (30000, 7), (777, 333)):
+        s = bench.window_start(20000, K, W)
+        assert s % bench.FALLBACK_EVERY == 0 and s >= W, (K, W, s)
+        if K + W + bench.FALLBACK_EVERY <= 20000:
+            assert s + K <= 20000 and s + K > 20000 - bench.FALLBACK_EVERY - K % bench.FALLBACK_EVERY, (K, W, s)
+    assert bench.window_start(20000, 20, 5) == 19950
+    assert bench.window_start(20000, 2000, 50) == 18000
+
+
+def test_bad_step_counts_refused():
+    for argv in (["--steps", "0"], ["--steps", "-30"], ["--warmup", "-1"]):
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + argv,
+                           capture_output=True, text=True, timeout=120)
+        assert r.returncode == 2 and "must be" in r.stderr, argv
+
+
+def test_host_cpu_description():
+    h = bench.host_cpu()
+    assert h["nproc"] >= 1 and h["available"] >= 1
+
+
+def test_cpu_baseline_legs_run():
+    """Both legs of the oracle baseline run on a small workload (the single
+    process and the side-by-side processes, one thread each)."""
+    r = bench.cpu_baseline("cfg1", 0.2, max_procs=2)
+    assert r["kind"] == "oracle" and r["value"] > 0 and r["cores"] == min(2, bench.host_cpu()["available"])
+    assert r["single_core"]["value"] > 0 and r["single_core"]["cores"] == 1
+
+
 def test_peaks_and_flop_model():
     assert bench.HBM_PEAK_GBS == 8000.0 and bench.BF16_MFMA_PEAK_TFLOPS == 2500.0
     assert bench.NN_FLOPS_PER_SITE["nn_conv"] == 73728

@@ -313,3 +313,23 @@ def test_site_mrt_matches_whole_lattice_step():
         o, r, v = L.site(f, F, 0.0, z, y, x, mrt=(0.2, -0.4, 0.3))
         assert np.allclose(o, out[:, z, y, x], rtol=0, atol=1e-15)
         assert abs(r - rho[z, y, x]) < 1e-15 and np.allclose(v, u[:, z, y, x], rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_mrt_gammas_invert_the_pinned_viscosities(d):
+    """The viscosity relations of Sec. II in d dimensions: the factors from
+    mrt_gammas give back the lattice viscosities nu = eta dt/(rho dx^2) and
+    nu_B = eta_B dt/(rho dx^2) through the shear (gamma_s) and bulk (gamma_b)
+    relations that the shear-wave and sound-attenuation tests above fix (d = 3)
+    and that the two-dimensional ones fix (d = 2: nu_B = (c_s^2/2)(1 + gamma_b)/(1 - gamma_b))."""
+    from oracle import epdlb_oracle as O2
+    dx, dt = 1.0 / 3.0, 0.002
+    conv = dt / dx ** 2
+    for eta, eta_B, rho in ((1.0, 1.0, 1.0), (0.7, 2.5, 1.0), (1.3, 0.4, 1.7)):
+        gs, gb = O2.mrt_gammas(eta, eta_B, rho, dx, dt, d=d)
+        if d == 3:
+            nu, nuB = L.mrt_viscosities(gs, gb)
+        else:
+            nu = 0.5 * O2.CS2 * (1 + gs) / (1 - gs)
+            nuB = 0.5 * O2.CS2 * (1 + gb) / (1 - gb)
+        assert abs(nu - eta * conv / rho) < 1e-14 and abs(nuB - eta_B * conv / rho) < 1e-14, (eta, eta_B, rho)

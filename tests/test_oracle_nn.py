@@ -154,3 +154,58 @@ def test_surrogate_force_differences_one_estimator():
         ref = sum((f(s["omegas"][k])[I] - f(s["omegas"][k - 1])[I]) / D[I] for I in range(3))
         assert np.max(np.abs(s["Ss"][k - 1] - ref)) < 1e-12, k
     assert np.allclose(s["errs"], np.max(np.abs(delta[:2])), rtol=0, atol=1e-16)
+
+
+def test_activation_closed_forms():
+    """softplus(z) = ln(1 + e^z), sigmoid its derivative, SiLU z sigmoid(z) with
+    derivative sigmoid(z)(1 + z(1 - sigmoid(z))), at points with closed values."""
+    z = np.array([0.0, np.log(np.e - 1.0), -np.log(3.0), 40.0, -40.0])
+    assert np.allclose(NN.softplus(z), [np.log(2.0), 1.0, np.log(4.0 / 3.0), 40.0, np.exp(-40.0)],
+                       rtol=1e-15, atol=1e-300)
+    assert np.allclose(NN.sigmoid(np.array([0.0, np.log(3.0)])), [0.5, 0.75], rtol=1e-15)
+    assert np.allclose(NN.silu(np.array([0.0, np.log(3.0)])), [0.0, 0.75 * np.log(3.0)], rtol=1e-15)
+    h = 1e-6
+    zz = np.linspace(-4, 4, 17)
+    assert np.max(np.abs((NN.softplus(zz + h) - NN.softplus(zz - h)) / (2 * h) - NN.sigmoid(zz))) < 1e-9
+    assert np.max(np.abs((NN.silu(zz + h) - NN.silu(zz - h)) / (2 * h) - NN.silu_grad(zz))) < 1e-9
+
+
+def test_input_channels_and_gauge_invariance():
+    """The network sees w_I - <w_I> and the constant channels f_A and 1/N, so its
+    densities, like the exact ones (Sec. II: the potentials enter only up to a
+    constant per species), do not change when a constant is added to a field."""
+    rng = np.random.default_rng(9)
+    omega = 0.3 * rng.standard_normal((3, 8, 8))
+    x = NN.make_input(omega, 0.3, 32)
+    assert np.all(x[..., 3] == 0.3) and np.all(x[..., 4] == 0.03125)
+    assert np.max(np.abs(x[..., :3].mean(axis=(0, 1)))) < 1e-16
+    params = small_params(rng)
+    p = dict(f_A=0.3, phi_P=0.15, n_contour=32)
+    a = NN.predict_densities(params, omega, p)
+    b = NN.predict_densities(params, omega + np.array([0.7, -1.2, 2.5])[:, None, None], p)
+    assert np.max(np.abs(a - b)) < 1e-14
+    ex_a = O.densities(omega, dict(O_defaults(), nx=8, ny=8, n_contour=32, f_A=0.3, phi_P=0.15))["phi"]
+    ex_b = O.densities(omega + np.array([0.7, -1.2, 2.5])[:, None, None],
+                       dict(O_defaults(), nx=8, ny=8, n_contour=32, f_A=0.3, phi_P=0.15))["phi"]
+    assert np.max(np.abs(ex_a - ex_b)) < 1e-14
+
+
+def test_exact_steps_fall_on_multiples_of_the_fallback_interval():
+    """Step k (counted from 0 after seeding) is exact when k % fallback_every == 0:
+    the first step is exact, and with a biased estimator the state's densities
+    carry the bias exactly after the other steps."""
+    p = _small_p(couple_lb=0)
+    rng = np.random.default_rng(12)
+    w0 = 0.2 * rng.standard_normal((3, p["ny"], p["nx"]))
+    delta = 1e-3 * rng.standard_normal((3, p["ny"], p["nx"]))
+    delta[2] = 0.0
+
+    def f(w):
+        return O.densities(w, p)["phi"] + delta
+
+    for n in range(1, 8):
+        s = NN.surrogate_run(p, None, w0, n, 3, dens_fn=f)
+        assert len(s["errs"]) == 1 + len(range(0, n, 3)), n
+        last_exact = (n - 1) % 3 == 0
+        dev = np.max(np.abs(s["phi"] - O.densities(s["omega"], p)["phi"]))
+        assert (dev < 1e-15) if last_exact else abs(dev - np.max(np.abs(delta))) < 1e-15, n
