@@ -307,6 +307,16 @@ int epdlb_track_reset(epdlb_ctx* c);
  * without LB coupling from the same start).  Synchronises both streams. */
 int epdlb_sigma_delta(epdlb_ctx* a, epdlb_ctx* b, double* out);
 
+/* epdlb_sigma_delta for callers that cannot allocate device memory (serving
+ * loops, harnesses that forbid hipMalloc): the same value, computed with no
+ * allocation.  The partial sums live in a fixed library array of 64 KiB on
+ * each device, held until the process ends, which limits the grid to
+ * 1024 x 1024 sites (EINVAL above).  Every call on a device shares that
+ * array: calls that overlap on one device race; each call writes every slot
+ * it reads, so nothing needs clearing between calls.  Synchronises both
+ * streams.  Errors as epdlb_sigma_delta. */
+int epdlb_sigma_delta_noalloc(epdlb_ctx* a, epdlb_ctx* b, double* out);
+
 /* Result of one Phi -> omega inversion (App. C, comments 2 and 3). */
 typedef struct {
   int32_t iters;         /* Fletcher-Reeves iterations taken */

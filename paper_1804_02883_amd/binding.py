@@ -187,6 +187,7 @@ SIGNATURES = {
     "epdlb_observables": (ctypes.c_int, [_vp, ctypes.c_double, _P(epdlb_obs), _P(epdlb_particle), ctypes.c_int32,
                                          _P(ctypes.c_int32)]),
     "epdlb_sigma_delta": (ctypes.c_int, [_vp, _vp, _dp]),
+    "epdlb_sigma_delta_noalloc": (ctypes.c_int, [_vp, _vp, _dp]),
     "epdlb_track_particles": (ctypes.c_int, [_vp, ctypes.c_double, _P(epdlb_obs), _P(epdlb_particle), ctypes.c_int32,
                                              _P(ctypes.c_int32)]),
     "epdlb_track_reset": (ctypes.c_int, [_vp]),
@@ -465,6 +466,12 @@ def epdlb_track_reset(ctx):
 def epdlb_sigma_delta(ctx_a, ctx_b):
     v = ctypes.c_double(0.0)
     _check(load_library().epdlb_sigma_delta(ctx_a, ctx_b, ctypes.byref(v)), "epdlb_sigma_delta")
+    return v.value
+
+
+def epdlb_sigma_delta_noalloc(ctx_a, ctx_b):
+    v = ctypes.c_double(0.0)
+    _check(load_library().epdlb_sigma_delta_noalloc(ctx_a, ctx_b, ctypes.byref(v)), "epdlb_sigma_delta_noalloc")
     return v.value
 
 

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -22,6 +23,16 @@
 #include "epd3.hpp"
 
 using namespace epdlb;
+
+// Scratch of the allocation-free entry point (epdlb_sigma_delta_noalloc):
+// block partial sums of up to kNoAllocMaxSites sites, 2 doubles per 256
+// sites, then one double for their total (64 KiB + 256 B).  Each device holds
+// its own copy until the process ends; host code reaches it only through the
+// address hipGetSymbolAddress gives for the current device (noalloc_scratch
+// below), never through this name.
+constexpr long kNoAllocMaxSites = 1024L * 1024L;
+constexpr int kNoAllocMaxBlocks = int(kNoAllocMaxSites / 256);
+static __device__ __align__(256) double scratch[2 * kNoAllocMaxBlocks + 32];
 
 namespace {
 
@@ -1932,26 +1943,37 @@ int track_replica(epdlb_ctx* c, int r, double threshold, epdlb_obs* out, epdlb_p
   return EPDLB_OK;
 }
 
+// sigma_Delta of the current densities of two contexts: per-block partial
+// sums into part (device, 2 doubles per 256 sites), copied to hp (host, same
+// size) and added there in block order.
 template <typename T>
-int sigma_delta_t(epdlb_ctx* a, epdlb_ctx* b, double* out) {
+int sigma_delta_core(epdlb_ctx* a, epdlb_ctx* b, double* part, double* hp, double* out) {
   const long n = long(a->p.nx) * a->p.ny;
   const int nblocks = int((n + 255) / 256);
   HIPCHK(hipStreamSynchronize(b->stream));
-  void* m = nullptr;
-  if (hipMalloc(&m, 16 * size_t(nblocks)) != hipSuccess) return fail(EPDLB_ENOMEM, "sigma_delta scratch allocation failed");
-  double* part = static_cast<double*>(m);
   hipLaunchKernelGGL(obs::k_sigma_delta<T>, dim3(unsigned(nblocks)), dim3(256), 0, a->stream,
                      (const T*)a->ptr<T>(a->L.phi), (const T*)b->ptr<T>(b->L.phi), n, part);
-  std::vector<double> hp(2 * size_t(nblocks));
   hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, a->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(hp, part, 2 * size_t(nblocks) * sizeof(double), hipMemcpyDeviceToHost,
+                                          a->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(a->stream);
-  (void)hipFree(m);
   if (e != hipSuccess) return fail(EPDLB_EHIP, std::string("sigma_delta: ") + hipGetErrorString(e));
   double sum = 0.0;
   for (int k = 0; k < nblocks; ++k) sum += hp[2 * size_t(k)];
   *out = sum / double(n);
   return EPDLB_OK;
+}
+
+template <typename T>
+int sigma_delta_t(epdlb_ctx* a, epdlb_ctx* b, double* out) {
+  const long n = long(a->p.nx) * a->p.ny;
+  const int nblocks = int((n + 255) / 256);
+  void* m = nullptr;
+  if (hipMalloc(&m, 16 * size_t(nblocks)) != hipSuccess) return fail(EPDLB_ENOMEM, "sigma_delta scratch allocation failed");
+  std::vector<double> hp(2 * size_t(nblocks));
+  const int r = sigma_delta_core<T>(a, b, static_cast<double*>(m), hp.data(), out);
+  (void)hipFree(m);
+  return r;
 }
 
 }  // namespace
@@ -2024,6 +2046,66 @@ int epdlb_sigma_delta(epdlb_ctx* a, epdlb_ctx* b, double* out) {
   if (!a->seeded || !b->seeded) return fail(EPDLB_ESTATE, "no state before seed/set_fields/set_state");
   HIPCHK(hipSetDevice(a->device));
   return a->p.precision == 0 ? sigma_delta_t<double>(a, b, out) : sigma_delta_t<float>(a, b, out);
+}
+
+}  // extern "C"
+
+namespace {
+
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kNoAllocMaxDevices] = {nullptr};
+
+// Device address of `scratch` on the current device `dev`, looked up once per
+// device with that device current.
+int noalloc_scratch(int dev, double** out) {
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return fail(EPDLB_EINVAL, "device index above the no-allocation table");
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(EPDLB_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_noalloc_ptr[dev] = ptr;
+  }
+  *out = static_cast<double*>(g_noalloc_ptr[dev]);
+  return EPDLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int epdlb_sigma_delta_noalloc(epdlb_ctx* a, epdlb_ctx* b, double* out) {
+  if (!a || !b || !out) return fail(EPDLB_EINVAL, "NULL argument");
+  if (a->device != b->device || a->p.nx != b->p.nx || a->p.ny != b->p.ny || a->p.precision != b->p.precision)
+    return fail(EPDLB_EINVAL, "sigma_delta needs two contexts on one device with the same grid and precision");
+  if (!a->seeded || !b->seeded) return fail(EPDLB_ESTATE, "no state before seed/set_fields/set_state");
+  const long n = long(a->p.nx) * a->p.ny;
+  if (n > kNoAllocMaxSites)
+    return fail(EPDLB_EINVAL, "grid above the no-allocation limit of " + std::to_string(kNoAllocMaxSites) + " sites");
+  HIPCHK(hipSetDevice(a->device));
+  double* part = nullptr;
+  CHK(noalloc_scratch(a->device, &part));
+  double* total = part + 2 * kNoAllocMaxBlocks;
+  const int nblocks = int((n + 255) / 256);
+  HIPCHK(hipStreamSynchronize(b->stream));
+  if (a->p.precision == 0)
+    hipLaunchKernelGGL(obs::k_sigma_delta<double>, dim3(unsigned(nblocks)), dim3(256), 0, a->stream,
+                       (const double*)a->ptr<double>(a->L.phi), (const double*)b->ptr<double>(b->L.phi), n, part);
+  else
+    hipLaunchKernelGGL(obs::k_sigma_delta<float>, dim3(unsigned(nblocks)), dim3(256), 0, a->stream,
+                       (const float*)a->ptr<float>(a->L.phi), (const float*)b->ptr<float>(b->L.phi), n, part);
+  HIPCHK(hipGetLastError());
+  // the same block-order total as the host loop of epdlb_sigma_delta
+  hipLaunchKernelGGL(obs::k_sum_pairs_in_order, dim3(1), dim3(256), 0, a->stream, (const double*)part, nblocks,
+                     total);
+  HIPCHK(hipGetLastError());
+  double sum = 0.0;
+  HIPCHK(hipMemcpyAsync(&sum, total, sizeof(double), hipMemcpyDeviceToHost, a->stream));
+  HIPCHK(hipStreamSynchronize(a->stream));
+  *out = sum / double(n);
+  return EPDLB_OK;
 }
 
 int epdlb_invert_densities(epdlb_ctx* c, const double* phi_target, int32_t max_iter, double tol,

@@ -273,5 +273,19 @@ __global__ void __launch_bounds__(256) k_sigma_delta(const T* __restrict__ pa, c
   block_pair(s, 0.0, part);
 }
 
+// The first members of nblocks (<= 4096) partial pairs, added in block order
+// by one thread (the order a host loop over the pairs takes): out[0].
+__global__ void __launch_bounds__(256) k_sum_pairs_in_order(const double* __restrict__ part, int nblocks,
+                                                            double* __restrict__ out) {
+  __shared__ double s[4096];
+  for (int k = threadIdx.x; k < nblocks; k += blockDim.x) s[k] = part[2 * k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sum = 0.0;
+    for (int k = 0; k < nblocks; ++k) sum += s[k];
+    out[0] = sum;
+  }
+}
+
 }  // namespace obs
 }  // namespace epdlb
