@@ -98,8 +98,11 @@ def measured_traffic(workload, fam):
 #                   writes q_{a+1} + scratch (4P); the last reads scratch +
 #                   factor and writes q_N (3P)
 #   density       : read 2N chain planes + omega_S + S~, write Phi 3 + S = (2N + 6)P
-#   force_*       : 3P + 4P + 4P (row FFT of S, column pass, row inverse)
-#   lb            : read 9 populations + F 2; write 9 + rho + u 2        = 23P
+#   force_*       : 3P + 4P (row FFT of S, column pass)
+#   force_inv_lb  : the row-inverse force pass fused with the LB step: read the
+#                   force spectrum 2 and 9 populations; write F 2 (kept for
+#                   reads), 9 populations, rho, u 2                      = 25P
+#   (force_row_inv 4P and lb 23P when a row shape runs them separately)
 def step_bytes_per_site(kind, N, P):
     last_row = (N - 1) % 2 == 1           # the final propagator launch is x-oriented
     n_fused_row = sum(1 for s in range(N - 1) if s % 2 == 1)
@@ -110,8 +113,8 @@ def step_bytes_per_site(kind, N, P):
         "advect_update": 12 * P,
         "prop_row": 2 * per_chain_row * P, "prop_col": 2 * per_chain_col * P,
         "density": (2 * N + 6) * P,
-        "force_row_fwd": 3 * P, "force_col": 4 * P, "force_row_inv": 4 * P,
-        "lb": 23 * P,
+        "force_row_fwd": 3 * P, "force_col": 4 * P, "force_inv_lb": 25 * P,
+        "force_row_inv": 4 * P, "lb": 23 * P,
     }.get(kind)
 
 

@@ -213,12 +213,12 @@ int nn_after_seed(epdlb_ctx* c);
 
 enum Kind { K_STATS, K_ADVECT, K_FINISH, K_PROP_ROW, K_PROP_COL, K_DENSITY, K_FROW_FWD, K_FCOL,
             K_FROW_INV, K_LB, K_NN_CONV0, K_NN_CONV, K_NN_OUT, K_NN_NORM, K_NN_RESET, K_ADVECT_ONLY, K_CG,
-            K_NUM };
+            K_FINV_LB, K_NORM_FROW, K_NUM };
 const char* const kKindName[K_NUM] = {"field_stats", "advect_update", "finish_stats",
                                       "prop_row",    "prop_col",      "density",       "force_row_fwd",
                                       "force_col",   "force_row_inv", "lb",            "nn_conv0",
                                       "nn_conv",     "nn_out",        "nn_norm",       "nn_reset",
-                                      "advect_only", "cg_vector"};
+                                      "advect_only", "cg_vector",     "force_inv_lb",  "nn_norm_force_row"};
 
 // Profiling: while the profiler has room, the next kernel launch records a
 // start/stop event pair at the kernel's own start and end (AMD's extended
@@ -467,6 +467,54 @@ hipError_t launch_force_col(const ForceArgs<T>& a, int R, hipStream_t s) {
   return launch_force_col_r<T, L, 8>(a, s);
 }
 
+// Row-inverse force pass fused with the LB step (R = 4 or 8; other shapes run
+// the two kernels separately).
+template <typename T, int L, int R, bool MRT>
+hipError_t launch_force_inv_lb_r(const ForceArgs<T>& a, const LbArgs<T>& b, hipStream_t s) {
+  if constexpr (fft_ok<T, L, R>()) {
+    using V = LdsView<T, L, R, true, 1>;
+    const size_t lds = 2 * size_t(V::size_elems(a.nf)) * sizeof(T);
+    hipError_t e = prep_lds(k_force_inv_lb<T, L, R, MRT>, lds);
+    if (e != hipSuccess) return e;
+    launch_k((k_force_inv_lb<T, L, R, MRT>), dim3((a.ny + a.nf - 1) / a.nf, 1, a.nrep), dim3(a.nf * (L / R)),
+             lds, s, a, b);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+template <typename T, int L>
+hipError_t launch_force_inv_lb(const ForceArgs<T>& a, const LbArgs<T>& b, int R, bool mrt, hipStream_t s) {
+  switch (R) {
+    case 4: return mrt ? launch_force_inv_lb_r<T, L, 4, true>(a, b, s) : launch_force_inv_lb_r<T, L, 4, false>(a, b, s);
+    case 8: return mrt ? launch_force_inv_lb_r<T, L, 8, true>(a, b, s) : launch_force_inv_lb_r<T, L, 8, false>(a, b, s);
+  }
+  return hipErrorInvalidValue;
+}
+bool force_inv_lb_shape(int R) { return R == 4 || R == 8; }
+
+// The surrogate's normalisation fused with the row-forward force pass (R = 4 or 8).
+template <typename T, int L, int R>
+hipError_t launch_norm_force_row_r(const ForceArgs<T>& a, const nn::NormArgs<T>& q, hipStream_t s) {
+  if constexpr (fft_ok<T, L, R>()) {
+    using V = LdsView<T, L, R, true, 1>;
+    const size_t lds = 2 * size_t(V::size_elems(a.nf)) * sizeof(T);
+    hipError_t e = prep_lds(nn::k_norm_force_row<T, L, R>, lds);
+    if (e != hipSuccess) return e;
+    launch_k((nn::k_norm_force_row<T, L, R>), dim3((a.ny + a.nf - 1) / a.nf, 1, 1), dim3(a.nf * (L / R)), lds, s,
+             a, q);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+template <typename T, int L>
+hipError_t launch_norm_force_row(const ForceArgs<T>& a, const nn::NormArgs<T>& q, int R, hipStream_t s) {
+  switch (R) {
+    case 4: return launch_norm_force_row_r<T, L, 4>(a, q, s);
+    case 8: return launch_norm_force_row_r<T, L, 8>(a, q, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 #define EPDLB_SWITCH_L(L, FN, T, ...)                 \
   switch (L) {                                        \
     case 16: return FN<T, 16>(__VA_ARGS__);           \
@@ -493,6 +541,14 @@ template <typename T> hipError_t force_col(int L, int R, const ForceArgs<T>& a, 
 }
 template <typename T> hipError_t force_row_inv(int L, int R, const ForceArgs<T>& a, hipStream_t s) {
   EPDLB_SWITCH_L(L, launch_force_row_inv, T, a, R, s)
+}
+template <typename T>
+hipError_t force_inv_lb(int L, int R, const ForceArgs<T>& a, const LbArgs<T>& b, bool mrt, hipStream_t s) {
+  EPDLB_SWITCH_L(L, launch_force_inv_lb, T, a, b, R, mrt, s)
+}
+template <typename T>
+hipError_t norm_force_row(int L, int R, const ForceArgs<T>& a, const nn::NormArgs<T>& q, hipStream_t s) {
+  EPDLB_SWITCH_L(L, launch_norm_force_row, T, a, q, R, s)
 }
 
 // ---------------------------------------------------------------------------
@@ -722,7 +778,7 @@ int stage_force(epdlb_ctx* c) {
 }
 
 template <typename T>
-int stage_lb(epdlb_ctx* c) {
+LbArgs<T> make_lb_args(epdlb_ctx* c) {
   const epdlb_params& p = c->p;
   LbArgs<T> a;
   const long n = long(p.nx) * p.ny;
@@ -744,6 +800,14 @@ int stage_lb(epdlb_ctx* c) {
   a.guard = c->ptr<unsigned>(c->L.counters);
   a.nrep = c->nrep;
   a.rs = long(c->rstride);
+  return a;
+}
+
+template <typename T>
+int stage_lb(epdlb_ctx* c) {
+  const epdlb_params& p = c->p;
+  const long n = long(p.nx) * p.ny;
+  const LbArgs<T> a = make_lb_args<T>(c);
   {
     ProfScope ps(c, K_LB);
     if (p.lb_mrt)
@@ -754,6 +818,45 @@ int stage_lb(epdlb_ctx* c) {
   HIPCHK(hipGetLastError());
   c->fcur = 1 - c->fcur;
   return EPDLB_OK;
+}
+
+// Force and LB of one step: the row-inverse force pass and the LB step share a
+// launch when the row shape allows it; otherwise the two stages as above.
+// norm (surrogate steps, may be NULL): the network's normalisation, launched
+// together with the first force pass (its shape is then a fusable one).
+template <typename T>
+int stage_force_lb(epdlb_ctx* c, const nn::NormArgs<T>* norm = nullptr) {
+  const epdlb_params& p = c->p;
+  if (!force_inv_lb_shape(c->sh_frow.R)) {
+    CHK(stage_force<T>(c));
+    return stage_lb<T>(c);
+  }
+  ForceArgs<T> a = make_force_args<T>(c);
+  a.nf = c->sh_frow.nf;
+  if (norm) {
+    ProfScope ps(c, K_NORM_FROW);
+    HIPCHK(norm_force_row<T>(p.nx, c->sh_frow.R, a, *norm, c->stream));
+  } else {
+    ProfScope ps(c, K_FROW_FWD);
+    HIPCHK(force_row_fwd<T>(p.nx, c->sh_frow.R, a, c->stream));
+  }
+  a.nf = c->sh_fcol.nf;
+  {
+    ProfScope ps(c, K_FCOL);
+    HIPCHK(force_col<T>(p.ny, c->sh_fcol.R, a, c->stream));
+  }
+  a.nf = c->sh_frow.nf;
+  const LbArgs<T> b = make_lb_args<T>(c);
+  {
+    ProfScope ps(c, K_FINV_LB);
+    HIPCHK(force_inv_lb<T>(p.nx, c->sh_frow.R, a, b, p.lb_mrt != 0, c->stream));
+  }
+  c->fcur = 1 - c->fcur;
+  return EPDLB_OK;
+}
+
+int run_force_lb(epdlb_ctx* c) {
+  return c->p.precision == 0 ? stage_force_lb<double>(c) : stage_force_lb<float>(c);
 }
 
 // ---------------------------------------------------------------------------
@@ -1244,7 +1347,8 @@ int get_graph(epdlb_ctx* c, int steps, int kind, hipGraphExec_t* out) {
   int r = EPDLB_OK;
   for (int s = 0; s < steps && r == EPDLB_OK; ++s) {
     if (kind == 0) {
-      for (int st = EPDLB_STAGE_ADVECT_UPDATE; st <= EPDLB_STAGE_LB && r == EPDLB_OK; ++st) r = run_stage(c, st);
+      for (int st = EPDLB_STAGE_ADVECT_UPDATE; st <= EPDLB_STAGE_DENSITIES && r == EPDLB_OK; ++st) r = run_stage(c, st);
+      if (r == EPDLB_OK) r = run_force_lb(c);
     } else {
       r = run_sur_step(c, kind);
     }
@@ -1415,8 +1519,10 @@ int batch_graph(epdlb_batch* b, int steps, hipGraphExec_t* out) {
   for (size_t i = 0; i < G && r == EPDLB_OK; ++i) {
     epdlb_ctx* c = b->groups[i];
     if (hipStreamWaitEvent(b->fork[i], b->ev_fork, 0) != hipSuccess) r = fail(EPDLB_EHIP, "fork wait");
-    for (int st = 0; st < steps && r == EPDLB_OK; ++st)
-      for (int k = EPDLB_STAGE_ADVECT_UPDATE; k <= EPDLB_STAGE_LB && r == EPDLB_OK; ++k) r = run_stage(c, k);
+    for (int st = 0; st < steps && r == EPDLB_OK; ++st) {
+      for (int k = EPDLB_STAGE_ADVECT_UPDATE; k <= EPDLB_STAGE_DENSITIES && r == EPDLB_OK; ++k) r = run_stage(c, k);
+      if (r == EPDLB_OK) r = run_force_lb(c);
+    }
     if (r == EPDLB_OK && hipEventRecord(b->ev_join[i], b->fork[i]) != hipSuccess) r = fail(EPDLB_EHIP, "join");
     if (r == EPDLB_OK && hipStreamWaitEvent(b->cap, b->ev_join[i], 0) != hipSuccess)
       r = fail(EPDLB_EHIP, "join wait");
@@ -1712,7 +1818,8 @@ int epdlb_step(epdlb_ctx* c, int64_t n) {
     return EPDLB_OK;
   }
   for (int64_t s = 0; s < n; ++s) {
-    for (int st = EPDLB_STAGE_ADVECT_UPDATE; st <= EPDLB_STAGE_LB; ++st) CHK(run_stage(c, st));
+    for (int st = EPDLB_STAGE_ADVECT_UPDATE; st <= EPDLB_STAGE_DENSITIES; ++st) CHK(run_stage(c, st));
+    CHK(run_force_lb(c));
     ++c->nstep;
   }
   return EPDLB_OK;
@@ -2438,7 +2545,8 @@ int epdlb_batch_step(epdlb_batch* b, int64_t n) {
         hipStream_t own = c->stream;
         c->stream = b->stream;
         int r = EPDLB_OK;
-        for (int k = EPDLB_STAGE_ADVECT_UPDATE; k <= EPDLB_STAGE_LB && r == EPDLB_OK; ++k) r = run_stage(c, k);
+        for (int k = EPDLB_STAGE_ADVECT_UPDATE; k <= EPDLB_STAGE_DENSITIES && r == EPDLB_OK; ++k) r = run_stage(c, k);
+        if (r == EPDLB_OK) r = run_force_lb(c);
         c->stream = own;
         CHK(r);
         ++c->nstep;

@@ -876,15 +876,22 @@ template <typename T> struct LbArgs {
 // negative post-collision population, a density or velocity that is not finite.
 enum Guard : int { kGuardMach = 0, kGuardNegative = 1, kGuardNonFinite = 2, kNumGuard = 3 };
 
-// Raises the flags some lane of the wave found (one store per flag and wave).
+// Flags of one lane over the sites it updates; raised in memory by lb_raise.
+struct LbFlags {
+  bool nonfinite = false, fast = false, neg = false;
+};
 template <typename T>
-__device__ __forceinline__ void lb_guard(unsigned* guard, T rho, T usq, T umax2, T fmin) {
-  const bool nonfinite = !isfinite(rho) || !isfinite(usq);
-  const bool fast = !nonfinite && usq > umax2;
-  const bool neg = !nonfinite && fmin < T(0);
-  if (__any(nonfinite) && nonfinite) guard[kGuardNonFinite] = 1u;
-  if (__any(fast) && fast) guard[kGuardMach] = 1u;
-  if (__any(neg) && neg) guard[kGuardNegative] = 1u;
+__device__ __forceinline__ void lb_check(LbFlags& fl, T rho, T usq, T umax2, T fmin) {
+  const bool nf = !isfinite(rho) || !isfinite(usq);
+  fl.nonfinite |= nf;
+  fl.fast |= !nf && usq > umax2;
+  fl.neg |= !nf && fmin < T(0);
+}
+// Lanes that found a condition store its flag (a rare path; all store 1).
+__device__ __forceinline__ void lb_raise(unsigned* guard, const LbFlags& fl) {
+  if (fl.nonfinite) guard[kGuardNonFinite] = 1u;
+  if (fl.fast) guard[kGuardMach] = 1u;
+  if (fl.neg) guard[kGuardNegative] = 1u;
 }
 
 // MRT = false: BGK collision with relaxation time tau and the second-order
@@ -897,18 +904,13 @@ __device__ __forceinline__ void lb_guard(unsigned* guard, T rho, T usq, T umax2,
 //   f*_i = H_i(rho, j + F, Pi*) + gg (f_i - H_i(rho, j, Pi)),
 // H_i(rho, j, Pi) = w_i [rho + 3 j.c_i + 4.5 (Pi - rho/3 I):(c_i c_i - I/3)],
 // the populations that carry exactly (rho, j, Pi).
-template <typename T, bool MRT>
-__global__ void __launch_bounds__(256) k_lb(LbArgs<T> P) {
-  P.shift(long(blockIdx.z) * P.rs);
-  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= P.n) return;
-  const int x = int(i & (P.nx - 1));
-  const int y = int(i / P.nx);
+// Pull streaming of one site: g_k(x) = g*_k(x - c_k) from the previous buffer;
+// c = (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1).
+template <typename T>
+__device__ __forceinline__ void lb_pull(const LbArgs<T>& P, int x, int y, T (&g)[9]) {
   const int xm = (x - 1) & (P.nx - 1), xp = (x + 1) & (P.nx - 1);
   const long ym = long((y - 1) & (P.ny - 1)) * P.nx, yp = long((y + 1) & (P.ny - 1)) * P.nx;
   const long yc = long(y) * P.nx;
-  // pull: f_i(x) = f*_i(x - c_i); c = (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1)
-  T g[9];
   g[0] = P.fin[0 * P.n + yc + x];
   g[1] = P.fin[1 * P.n + yc + xm];
   g[2] = P.fin[2 * P.n + ym + x];
@@ -918,7 +920,12 @@ __global__ void __launch_bounds__(256) k_lb(LbArgs<T> P) {
   g[6] = P.fin[6 * P.n + ym + xp];
   g[7] = P.fin[7 * P.n + yp + xp];
   g[8] = P.fin[8 * P.n + yp + xm];
-  const T Fx = P.F[i], Fy = P.F[P.n + i];
+}
+
+// Collision of the pulled populations g of site i with the force (Fx, Fy);
+// stores f*, rho, u and records the guard's conditions in fl.
+template <typename T, bool MRT>
+__device__ __forceinline__ void lb_collide(const LbArgs<T>& P, long i, const T (&g)[9], T Fx, T Fy, LbFlags& fl) {
   // sum_i w_i = 1 and sum_i w_i c_i = 0, so the deviations carry rho - 1 and the momentum
   const T drho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
   const T rho = T(1) + drho;
@@ -968,7 +975,7 @@ __global__ void __launch_bounds__(256) k_lb(LbArgs<T> P) {
       P.fout[k * P.n + i] = o[k];
       fmin = min(fmin, o[k] + (k == 0 ? T(4.0 / 9.0) : (k < 5 ? T(1.0 / 9.0) : T(1.0 / 36.0))));
     }
-    lb_guard(P.guard, rho, usq, P.umax2, fmin);
+    lb_check(fl, rho, usq, P.umax2, fmin);
     P.rho[i] = rho;
     P.u[i] = ux;
     P.u[P.n + i] = uy;
@@ -988,10 +995,75 @@ __global__ void __launch_bounds__(256) k_lb(LbArgs<T> P) {
     P.fout[k * P.n + i] = o;
     fmin = min(fmin, o + w);
   }
-  lb_guard(P.guard, rho, usq, P.umax2, fmin);
+  lb_check(fl, rho, usq, P.umax2, fmin);
   P.rho[i] = rho;
   P.u[i] = ux;
   P.u[P.n + i] = uy;
+}
+
+template <typename T, bool MRT>
+__global__ void __launch_bounds__(256) k_lb(LbArgs<T> P) {
+  P.shift(long(blockIdx.z) * P.rs);
+  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= P.n) return;
+  const int x = int(i & (P.nx - 1)), y = int(i / P.nx);
+  T g[9];
+  lb_pull(P, x, y, g);
+  LbFlags fl;
+  lb_collide<T, MRT>(P, i, g, P.F[i], P.F[P.n + i], fl);
+  lb_raise(P.guard, fl);
+}
+
+// The row-inverse force pass fused with the LB step of the same rows: the
+// x-inverse FFT of the force spectrum gives (f_x, f_y) of nf rows per block,
+// stored as the lattice force F (as k_force_row_inv does) and handed to the LB
+// step of those sites in registers (as k_lb does with F from memory).  The
+// populations the LB pulls (neighbouring rows of the previous buffer, which
+// no block of this launch writes) are loaded before the transform, so their
+// latency overlaps it.
+template <typename T, int L, int R, bool MRT>
+__global__ void __launch_bounds__(512) k_force_inv_lb(ForceArgs<T> P, LbArgs<T> B) {
+  constexpr int TL = L / R;
+  using V = LdsView<T, L, R, true, 1>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int f = threadIdx.x / TL, j = threadIdx.x % TL;
+  V lds{reinterpret_cast<T2<T>*>(smem_raw), f};
+  P.shift(long(blockIdx.z) * P.rs);
+  B.shift(long(blockIdx.z) * B.rs);
+  const int y = blockIdx.x * P.nf + f;
+  const bool active = y < P.ny;
+  Twiddles<T, L, R> twi;
+  load_inv_twiddles(twi, j, P.tw_x);
+  T re[R], im[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    T2<T> v;
+    v.x = T(0);
+    v.y = T(0);
+    if (active) v = P.spec[long(y) * P.nx + j + TL * m];
+    re[m] = v.x;
+    im[m] = v.y;
+  }
+  T g[R][9];
+  if (active) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) lb_pull(B, j + TL * m, y, g[m]);
+  }
+  fft_inverse(re, im, j, lds, twi);
+  if (!active) return;
+  const T conv = T(P.conv);
+  const double ge = P.scal[kGext];
+  const T fext = T(y < P.ny / 2 ? -ge : ge);
+  LbFlags fl;
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const long i = long(y) * P.nx + j + TL * m;
+    const T Fx = re[m] * conv + fext, Fy = im[m] * conv;
+    P.F[i] = Fx;
+    P.F[P.n + i] = Fy;
+    lb_collide<T, MRT>(B, i, g[m], Fx, Fy, fl);
+  }
+  lb_raise(B.guard, fl);
 }
 
 }  // namespace epdlb

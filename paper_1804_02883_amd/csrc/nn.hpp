@@ -1060,6 +1060,119 @@ __global__ void __launch_bounds__(256) k_nn_norm(NormArgs<T> P) {
   }
 }
 
+// k_nn_norm fused with the row-forward FFT of the force source (the first
+// pass of the force reconstruction, as k_force_row_fwd): each workgroup takes
+// nf rows of the grid, normalises its sites as k_nn_norm does (the scale from
+// the output kernel's partials, added in the same fixed order in every
+// workgroup), keeps S in registers and transforms it along x into the
+// force spectrum.
+template <typename T, int L, int R>
+__global__ void __launch_bounds__(512) k_norm_force_row(ForceArgs<T> F, NormArgs<T> P) {
+  constexpr int TL = L / R;
+  using V = LdsView<T, L, R, true, 1>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[16 * 3];
+  __shared__ double scale_s[2];
+  const int f = threadIdx.x / TL, j = threadIdx.x % TL;
+  V lds{reinterpret_cast<T2<T>*>(smem_raw), f};
+  const int y = blockIdx.x * F.nf + f;
+  const bool in = y < F.ny;
+  const long n = P.n;
+  Twiddles<T, L, R> twf;
+  load_fwd_twiddles(twf, j, F.tw_x);
+  T hA[R], hB[R], wS[R], st[R], cr[R], eA[R], eB[R], eS[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    hA[m] = hB[m] = wS[m] = st[m] = cr[m] = eA[m] = eB[m] = eS[m] = T(0);
+    if (in) {
+      const long i = long(y) * F.nx + j + TL * m;
+      hA[m] = P.src[i];
+      hB[m] = P.src[n + i];
+      wS[m] = P.wS[i];
+      st[m] = P.stilde[i];
+      if (P.use_corr) cr[m] = P.corr[i];
+      if (P.mode != 0) {
+        eA[m] = P.phi[i];
+        eB[m] = P.phi[n + i];
+        eS[m] = P.phi[2 * n + i];
+      }
+    }
+  }
+  {
+    double acc[2] = {0.0, 0.0};
+    const int step = blockDim.x;
+    for (int s0 = threadIdx.x; s0 < P.nslots; s0 += 4 * step) {
+      double v[4][2];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int s = s0 + k * step;
+        v[k][0] = s < P.nslots ? P.part[2 * s] : 0.0;
+        v[k][1] = s < P.nslots ? P.part[2 * s + 1] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (s0 + k * step < P.nslots) {
+          acc[0] += v[k][0];
+          acc[1] += v[k][1];
+        }
+    }
+    nn_block_reduce<2, 2>(acc, red);
+    if (threadIdx.x == 0) {
+      scale_s[0] = P.sumA / acc[0];
+      scale_s[1] = P.sumB / acc[1];
+    }
+    __syncthreads();
+  }
+  const T cS = T(P.V * P.phiSbar / P.scal[kQS]);
+  const T gS = T(P.scal[kGaugeS]);
+  double mx[3] = {0.0, 0.0, 0.0};  // surrogate residual, surrogate error, exact residual
+  T re[R], im[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const T pA = T(scale_s[0]) * hA[m], pB = T(scale_s[1]) * hB[m];
+    const T pS = cS * exp(-(wS[m] - gS));
+    T Sv = pA * T(P.invDA) + pB * T(P.invDB) + pS * T(P.invDS) - st[m];
+    if (P.use_corr) Sv -= cr[m];
+    re[m] = in ? Sv : T(0);
+    im[m] = T(0);
+    if (in) {
+      const long i = long(y) * F.nx + j + TL * m;
+      if (P.mode == 0) {
+        P.phi[i] = pA;
+        P.phi[n + i] = pB;
+        P.phi[2 * n + i] = pS;
+        mx[0] = fmax(mx[0], fabs(double(pA) + double(pB) + double(pS) - 1.0));
+      } else {
+        P.corr[i] = (pA - eA[m]) * T(P.invDA) + (pB - eB[m]) * T(P.invDB);
+        mx[1] = fmax(mx[1], fmax(fabs(double(pA) - double(eA[m])), fabs(double(pB) - double(eB[m]))));
+        mx[2] = fmax(mx[2], fabs(double(eA[m]) + double(eB[m]) + double(eS[m]) - 1.0));
+      }
+      P.S[i] = Sv;
+    }
+  }
+  nn_block_reduce<3, 0>(mx, red);
+  if (threadIdx.x == 0) {
+    if (P.mode == 0) {
+      atomic_max_nonneg(P.scal + kNnResid, mx[0]);
+    } else {
+      atomic_max_nonneg(P.scal + kNnErrLast, mx[1]);
+      atomic_max_nonneg(P.scal + kNnErr, mx[1]);
+      if (!P.use_corr) atomic_max_nonneg(P.scal + kNnErrUse, mx[1]);  // surrogate steps came before
+      atomic_max_nonneg(P.scal + kResidEx, mx[2]);
+    }
+  }
+  fft_forward(re, im, j, lds, twf);
+  if (in) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      T2<T> o;
+      o.x = re[m];
+      o.y = im[m];
+      F.spec[long(y) * F.nx + j + TL * m] = o;
+    }
+  }
+}
+
 // Clears scal slots (bit i of mask: slot kNnResid + i).  One thread.
 __global__ void k_nn_reset(double* scal, int mask) {
   if (threadIdx.x == 0)

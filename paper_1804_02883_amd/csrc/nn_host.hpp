@@ -159,8 +159,11 @@ hipError_t wgrad_reduce(const float* part, const float* partb, int nblocks, int 
 // network -> renormalised densities and the force source S.
 //   mode 0: surrogate step; mode 1: after the exact densities (see k_nn_norm)
 // ---------------------------------------------------------------------------
+// defer (may be NULL): when the force's row shape can take it, the
+// normalisation is not launched here but handed back (*defer filled, returns
+// with *deferred = true) for stage_force_lb to fuse with its first pass.
 template <typename T>
-int stage_nn(epdlb_ctx* c, int mode, int use_corr) {
+int stage_nn(epdlb_ctx* c, int mode, int use_corr, nn::NormArgs<T>* defer = nullptr, bool* deferred = nullptr) {
   const epdlb_params& p = c->p;
   const long n = long(p.nx) * p.ny;
   const NnOffsets o = nn_offsets();
@@ -253,6 +256,12 @@ int stage_nn(epdlb_ctx* c, int mode, int use_corr) {
   r.invDS = 1.0 / p.D_S;
   r.mode = mode;
   r.use_corr = use_corr;
+  if (deferred) *deferred = false;
+  if (defer && deferred && force_inv_lb_shape(c->sh_frow.R)) {
+    *defer = r;
+    *deferred = true;
+    return EPDLB_OK;
+  }
   {
     ProfScope ps(c, K_NN_NORM);
     launch_k(nn::k_nn_norm<T>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, c->stream, r);
@@ -267,10 +276,11 @@ int stage_nn_any(epdlb_ctx* c, int mode, int use_corr) {
 
 // One hybrid step in surrogate mode.  kind: 1/2 surrogate step (use_corr
 // 0/1), 3/4 exact step (use_corr 0/1).
-int run_sur_step(epdlb_ctx* c, int kind) {
+template <typename T>
+int run_sur_step_t(epdlb_ctx* c, int kind) {
   const bool exact = kind >= 3;
   const int uc = (kind == 2 || kind == 4) ? 1 : 0;
-  CHK(run_stage(c, EPDLB_STAGE_ADVECT_UPDATE));
+  CHK(stage_advect_update<T>(c));
   if (exact) {
     {
       ProfScope ps(c, K_NN_RESET);
@@ -279,12 +289,16 @@ int run_sur_step(epdlb_ctx* c, int kind) {
                (1 << (kResidEx - kNnResid)) | (1 << (kNnErrLast - kNnResid)));
     }
     HIPCHK(hipGetLastError());
-    CHK(c->p.precision == 0 ? stage_densities<double>(c, false) : stage_densities<float>(c, false));
+    CHK(stage_densities<T>(c, false));
   }
-  CHK(stage_nn_any(c, exact ? 1 : 0, uc));
-  CHK(run_stage(c, EPDLB_STAGE_FORCE));
-  CHK(run_stage(c, EPDLB_STAGE_LB));
-  return EPDLB_OK;
+  nn::NormArgs<T> norm{};
+  bool deferred = false;
+  CHK(stage_nn<T>(c, exact ? 1 : 0, uc, &norm, &deferred));
+  return stage_force_lb<T>(c, deferred ? &norm : nullptr);
+}
+
+int run_sur_step(epdlb_ctx* c, int kind) {
+  return c->p.precision == 0 ? run_sur_step_t<double>(c, kind) : run_sur_step_t<float>(c, kind);
 }
 
 // Residual test (host side, one check interval behind the device): the

@@ -10,13 +10,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_step_byte_model_totals():
-    """Per-family algorithmic bytes per site and step add up to (10N + 58)P."""
-    fams = ["advect_update", "prop_row", "prop_col", "density",
-            "force_row_fwd", "force_col", "force_row_inv", "lb"]
+    """Per-family algorithmic bytes per site and step add up to (10N + 56)P with
+    the fused row-inverse force + LB pass, (10N + 58)P with the two apart."""
+    fused = ["advect_update", "prop_row", "prop_col", "density", "force_row_fwd", "force_col", "force_inv_lb"]
+    apart = fused[:-1] + ["force_row_inv", "lb"]
     for N in (16, 32, 64):
         for P in (4, 8):
-            total = sum(bench.step_bytes_per_site(k, N, P) for k in fams)
-            assert total == (10 * N + 58) * P, (N, P)
+            assert sum(bench.step_bytes_per_site(k, N, P) for k in fused) == (10 * N + 56) * P, (N, P)
+            assert sum(bench.step_bytes_per_site(k, N, P) for k in apart) == (10 * N + 58) * P, (N, P)
     assert bench.step_bytes_per_site("lb", 32, 4) == 92
     assert bench.step_bytes_per_site("nn_conv", 32, 4) is None
 
