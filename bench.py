@@ -27,7 +27,9 @@ events at its own start and end in 100 steps that continue the run.
 `plain_full_scale` adds the plain path on 1024 x 512, N = 64 with the HBM
 roofline of its dominant kernel family; `fluid3d` and `densities3d` the
 three-dimensional D3Q19 fluid (256^3, FP32) and the three-dimensional
-propagators and densities (256^3, N = 32, FP32), each with its roofline.
+propagators and densities (256^3, N = 32, FP32), each with its roofline;
+`sync_costs` the launch and device-wide barrier costs the step's design
+rests on (a separate probe process).
 
 `cpu_baseline` is the FP64 NumPy oracle's plain step of the same workload on
 the host: one process (one thread), and one single-threaded process per
@@ -64,7 +66,15 @@ NN_FLOPS_PER_SITE = {"nn_conv0": 9 * 5 * 64 * 2, "nn_conv": 9 * 64 * 64 * 2}
 # WRITE x1.0); the summaries with their commands are under profiles/.  An
 # entry holds only while the sources its kernels are built from hash to
 # `source_sha256`; otherwise the bench reports null.
+_PROP_FILES = ("fft.hpp", "kernels.hpp")
+_NN_FILES = ("kernels.hpp", "nn.hpp")
 MEASURED_TRAFFIC = {
+    # profiles/prop_cfg3_traffic.md: the x-oriented propagator pass on 1024 x 512, N = 64
+    ("cfg3", "prop_row"): dict(bytes_per_launch=16160000, files=_PROP_FILES,
+                               source_sha256="29e4a4b66619c24df2efa7b80b6e068fe1cf47f3f2eaa8efc860711193ef7b2d"),
+    # profiles/nn_conv_cfg5q_traffic.md: mean over the two 64 -> 64 launches of a surrogate step
+    ("cfg5q", "nn_conv"): dict(bytes_per_launch=63890000, files=_NN_FILES,
+                               source_sha256="6f87d0222cbf233c2d8c5b860e20dab28b8e3c2b66e9e58be8fba526f0188600"),
     # profiles/lb3_fluid3d_256_traffic.md: the step kernel without moment stores
     ("fluid3d_256", "lb3"): dict(bytes_per_launch=2873793431, files=("lb3.hpp",),
                                  source_sha256="e7e59f031e128b313dda272b0a26b0ab5c5fe413ad9252a506d9b009c091450e"),
@@ -471,6 +481,19 @@ def densities3d_line(cpu=True):
     return r
 
 
+def sync_costs():
+    """Host and GPU cost of a dependent kernel launch (stream and graph node)
+    and of a device-wide barrier in a cooperative kernel, from the probe built
+    with the library (paper_1804_02883_amd/probes/sync_costs.hip)."""
+    exe = os.path.join(ROOT, "paper_1804_02883_amd", "probes", "sync_costs")
+    if not os.path.exists(exe):
+        return dict(note="probe not built")
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    if r.returncode != 0:
+        return dict(note="probe failed: " + r.stderr[-300:])
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def positive(v):
     i = int(v)
     if i < 1:
@@ -532,6 +555,9 @@ def main(argv=None):
         out["densities3d"] = densities3d_line(cpu=not args.no_cpu_baseline)
     out["gpu"] = gpu_info()
     out["gpu_wall_s"] = round(time.perf_counter() - t0, 1)
+    if not args.no_secondary:
+        say("sync costs probe")
+        out["sync_costs"] = sync_costs()
     if not args.no_cpu_baseline and args.workload != "cfg4":
         say(f"cpu baseline: the oracle on {args.workload}, {args.cpu_seconds:g} s per leg")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)

@@ -26,6 +26,24 @@ FLAGS = [
 ]
 
 
+PROBE_SRC = os.path.join(PKG, "probes", "sync_costs.hip")
+PROBE = os.path.join(PKG, "probes", "sync_costs")
+
+
+def build_probe(verbose=True):
+    """The synchronisation-cost probe (a stand-alone program; see its header)."""
+    cmd = [HIPCC, "-O3", "-std=c++17", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
+           "-packed-fp32-ops", PROBE_SRC, "-o", PROBE + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed building the sync-cost probe")
+    os.replace(PROBE + ".tmp", PROBE)
+    return PROBE
+
+
 def build(verbose=True):
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp"
@@ -42,6 +60,7 @@ def build(verbose=True):
     if verbose and noise:
         sys.stderr.write("\n".join(noise) + "\n")
     os.replace(tmp, LIB)
+    build_probe(verbose)
     return LIB
 
 
