@@ -14,7 +14,9 @@ Grid: nx x ny sites, arrays indexed [y, x]; site (x, y) is the cell centre
 ((x + 1/2) dx, (y + 1/2) dx); periodic in both directions.
 
 Every function here has a pin in tests/test_oracle_*.py except the ones named
-in PARITY_UNPINNED.
+in PARITY_UNPINNED (none): the chemical potential and the field update are
+pinned to the free energy of Sec. II and to closed-form single-mode updates,
+the advection to a hand-computed case (tests/test_oracle_epd_update.py).
 """
 import numpy as np
 

@@ -135,9 +135,15 @@ template <int L, int R> struct Plan {
   static constexpr int S = passes();              // number of radix passes
   static constexpr int R0 = L / ipow(R, S - 1);   // the one small radix
   static constexpr int T = L / R;                 // lanes per transform
-  static constexpr int LP = L + L / 64;           // padded LDS length per component
+  static constexpr int LP = L + L / 64;           // LDS length per transform (slack kept)
   static_assert(R0 >= 2 && R0 <= R && R0 * ipow(R, S - 1) == L, "plan");
-  __device__ static __forceinline__ int skew(int i) { return i + (i >> 6); }
+  // LDS position of element i: a permutation inside each aligned group of 16
+  // elements (128 bytes, one pass over the 32 banks), i xor (5 g mod 16) with
+  // g = i / 16.  The strided writes of the early passes (stride r elements
+  // across lanes) and the contiguous reads then fall into distinct 8-byte bank
+  // pairs within each 16-lane group, where an additive pad of one element per
+  // 64 left them 2- to 4-way conflicted.
+  __device__ static __forceinline__ int skew(int i) { return i ^ ((5 * (i >> 4)) & 15); }
 };
 
 // LDS view of one transform: complex element i (real and imaginary part

@@ -53,8 +53,15 @@ def test_plain_workloads(wl):
     assert out["config"]["path"] == "plain" and out["config"]["workload"].startswith(wl)
     assert out["steps"] == 20 and out["value"] > 0 and out["roofline"]["bound"] == "hbm"
     assert out["ms_per_step"] * 20 / 1e3 < wall
-    if wl != "cfg4":  # (the groups of a batch run as concurrent graph branches)
+    # the profiled launches are stream launches, each timed from its own start
+    # to its end; at 1024 x 512 the kernels dominate and their sum fits in the
+    # graph-replayed step, while on smaller grids each short kernel's timed
+    # extent carries its launch's event work (cfg2: 250 us of kernels against
+    # a 231 us step); the groups of a batch run as concurrent graph branches
+    if wl == "cfg3":
         assert out["roofline"]["kernel_sum_us_per_step"] <= 1.05 * 1e3 * out["ms_per_step"]
+    elif wl != "cfg4":
+        assert out["roofline"]["kernel_sum_us_per_step"] <= 1.3 * 1e3 * out["ms_per_step"]
 
 
 def test_surrogate_line_without_secondaries():
