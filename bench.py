@@ -29,7 +29,8 @@ roofline of its dominant kernel family; `fluid3d` and `densities3d` the
 three-dimensional D3Q19 fluid (256^3, FP32) and the three-dimensional
 propagators and densities (256^3, N = 32, FP32), each with its roofline;
 `sync_costs` the launch and device-wide barrier costs the step's design
-rests on (a separate probe process).
+rests on, and `conv_floor` the matrix-work, store and combined ceilings of
+one 64 -> 64 layer at 512^2 (separate probe processes).
 
 `cpu_baseline` is the FP64 NumPy oracle's plain step of the same workload on
 the host: one process (one thread), and one single-threaded process per
@@ -69,9 +70,11 @@ NN_FLOPS_PER_SITE = {"nn_conv0": 9 * 5 * 64 * 2, "nn_conv": 9 * 64 * 64 * 2}
 _PROP_FILES = ("fft.hpp", "kernels.hpp")
 _NN_FILES = ("kernels.hpp", "nn.hpp")
 MEASURED_TRAFFIC = {
-    # profiles/prop_cfg3_traffic.md: the x-oriented propagator pass on 1024 x 512, N = 64
-    ("cfg3", "prop_row"): dict(bytes_per_launch=16160000, files=_PROP_FILES,
-                               source_sha256="29e4a4b66619c24df2efa7b80b6e068fe1cf47f3f2eaa8efc860711193ef7b2d"),
+    # profiles/prop_cfg3_traffic.md: the tuned propagator passes on 1024 x 512, N = 64
+    ("cfg3", "prop_row"): dict(bytes_per_launch=16168831, files=_PROP_FILES,
+                               source_sha256="c0417f77c5afb5ce03280c737880ab070e54022184eedd7e541aad78955a39ff"),
+    ("cfg3", "prop_col"): dict(bytes_per_launch=17296688, files=_PROP_FILES,
+                               source_sha256="c0417f77c5afb5ce03280c737880ab070e54022184eedd7e541aad78955a39ff"),
     # profiles/nn_conv_cfg5q_traffic.md: mean over the two 64 -> 64 launches of a surrogate step
     ("cfg5q", "nn_conv"): dict(bytes_per_launch=63890000, files=_NN_FILES,
                                source_sha256="6f87d0222cbf233c2d8c5b860e20dab28b8e3c2b66e9e58be8fba526f0188600"),
@@ -481,11 +484,14 @@ def densities3d_line(cpu=True):
     return r
 
 
-def sync_costs():
-    """Host and GPU cost of a dependent kernel launch (stream and graph node)
-    and of a device-wide barrier in a cooperative kernel, from the probe built
-    with the library (paper_1804_02883_amd/probes/sync_costs.hip)."""
-    exe = os.path.join(ROOT, "paper_1804_02883_amd", "probes", "sync_costs")
+def run_probe(name):
+    """Run a stand-alone probe built with the library (paper_1804_02883_amd/probes/<name>.hip)
+    and return its JSON line:
+      sync_costs  host and GPU cost of a dependent kernel launch (stream and graph
+                  node) and of a device-wide barrier in a cooperative kernel;
+      conv_floor  the matrix work, the activation stores and both together of one
+                  64 -> 64 layer at 512^2, launched as the layer kernel is."""
+    exe = os.path.join(ROOT, "paper_1804_02883_amd", "probes", name)
     if not os.path.exists(exe):
         return dict(note="probe not built")
     r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
@@ -557,7 +563,9 @@ def main(argv=None):
     out["gpu_wall_s"] = round(time.perf_counter() - t0, 1)
     if not args.no_secondary:
         say("sync costs probe")
-        out["sync_costs"] = sync_costs()
+        out["sync_costs"] = run_probe("sync_costs")
+        say("convolution floor probe")
+        out["conv_floor"] = run_probe("conv_floor")
     if not args.no_cpu_baseline and args.workload != "cfg4":
         say(f"cpu baseline: the oracle on {args.workload}, {args.cpu_seconds:g} s per leg")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)

@@ -26,22 +26,22 @@ FLAGS = [
 ]
 
 
-PROBE_SRC = os.path.join(PKG, "probes", "sync_costs.hip")
-PROBE = os.path.join(PKG, "probes", "sync_costs")
+PROBES = ("sync_costs", "conv_floor")  # stand-alone programs under probes/ (see their headers)
 
 
-def build_probe(verbose=True):
-    """The synchronisation-cost probe (a stand-alone program; see its header)."""
+def build_probe(name, verbose=True):
+    src = os.path.join(PKG, "probes", name + ".hip")
+    exe = os.path.join(PKG, "probes", name)
     cmd = [HIPCC, "-O3", "-std=c++17", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
-           "-packed-fp32-ops", PROBE_SRC, "-o", PROBE + ".tmp"]
+           "-packed-fp32-ops", src, "-o", exe + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building the sync-cost probe")
-    os.replace(PROBE + ".tmp", PROBE)
-    return PROBE
+        raise RuntimeError("hipcc failed building the probe " + name)
+    os.replace(exe + ".tmp", exe)
+    return exe
 
 
 def build(verbose=True):
@@ -60,7 +60,8 @@ def build(verbose=True):
     if verbose and noise:
         sys.stderr.write("\n".join(noise) + "\n")
     os.replace(tmp, LIB)
-    build_probe(verbose)
+    for name in PROBES:
+        build_probe(name, verbose)
     return LIB
 
 

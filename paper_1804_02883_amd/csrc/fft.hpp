@@ -144,12 +144,22 @@ template <int L, int R> struct Plan {
   // pairs within each 16-lane group, where an additive pad of one element per
   // 64 left them 2- to 4-way conflicted.
   __device__ static __forceinline__ int skew(int i) { return i ^ ((5 * (i >> 4)) & 15); }
+  // Interleaved views (NF transforms side by side, NF = 4 or 8): a lane's
+  // bank pair is f + NF * (position mod 16/NF), so only the low bits of the
+  // position matter, and within a group of 16 lanes the same-f lanes hold
+  // consecutive butterflies.  Their reads are consecutive positions, their
+  // writes r apart for r = 4 or 8 (pairs 2r apart in a pass after a radix-2
+  // one).  Xoring bits 2 and 3 into bits 0 and 1 keeps four consecutive
+  // positions distinct mod 4 and makes four positions at those strides
+  // distinct mod 4 as well, where the group xor above left them 2-way
+  // conflicted.
+  __device__ static __forceinline__ int skew_il(int i) { return i ^ (((i >> 2) ^ (i >> 3)) & 3); }
 };
 
 // LDS view of one transform: complex element i (real and imaginary part
 // side by side, one 64-/128-bit access each).
 //  * CONTIG:      transform f occupies [f*LP, (f+1)*LP)
-//  * interleaved: transforms are the fastest index (f + NF*skew(i)), so that
+//  * interleaved: transforms are the fastest index (f + NF*skew_il(i)), so that
 //                 lanes of one wavefront holding different transforms hit
 //                 consecutive banks
 template <typename T, int L, int R, bool CONTIG, int NF>
@@ -158,7 +168,7 @@ struct LdsView {
   int f;
   __device__ __forceinline__ int at(int i) const {
     if constexpr (CONTIG) return f * Plan<L, R>::LP + Plan<L, R>::skew(i);
-    else return f + NF * Plan<L, R>::skew(i);
+    else return f + NF * Plan<L, R>::skew_il(i);
   }
   // complex elements needed for nf transforms
   __host__ __device__ static constexpr int size_elems(int nf) {

@@ -44,6 +44,10 @@ def test_driver_command():
     # the plain path's kernels, each timed at its own start and end, fit in its step
     assert out["plain"]["kernel_sum_us_per_step"] <= 1.02 * 1e3 * out["plain"]["ms_per_step"]
     assert out["density_err"]["in_use"] <= 1e-3
+    # the probes ran: the layer's ceilings order as matrix work <= work + stores
+    cf = out["conv_floor"]
+    assert 0 < cf["mfma"]["us"] <= cf["mfma_store"]["us"] and cf["store"]["us"] > 0, cf
+    assert out["sync_costs"]["graph_node_gpu_us"] > 0
 
 
 @pytest.mark.parametrize("wl", ["cfg2", "cfg3", "cfg5", "cfg4"])
