@@ -71,13 +71,13 @@ _PROP_FILES = ("fft.hpp", "kernels.hpp")
 _NN_FILES = ("kernels.hpp", "nn.hpp")
 MEASURED_TRAFFIC = {
     # profiles/prop_cfg3_traffic.md: the tuned propagator passes on 1024 x 512, N = 64
-    ("cfg3", "prop_row"): dict(bytes_per_launch=16168831, files=_PROP_FILES,
-                               source_sha256="c0417f77c5afb5ce03280c737880ab070e54022184eedd7e541aad78955a39ff"),
-    ("cfg3", "prop_col"): dict(bytes_per_launch=17296688, files=_PROP_FILES,
-                               source_sha256="c0417f77c5afb5ce03280c737880ab070e54022184eedd7e541aad78955a39ff"),
+    ("cfg3", "prop_row"): dict(bytes_per_launch=16168805, files=_PROP_FILES,
+                               source_sha256="877088b805e92cfbe6994e99c9fc2c678ef2c3253a7fbadb1721b17fee5559c1"),
+    ("cfg3", "prop_col"): dict(bytes_per_launch=17296672, files=_PROP_FILES,
+                               source_sha256="877088b805e92cfbe6994e99c9fc2c678ef2c3253a7fbadb1721b17fee5559c1"),
     # profiles/nn_conv_cfg5q_traffic.md: mean over the two 64 -> 64 launches of a surrogate step
-    ("cfg5q", "nn_conv"): dict(bytes_per_launch=63890000, files=_NN_FILES,
-                               source_sha256="6f87d0222cbf233c2d8c5b860e20dab28b8e3c2b66e9e58be8fba526f0188600"),
+    ("cfg5q", "nn_conv"): dict(bytes_per_launch=63871133, files=_NN_FILES,
+                               source_sha256="d085c160fd00ceae2554be7dfed9b4249a4a78738a1216f4bc593522dcf7a606"),
     # profiles/lb3_fluid3d_256_traffic.md: the step kernel without moment stores
     ("fluid3d_256", "lb3"): dict(bytes_per_launch=2873793431, files=("lb3.hpp",),
                                  source_sha256="e7e59f031e128b313dda272b0a26b0ab5c5fe413ad9252a506d9b009c091450e"),

@@ -641,9 +641,22 @@ __global__ void __launch_bounds__(256) k_advect_update(UpdArgs<T> P) {
   const int tid = threadIdx.x;
   load_advect_tile(P, tx0, ty0, sIn);
   __syncthreads();
-  // advected fields and mu~ on the halo-1 region
-  for (int e = tid; e < kMX * kMY; e += blockDim.x) {
-    const int mx = e % kMX, my = e / kMX;
+  // advected fields and mu~ on the halo-1 region, 34 x 10 sites: the first
+  // pass gives each 32-lane half of a wave one row of 32 sites, so that every
+  // LDS access of the stencil is 32 consecutive words of one row (no bank
+  // conflicts); the second covers rows 8-9 and then columns 32-33
+  static_assert(kTX == 32 && kTY == 8 && kMX == 34 && kMY == 10, "halo-1 pass mapping");
+  for (int pass = 0; pass < 2; ++pass) {
+    int mx, my;
+    if (pass == 0) {
+      mx = tid & 31, my = tid >> 5;
+    } else if (tid < 64) {
+      mx = tid & 31, my = 8 + (tid >> 5);
+    } else if (tid < 84) {
+      mx = 32 + ((tid - 64) & 1), my = (tid - 64) >> 1;
+    } else {
+      break;
+    }
     T pt[3], wt[3];
     advect_site(sIn, mx + 1, my + 1, pt, wt);  // position in sIn
     const T tot = pt[0] + pt[1] + pt[2];
