@@ -1100,9 +1100,22 @@ hipError_t launch_family(epdlb_ctx* c, int fam, int R, int nf, hipStream_t s) {
   ForceArgs<T> a = make_force_args<T>(c);
   a.nf = nf;
   if (fam == F_FORCE_ROW) {
+    // the row passes of the force together with the LB step, as the step runs
+    // them: fused with the row inverse where the shape allows, else after it
+    // (the LB part writes u, rho, the guard words and the other population
+    // buffer: epdlb_autotune keeps the first three)
     hipError_t e = force_row_fwd<T>(p.nx, R, a, s);
     if (e != hipSuccess) return e;
-    return force_row_inv<T>(p.nx, R, a, s);
+    const LbArgs<T> b = make_lb_args<T>(c);
+    if (force_inv_lb_shape(R)) return force_inv_lb<T>(p.nx, R, a, b, p.lb_mrt != 0, s);
+    e = force_row_inv<T>(p.nx, R, a, s);
+    if (e != hipSuccess) return e;
+    const long n = long(p.nx) * p.ny;
+    if (p.lb_mrt)
+      launch_k((k_lb<T, true>), dim3((n + 255) / 256, 1, c->nrep), dim3(256), 0, s, b);
+    else
+      launch_k((k_lb<T, false>), dim3((n + 255) / 256, 1, c->nrep), dim3(256), 0, s, b);
+    return hipGetLastError();
   }
   return force_col<T>(p.ny, R, a, s);
 }
@@ -2295,6 +2308,32 @@ int epdlb_autotune(epdlb_ctx* c, int32_t reps, const char* cache_path) {
     }
   }
   const bool fp32 = c->p.precision == 1;
+  // the force-row candidates run the LB step: keep u, rho and the guard words
+  // of every replica and put them back afterwards
+  const size_t plane = size_t(c->p.nx) * c->p.ny * elem(c);
+  const size_t keep_bytes = 3 * plane + 16 * sizeof(unsigned);
+  unsigned char* keep = nullptr;
+  HIPCHK(hipMalloc(&keep, keep_bytes * size_t(c->nrep)));
+  auto copy_state = [&](bool save) -> int {
+    for (int r = 0; r < c->nrep; ++r) {
+      unsigned char* k = keep + keep_bytes * size_t(r);
+      unsigned char* o = c->base + c->roff(r);
+      const std::pair<size_t, size_t> parts[3] = {{c->L.u, 2 * plane}, {c->L.rho, plane},
+                                                  {c->L.counters, 16 * sizeof(unsigned)}};
+      size_t at = 0;
+      for (const auto& pt : parts) {
+        HIPCHK(hipMemcpyAsync(save ? k + at : o + pt.first, save ? o + pt.first : k + at, pt.second,
+                              hipMemcpyDeviceToDevice, c->stream));
+        at += pt.second;
+      }
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return EPDLB_OK;
+  };
+  if (int e = copy_state(true)) {
+    (void)hipFree(keep);
+    return e;
+  }
   const char* verbose_env = std::getenv("EPDLB_TUNE_VERBOSE");
   const bool verbose = verbose_env && std::atoi(verbose_env) != 0;
   for (int fam = 0; fam < F_NUM; ++fam) {
@@ -2345,7 +2384,9 @@ int epdlb_autotune(epdlb_ctx* c, int32_t reps, const char* cache_path) {
   }
   drop_graphs(c);
   HIPCHK(hipStreamSynchronize(c->stream));
-  return EPDLB_OK;
+  const int e = copy_state(false);
+  HIPCHK(hipFree(keep));
+  return e;
 }
 
 int epdlb_get_shapes(epdlb_ctx* c, epdlb_shape* out, int32_t cap, int32_t* n_out) {
