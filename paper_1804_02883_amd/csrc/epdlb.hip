@@ -2383,9 +2383,10 @@ int epdlb_autotune(epdlb_ctx* c, int32_t reps, const char* cache_path) {
     }
   }
   drop_graphs(c);
-  HIPCHK(hipStreamSynchronize(c->stream));
-  const int e = copy_state(false);
-  HIPCHK(hipFree(keep));
+  const hipError_t se = hipStreamSynchronize(c->stream);
+  const int e = se == hipSuccess ? copy_state(false)
+                                 : fail(EPDLB_EHIP, std::string("autotune: ") + hipGetErrorString(se));
+  (void)hipFree(keep);
   return e;
 }
 
